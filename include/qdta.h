@@ -1,0 +1,235 @@
+/*
+ * qdta.h -- C ABI of the MI355X (gfx950) hot path of quasi-dynamic traffic
+ * assignment (QDTA), after Chan et al., "Quasi-Dynamic Traffic Assignment
+ * using High Performance Computing" (arXiv 2104.12911).
+ *
+ * One Frank-Wolfe (FW) iteration of the paper's link-flow form (Alg. 6) is:
+ *   BPR link costs (Eq. 1) -> all-or-nothing assignment (Alg. 3 / Alg. 7:
+ *   shortest paths to every destination, route truncation by Eq. 2, loading
+ *   by the truncated incidence of Eq. 5) -> convergence test (Eq. 7, or the
+ *   relative gap) -> line search on the Beckmann objective (Eq. 6, Eq. 8-10,
+ *   Alg. 8-9) -> link-flow update.  After an interval, residual demand is
+ *   carried to the next one (Alg. 4, Alg. 1).
+ *
+ * Conventions (all entry points):
+ *   - Return value: QDTA_OK (0) on success, a negative QDTA_E* code on error
+ *     (the context's last-error text says why), a positive QDTA_W* code for a
+ *     warning.  No exception crosses the ABI.  A call that fails leaves the
+ *     context usable unless it returns QDTA_EHIP.
+ *   - Pointers named host_* or documented as host are ordinary host memory.
+ *     All other arrays are device pointers on the context's device (e.g.
+ *     torch tensors' data_ptr()), owned by the caller, which must keep them
+ *     alive until the context's stream has executed the call.
+ *   - Calls that take device pointers enqueue work on the context's stream
+ *     and return without synchronising, unless documented otherwise.
+ *   - Flows are int64 fixed point in units of 2^-20 vehicle ("fx");
+ *     trips are converted with round-half-even(trips * 2^20).
+ *   - Times are seconds.  Capacities are vehicles per hour.  Within an
+ *     interval of dt seconds, a link's flow F (vehicles) enters the BPR curve
+ *     as the hourly rate kappa*F, kappa = 3600/dt; dt = +inf means plain
+ *     static assignment (kappa = 1, demand read as veh/h, no truncation).
+ *   - A context holds one or more network instances ("batched" solve: every
+ *     instance advances one FW iteration per launch sequence).  Node ids and
+ *     link ids passed in and out are local to an instance; device arrays over
+ *     "all links" are the instances' links concatenated in instance order
+ *     (qdta_layout() gives the offsets).
+ *   - A link's id ("uid") is its position in the caller's CSR.  Shortest-path
+ *     ties are broken towards the lowest uid.
+ *   - Contexts are not thread-safe; use one per host thread.
+ */
+#ifndef QDTA_H
+#define QDTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QDTA_OK 0
+#define QDTA_EARG (-1)      /* bad argument (null pointer, size, option range) */
+#define QDTA_ECSR (-2)      /* malformed CSR (row_ptr not monotone, col out of range) */
+#define QDTA_EVAL (-3)      /* free-flow time or capacity <= 0 or not finite */
+#define QDTA_EUNREACH (-4)  /* a leg's destination is unreachable from its origin */
+#define QDTA_EOVF (-5)      /* fixed-point, cost or exact-sum overflow */
+#define QDTA_ENOMEM (-6)    /* device allocation failed */
+#define QDTA_EHIP (-7)      /* HIP runtime error (text in last error) */
+#define QDTA_ESTATE (-8)    /* call out of order (e.g. solve before demand) */
+#define QDTA_WABSORB 1      /* FP32 absorption: the tie-rule fallback was used */
+
+#define QDTA_RULE_NONE 0    /* no truncation: walk to the destination */
+#define QDTA_RULE_CEIL 1    /* load a link entered before dt; stop at the first node reached at or after dt */
+#define QDTA_RULE_FLOOR 2   /* load a link only if it is left by dt */
+
+#define QDTA_LS_KSECTION 0  /* K step sizes per pass, bracket the root of C'(alpha) */
+#define QDTA_LS_QN 1        /* quasi-Newton search of Alg. 8 with the stencil of Eq. 10 */
+#define QDTA_LS_MSA 2       /* alpha_j = 1/(j+1) */
+
+#define QDTA_STOP_GAP 0     /* relative gap (sum c f - sum c y) / sum c f below tol */
+#define QDTA_STOP_OBJ 1     /* relative change of the Beckmann objective below tol (Eq. 7) */
+
+typedef struct qdta_ctx qdta_ctx;
+
+/* Solver options.  qdta_default_opts() fills the paper's values:
+ * BPR alpha 0.15, beta 4; CEIL truncation; K-section with K = 32, 3 passes;
+ * T1 = T2 = dx = 1e-4 (Alg. 8, Eq. 10); relative-gap stop at 1e-4. */
+typedef struct {
+    double alpha;          /* BPR alpha (Eq. 1), >= 0 */
+    int32_t beta;          /* BPR beta (Eq. 1), integer 1..16 */
+    int32_t trunc_rule;    /* QDTA_RULE_* (ignored for dt = +inf) */
+    int32_t ls_mode;       /* QDTA_LS_* */
+    int32_t K;             /* K-section points per pass, 3..64 */
+    int32_t passes;        /* K-section passes, 1..8 */
+    int32_t max_ls;        /* quasi-Newton iteration cap L, 1..100 */
+    double T1, T2, dx;     /* Alg. 8 thresholds (slope, step) and Eq. 10 stencil */
+    int32_t stop_rule;     /* QDTA_STOP_* */
+    double tol;            /* tolerance of the stop rule */
+    int32_t max_iter;      /* FW iteration cap */
+    int32_t fixed_iters;   /* > 0: exactly this many updates, stop rule ignored */
+    int32_t keep_history;  /* record (alpha_j, c_j) per iteration; needed by qdta_advance_interval */
+    int32_t sources_per_block; /* destinations per shortest-path batch: 0 auto, else 4, 8, 16 or 32 */
+    int32_t reserved[6];
+} qdta_opts;
+
+/* Per-instance results of qdta_solve. */
+typedef struct {
+    int32_t iters;         /* FW updates applied */
+    int32_t ls_evals;      /* line-search passes over the links */
+    int32_t qn_iters;      /* quasi-Newton iterations (QDTA_LS_QN) */
+    int32_t absorb;        /* 1 when the FP32-absorption tie fallback was used */
+    int32_t stopped_by;    /* 0 iteration cap / fixed count, 1 gap, 2 objective change */
+    int32_t status;        /* QDTA_OK or an error code for this instance */
+    double gap;            /* relative gap at the returned iterate */
+    double objective;      /* Beckmann objective at the returned iterate (veh s) */
+    double last_alpha;     /* last step size applied */
+} qdta_stats;
+
+/* Layout of the concatenated arrays (host output of qdta_layout). */
+typedef struct {
+    int32_t n_instances;
+    int64_t total_nodes, total_links, total_legs, total_dests;
+} qdta_layout_info;
+
+void qdta_default_opts(qdta_opts *opts);
+const char *qdta_strerror(int code);
+/* Text of the last error on this context (never NULL; "" when none). */
+const char *qdta_last_error(const qdta_ctx *ctx);
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the default stream).  *out receives the context. */
+int qdta_create(qdta_ctx **out, int device, void *stream);
+/* Free the context and its device memory.  Synchronises its stream. */
+int qdta_destroy(qdta_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+int qdta_set_stream(qdta_ctx *ctx, void *stream);
+
+/* Add a network instance (section 3.1 notation: graph G(V,A), capacity C_a,
+ * free-flow time c_0,a).  Host arrays: row_ptr int32[n+1] (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[n] = m), col int32[m] (head node of each link,
+ * 0 <= col < n), fftt float[m] (> 0, finite, s), cap float[m] (> 0, finite,
+ * veh/h).  Copied; the caller may free them on return.  *inst_out receives
+ * the instance index (0, 1, ...).  Errors: QDTA_EARG, QDTA_ECSR, QDTA_EVAL. */
+int qdta_add_network(qdta_ctx *ctx, int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
+                     const float *fftt, const float *cap, int32_t *inst_out);
+
+/* Set the original demand d^o(i) of instance `inst` for the next interval
+ * (Alg. 1): host arrays orig, dest int32[P] (local node ids), trips
+ * double[P] (>= 0, vehicles departing in the interval).  Legs with
+ * orig == dest or zero trips are dropped (Alg. 3 visits non-zero entries).
+ * Residual demand d^r(i) left by qdta_advance_interval is merged in
+ * (d(i) = d^o(i) + d^r(i)); legs with equal (orig, dest) are summed.
+ * dt_s: interval length in s, or +inf for plain static assignment.
+ * Errors: QDTA_EARG (ids out of range, negative or non-finite trips),
+ * QDTA_EOVF (trips beyond the fixed-point range). */
+int qdta_set_demand(qdta_ctx *ctx, int32_t inst, int32_t P, const int32_t *orig, const int32_t *dest,
+                    const double *trips, double dt_s);
+
+/* Sizes of the concatenated device arrays (host output). */
+int qdta_layout(qdta_ctx *ctx, qdta_layout_info *info);
+/* Host outputs: per-instance first node / first link / first leg / first
+ * destination in the concatenated order (each int64[n_instances+1]). */
+int qdta_offsets(qdta_ctx *ctx, int64_t *node_off, int64_t *link_off, int64_t *leg_off, int64_t *dest_off);
+
+/* A1 -- link costs by Eq. 1 over all links: cost[a] = fl32(c0 (1 + alpha
+ * (kappa F / C)^beta)), F = f_fx[a] * 2^-20, evaluated in FP64 without fused
+ * multiply-add, the power by repeated multiplication.  f_fx int64[total_links],
+ * cost float[total_links] (device).  Uses opts->alpha, opts->beta and each
+ * instance's dt.  Returns QDTA_EOVF (after the stream completes: this call
+ * synchronises) if a cost is not finite. */
+int qdta_bpr(qdta_ctx *ctx, const qdta_opts *opts, const int64_t *f_fx, float *cost);
+
+/* A2 -- shortest-path trees (Get_shortest_path of Alg. 3) on one instance:
+ * for each of the nq destinations (device int32[nq], local ids), the FP32
+ * min-plus time to it from every node, dist float[nq][n] (+inf when
+ * unreachable), and the successor link on the tree, succ int32[nq][n]
+ * (local uid; -1 at the destination and where unreachable).  The successor is
+ * the lowest-uid out-link (v,w) with fl32(dist[w] + cost) == dist[v] and
+ * dist[w] < dist[v]; where FP32 absorption leaves none, the lowest-uid tight
+ * link to a node one hop closer to the destination in the tight subgraph
+ * (then QDTA_WABSORB is returned; this call synchronises).  cost is the
+ * instance's float[m] (device). */
+int qdta_trees(qdta_ctx *ctx, const qdta_opts *opts, int32_t inst, const float *cost, int32_t nq,
+               const int32_t *dest, float *dist, int32_t *succ);
+
+/* A2 + A3 -- all-or-nothing assignment of the current demand (Alg. 3 /
+ * Alg. 7) under cost float[total_links]: y_fx int64[total_links] (device,
+ * overwritten) receives the truncated loading; stop int32[total_legs] (device,
+ * may be NULL) the stop node of each leg in qdta_get_legs() order (its
+ * destination when the leg completes).  Synchronises; returns
+ * QDTA_EUNREACH, QDTA_WABSORB or QDTA_OK. */
+int qdta_aon(qdta_ctx *ctx, const qdta_opts *opts, const float *cost, int64_t *y_fx, int32_t *stop);
+
+/* The current legs of all instances, in the order qdta_aon reports them:
+ * grouped by instance, then by destination.  Host outputs of
+ * int32/int32/int64[total_legs], local node ids; any may be NULL. */
+int qdta_get_legs(qdta_ctx *ctx, int32_t *host_orig, int32_t *host_dest, int64_t *host_d_fx);
+
+/* A5 -- exact line-search sums (Alg. 9 batched over K step sizes): for every
+ * instance i and k < K, C_i(alpha) = sum_a Q(obj_a) and C'_i(alpha) =
+ * sum_a Q(der_a) at alpha = alphas[i*K + k] (device double), where on
+ * v = F + alpha (Y - F): obj = c0 (v + alpha_b v p / (beta+1)),
+ * p = (kappa v / C)^beta, der = (Y - F) c0 (1 + alpha_b p), and
+ * Q(x) = round-half-even(x * 2^16) summed exactly as int128.
+ * sums: device int64[n_instances][K][2][2] = (C, C') x (low, high limb). */
+int qdta_ls_eval(qdta_ctx *ctx, const qdta_opts *opts, const int64_t *f_fx, const int64_t *y_fx,
+                 int32_t K, const double *alphas, int64_t *sums);
+
+/* A5 -- the step size of FW iteration j for every instance by opts->ls_mode
+ * (K-section, quasi-Newton of Alg. 8, or MSA), alpha_out double[n_instances]
+ * (device).  Synchronises. */
+int qdta_line_search(qdta_ctx *ctx, const qdta_opts *opts, const int64_t *f_fx, const int64_t *y_fx,
+                     int32_t j, double *alpha_out);
+
+/* A6 -- link-flow update f <- f + rint(alpha_i (y - f)) with alpha of each
+ * link's instance (device double[n_instances]). */
+int qdta_fw_update(qdta_ctx *ctx, int64_t *f_fx, const int64_t *y_fx, const double *alpha);
+
+/* A1-A7 -- Frank-Wolfe on the current demand of every instance (Alg. 6):
+ * initial AON at free flow, then BPR, AON, stop test, line search, update,
+ * until each instance's stop rule fires (its pre-update iterate is returned)
+ * or the cap is reached.  host_stats: qdta_stats[n_instances] (host).
+ * Synchronises once per FW iteration.  Returns the worst per-instance code. */
+int qdta_solve(qdta_ctx *ctx, const qdta_opts *opts, qdta_stats *host_stats);
+
+/* Copies of the solved link flows (int64 fx) and costs BPR(f) (float) over
+ * all links, device outputs; either may be NULL. */
+int qdta_get_flows(qdta_ctx *ctx, int64_t *f_fx);
+int qdta_get_costs(qdta_ctx *ctx, const qdta_opts *opts, float *cost);
+
+/* A8 -- residual demand after the solved interval (Alg. 4): every iterate's
+ * paths (weights lambda_j = alpha_j prod_{k>j}(1 - alpha_k), alpha_0 = 1) are
+ * re-truncated under the final costs BPR(f); a leg stopping at s != q leaves
+ * rint(lambda_j d) as demand (s, q), merged into the next qdta_set_demand.
+ * Needs opts->keep_history during qdta_solve.  Synchronises. */
+int qdta_advance_interval(qdta_ctx *ctx, const qdta_opts *opts);
+
+/* The pending residual demand of instance inst (host outputs).  Call with
+ * NULL arrays to get *count; arrays then hold at least *count entries. */
+int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host_orig,
+                      int32_t *host_dest, int64_t *host_w_fx, int64_t *host_done_fx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QDTA_H */

@@ -1,0 +1,156 @@
+// Private declarations shared by the library's kernels (qdta_kernels.hip)
+// and its host runtime (qdta_runtime.cpp).  Not installed, not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qdta {
+
+constexpr int kWG = 256;                 // threads per workgroup (4 wavefronts of 64)
+constexpr int kChunk = 2048;             // links per workgroup in link-parallel kernels
+constexpr uint32_t kInfBits = 0x7f800000u;
+constexpr int kMaxK = 64;                // step sizes per line-search pass
+
+// Static description of one instance inside the concatenated layout.
+struct InstDev {
+    int32_t node0, n;        // first global node, node count
+    int32_t link0, m;        // first global link, link count
+    int32_t q0, nq;          // first global destination index, count
+    int32_t leg0, nleg;      // first global leg, count
+    int32_t rule;            // effective truncation rule (NONE when dt = inf)
+    float dt32;              // interval length rounded to FP32
+    double kappa;            // 3600/dt, or 1 for dt = inf
+};
+
+// Per-instance Frank-Wolfe / line-search state, resident on the device.
+struct InstState {
+    int32_t active;          // instance has legs in this solve
+    int32_t converged;       // stop rule fired or cap reached: f is final
+    int32_t ls_done;         // line search finished for this iteration
+    int32_t iter;            // FW iteration j being computed (1-based)
+    int32_t stopped_by;      // 0 cap/fixed, 1 gap, 2 objective change
+    int32_t ls_evals;        // passes over the links (accumulated)
+    int32_t qn_iters;        // quasi-Newton iterations (accumulated)
+    int32_t iters;           // updates applied
+    int32_t ls_pass;         // passes in the current line search
+    int32_t pad0;
+    double gap;              // relative gap of the last test
+    double alpha;            // step size chosen for this iteration
+    double last_alpha;       // last applied step size
+    double lo, hi;           // K-section bracket
+    long long dlo[2], dhi[2];// C' at lo and hi (int128 limbs: low, high)
+    double qn_alpha;         // quasi-Newton iterate
+    double obj;              // objective (veh s) of the returned iterate
+};
+
+// Kernel arguments ---------------------------------------------------------
+
+struct NetDev {
+    const int32_t* row_ptr;  // [N+1] global forward CSR
+    const int32_t* col;      // [M]   head (global node)
+    const float* c0;         // [M]
+    const float* cap;        // [M]
+    const int32_t* rptr;     // [N+1] reverse CSR
+    const int32_t* rsrc;     // [M]   tail (global node) of each in-link
+    const int32_t* rlink;    // [M]   global link id of each in-link
+    const int32_t* revpos;   // [M]   position of link a in the reverse arrays
+    const InstDev* inst;     // [ninst]
+    const int32_t* blk_inst; // [nblk] instance of each link chunk
+    const int32_t* blk_start;// [nblk] first global link of each chunk
+    int32_t ninst, nblk;
+    int64_t N, M;
+};
+
+struct DemDev {
+    const int32_t* dest_node;// [Q] global node of each destination
+    const int32_t* dest_inst;// [Q]
+    const int64_t* dest_lab; // [Q] offset (floats) of slot 0 node 0 of its tree in the label array
+    const int32_t* qptr;     // [Q+1] legs of each destination (global leg index)
+    const int32_t* leg_orig; // [P] global origin node
+    const int64_t* leg_dfx;  // [P]
+    const int32_t* leg_q;    // [P] global destination index
+    const int32_t* b_inst;   // [B] batches: instance
+    const int32_t* b_q;      // [B] first destination
+    const int32_t* b_nq;     // [B] destinations in the batch (<= sources per block)
+    const int64_t* b_lab;    // [B] label-array offset of the batch
+    int32_t Q, P, B, sb;
+};
+
+struct Scratch {
+    int32_t* queues;         // [slots][2][nmax]
+    uint32_t* dirty;         // [slots][nmax]
+    int32_t* stamp;          // [slots][nmax] last round a node was queued for
+    int32_t nmax;
+    int32_t* work;           // batch work counter
+};
+
+struct FlagsDev {
+    int* err_overflow;       // set on non-finite cost / exact-sum overflow
+    int* err_unreach;        // set when a leg's origin cannot reach its destination
+    int* absorb_count;       // legs interrupted by FP32 absorption
+    int32_t* absorb_q;       // [Q] destination flagged for the tie fallback
+    int32_t* int_node;       // [P] node where an interrupted leg stopped (-1 none)
+    float* int_tau;          // [P] its elapsed time there
+};
+
+// Launchers (qdta_kernels.hip) ---------------------------------------------
+
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t count);
+hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t count);
+
+hipError_t launch_bpr(hipStream_t s, const NetDev& net, const int64_t* f, double alpha, int beta,
+                      float* cost, float* rcost, const InstState* st, int only_active, int* err);
+
+hipError_t launch_gap_sums(hipStream_t s, const NetDev& net, const float* cost, const int64_t* f,
+                           const int64_t* y, long long* acc /*[ninst][2][3]*/, const InstState* st, int* err);
+
+hipError_t launch_gap_decide(hipStream_t s, int ninst, const long long* acc, InstState* st, int stop_rule,
+                             double tol, int fixed_iters, int cap_iter, int j);
+
+hipError_t launch_ls_begin(hipStream_t s, int ninst, InstState* st, double* alphas, int K, int ls_mode,
+                           double dx, long long* ls_acc, int only_fallback);
+
+hipError_t launch_ls_eval(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
+                          double alpha_b, int beta, int K, const double* alphas, long long* ls_acc,
+                          const InstState* st, int only_pending, int* err);
+
+hipError_t launch_ls_decide(hipStream_t s, int ninst, InstState* st, double* alphas, int K, int ls_mode,
+                            int passes, int max_ls, double T1, double T2, double dx, long long* ls_acc);
+
+hipError_t launch_ls_export(hipStream_t s, int ninst, const long long* ls_acc, int K, int64_t* sums);
+
+hipError_t launch_obj_pair(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
+                           double alpha_b, int beta, long long* acc /*[ninst][2][3]*/, const InstState* st,
+                           int use_alpha, int* err);
+
+hipError_t launch_obj_decide(hipStream_t s, int ninst, const long long* acc, InstState* st, double tol,
+                             int apply_rule);
+
+hipError_t launch_fw_update(hipStream_t s, const NetDev& net, int64_t* f, const int64_t* y,
+                            const double* alpha_per_inst, const InstState* st);
+
+hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, double* out);
+hipError_t launch_after_update(hipStream_t s, int ninst, InstState* st);
+hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, float* rcost);
+
+hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* rcost, float* labels,
+                       const Scratch& scr, int slots, const InstState* st);
+
+hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+                       const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
+                       const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
+                       int32_t* r_orig, int32_t* r_dest, int64_t* r_w, unsigned long long* r_count,
+                       unsigned long long* done_fx);
+
+hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+                           const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
+                           const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
+                           int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
+                           unsigned long long* r_count, unsigned long long* done_fx,
+                           int trees_mode, int32_t* succ_out, int32_t n_out);
+
+hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+                            const float* cost_local, int32_t inst, float* dist, int32_t* succ,
+                            int32_t* absorb_q);
+
+}  // namespace qdta

@@ -1,0 +1,1167 @@
+// qdta_runtime.cpp -- host side of the QDTA library: argument validation,
+// the concatenated device layout of all instances, the Frank-Wolfe driver
+// (Alg. 6), the residual-demand step (Alg. 4) and the C ABI of qdta.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "qdta.h"
+#include "qdta_internal.h"
+
+using namespace qdta;
+
+namespace {
+
+struct Instance {
+    int32_t n = 0, m = 0;
+    std::vector<int32_t> row_ptr, col;
+    std::vector<float> fftt, cap;
+    // merged demand of the current interval, sorted by (dest, orig)
+    bool has_demand = false;
+    double dt_s = INFINITY;
+    std::vector<int32_t> orig, dest;
+    std::vector<int64_t> dfx;
+    // residual carried into the next interval (Alg. 4 output)
+    std::vector<int32_t> r_orig, r_dest;
+    std::vector<int64_t> r_w;
+    int64_t r_done = 0;
+    // per-iteration step sizes of the last solve (alpha_0 = 1)
+    std::vector<double> hist_alpha;
+    int32_t solved_iters = -1;
+};
+
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct qdta_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int cus = 256;
+    std::vector<Instance> inst;
+    bool net_dirty = true, dem_dirty = true;
+    int cur_sb = 0;
+    std::vector<void*> allocs;
+
+    // network layout
+    int64_t N = 0, M = 0;
+    int nblk = 0;
+    std::vector<InstDev> h_inst;
+    std::vector<int64_t> node_off, link_off, leg_off, dest_off;
+    DBuf<int32_t> row_ptr, col, rptr, rsrc, rlink, revpos, blk_inst, blk_start;
+    DBuf<float> c0, cap;
+    DBuf<InstDev> d_inst;
+
+    // demand layout
+    int64_t Q = 0, P = 0, B = 0, nmax = 0;
+    int slots = 0;
+    size_t label_floats = 0;
+    DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q, b_inst, b_q, b_nq;
+    DBuf<int64_t> dest_lab, leg_dfx, b_lab;
+    std::vector<int32_t> h_dest_inst, h_dest_node;
+    DBuf<float> labels;
+    DBuf<int32_t> queues;
+    DBuf<uint32_t> dirty;
+    DBuf<int32_t> stamp;
+    DBuf<int32_t> work;
+
+    // Frank-Wolfe state
+    DBuf<int64_t> f, y;
+    DBuf<float> cost, rcost, cfin;
+    DBuf<InstState> st;
+    DBuf<long long> acc, ls_acc;
+    DBuf<double> alphas, alpha_arr, lambda;
+    DBuf<int> flags;              // [0] overflow, [1] unreach, [2] absorb count
+    DBuf<int32_t> absorb_q, int_node;
+    DBuf<float> int_tau;
+    DBuf<float> hist_cost;
+    size_t hist_iters_cap = 0;
+    // residual output
+    DBuf<int32_t> r_orig, r_dest;
+    DBuf<int64_t> r_w;
+    DBuf<unsigned long long> r_count, done_fx;
+    InstState* h_st = nullptr;    // pinned mirror
+    int h_st_n = 0;
+    bool solved = false;
+};
+
+namespace {
+
+int set_err(qdta_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return code;
+}
+
+#define HIPCHECK(ctx, expr)                                                                          \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return set_err(ctx, QDTA_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int dalloc(qdta_ctx* c, DBuf<T>& b, size_t n) {
+    if (b.p && b.n >= n && n > 0) return QDTA_OK;
+    if (b.p) {
+        hipFree(b.p);
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)b.p);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        b.p = nullptr;
+        b.n = 0;
+    }
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        hipGetLastError();
+        return set_err(c, QDTA_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.n = std::max<size_t>(n, 1);
+    c->allocs.push_back((void*)b.p);
+    return QDTA_OK;
+}
+
+template <class T>
+int upload(qdta_ctx* c, DBuf<T>& b, const std::vector<T>& h) {
+    int rc = dalloc(c, b, h.size());
+    if (rc) return rc;
+    if (!h.empty()) HIPCHECK(c, hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return QDTA_OK;
+}
+
+#define RC(x)                  \
+    do {                       \
+        int rc_ = (x);         \
+        if (rc_ < 0) return rc_; \
+    } while (0)
+
+bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
+    if (!o) { set_err(c, QDTA_EARG, "opts is NULL"); return false; }
+    if (!(o->alpha >= 0.0 && std::isfinite(o->alpha))) { set_err(c, QDTA_EARG, "alpha must be finite and >= 0"); return false; }
+    if (o->beta < 1 || o->beta > 16) { set_err(c, QDTA_EARG, "beta must be in 1..16"); return false; }
+    if (o->trunc_rule < 0 || o->trunc_rule > 2) { set_err(c, QDTA_EARG, "bad trunc_rule"); return false; }
+    if (o->ls_mode < 0 || o->ls_mode > 2) { set_err(c, QDTA_EARG, "bad ls_mode"); return false; }
+    if (o->K < 3 || o->K > kMaxK) { set_err(c, QDTA_EARG, "K must be in 3..64"); return false; }
+    if (o->passes < 1 || o->passes > 8) { set_err(c, QDTA_EARG, "passes must be in 1..8"); return false; }
+    if (o->max_ls < 1 || o->max_ls > 100) { set_err(c, QDTA_EARG, "max_ls must be in 1..100"); return false; }
+    if (o->stop_rule < 0 || o->stop_rule > 1) { set_err(c, QDTA_EARG, "bad stop_rule"); return false; }
+    if (!(o->tol >= 0.0) || !(o->dx > 0.0) || !(o->T1 >= 0.0) || !(o->T2 >= 0.0)) {
+        set_err(c, QDTA_EARG, "tol, T1, T2 must be >= 0 and dx > 0");
+        return false;
+    }
+    if (o->max_iter < 0 || o->fixed_iters < 0) { set_err(c, QDTA_EARG, "negative iteration count"); return false; }
+    int sb = o->sources_per_block;
+    if (!(sb == 0 || sb == 4 || sb == 8 || sb == 16 || sb == 32)) {
+        set_err(c, QDTA_EARG, "sources_per_block must be 0, 4, 8, 16 or 32");
+        return false;
+    }
+    return true;
+}
+
+int choose_sb(const qdta_opts* o) { return o->sources_per_block ? o->sources_per_block : 16; }
+
+// ---------------------------------------------------------------------------
+// network layout: instances concatenated, reverse CSR, link chunks
+// ---------------------------------------------------------------------------
+int ensure_network(qdta_ctx* c) {
+    if (!c->net_dirty) return QDTA_OK;
+    if (c->inst.empty()) return set_err(c, QDTA_ESTATE, "no network added");
+    int ni = (int)c->inst.size();
+    c->node_off.assign(ni + 1, 0);
+    c->link_off.assign(ni + 1, 0);
+    for (int i = 0; i < ni; ++i) {
+        c->node_off[i + 1] = c->node_off[i] + c->inst[i].n;
+        c->link_off[i + 1] = c->link_off[i] + c->inst[i].m;
+    }
+    c->N = c->node_off[ni];
+    c->M = c->link_off[ni];
+    if (c->N >= INT32_MAX || c->M >= INT32_MAX) return set_err(c, QDTA_EARG, "total size beyond int32 ids");
+    std::vector<int32_t> rp(c->N + 1), col(c->M), rptr(c->N + 1, 0), rsrc(c->M), rlink(c->M), revpos(c->M);
+    std::vector<float> c0(c->M), cap(c->M);
+    std::vector<int32_t> bi, bs;
+    for (int i = 0; i < ni; ++i) {
+        const Instance& I = c->inst[i];
+        int32_t n0 = (int32_t)c->node_off[i], l0 = (int32_t)c->link_off[i];
+        for (int v = 0; v < I.n; ++v) rp[n0 + v] = l0 + I.row_ptr[v];
+        for (int a = 0; a < I.m; ++a) {
+            col[l0 + a] = n0 + I.col[a];
+            c0[l0 + a] = I.fftt[a];
+            cap[l0 + a] = I.cap[a];
+        }
+        for (int a0 = 0; a0 < I.m; a0 += kChunk) {
+            bi.push_back(i);
+            bs.push_back(l0 + a0);
+        }
+    }
+    rp[c->N] = (int32_t)c->M;
+    // reverse CSR (in-links of each node), link ids ascending within a node
+    std::vector<int32_t> tail(c->M);
+    for (int64_t v = 0; v < c->N; ++v)
+        for (int32_t a = rp[v]; a < rp[v + 1]; ++a) tail[a] = (int32_t)v;
+    for (int64_t a = 0; a < c->M; ++a) rptr[col[a] + 1]++;
+    for (int64_t v = 0; v < c->N; ++v) rptr[v + 1] += rptr[v];
+    std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
+    for (int64_t a = 0; a < c->M; ++a) {
+        int32_t pos = fill[col[a]]++;
+        rsrc[pos] = tail[a];
+        rlink[pos] = (int32_t)a;
+        revpos[a] = pos;
+    }
+    c->h_inst.assign(ni, InstDev{});
+    for (int i = 0; i < ni; ++i) {
+        InstDev& d = c->h_inst[i];
+        d.node0 = (int32_t)c->node_off[i];
+        d.n = c->inst[i].n;
+        d.link0 = (int32_t)c->link_off[i];
+        d.m = c->inst[i].m;
+        d.rule = QDTA_RULE_NONE;
+        d.dt32 = INFINITY;
+        d.kappa = 1.0;
+    }
+    c->nblk = (int)bi.size();
+    RC(upload(c, c->row_ptr, rp));
+    RC(upload(c, c->col, col));
+    RC(upload(c, c->c0, c0));
+    RC(upload(c, c->cap, cap));
+    RC(upload(c, c->rptr, rptr));
+    RC(upload(c, c->rsrc, rsrc));
+    RC(upload(c, c->rlink, rlink));
+    RC(upload(c, c->revpos, revpos));
+    RC(upload(c, c->blk_inst, bi));
+    RC(upload(c, c->blk_start, bs));
+    RC(upload(c, c->d_inst, c->h_inst));
+    RC(dalloc(c, c->f, c->M));
+    RC(dalloc(c, c->y, c->M));
+    RC(dalloc(c, c->cost, c->M));
+    RC(dalloc(c, c->rcost, c->M));
+    RC(dalloc(c, c->cfin, c->M));
+    RC(dalloc(c, c->st, ni));
+    RC(dalloc(c, c->acc, (size_t)ni * 6));
+    RC(dalloc(c, c->ls_acc, (size_t)ni * kMaxK * 6));
+    RC(dalloc(c, c->alphas, (size_t)ni * kMaxK));
+    RC(dalloc(c, c->alpha_arr, ni));
+    RC(dalloc(c, c->lambda, ni));
+    RC(dalloc(c, c->flags, 4));
+    RC(dalloc(c, c->done_fx, ni));
+    RC(dalloc(c, c->r_count, 1));
+    if (c->h_st_n < ni) {
+        if (c->h_st) hipHostFree(c->h_st);
+        HIPCHECK(c, hipHostMalloc((void**)&c->h_st, sizeof(InstState) * ni, hipHostMallocDefault));
+        c->h_st_n = ni;
+    }
+    c->net_dirty = false;
+    c->dem_dirty = true;
+    c->cur_sb = 0;
+    return QDTA_OK;
+}
+
+NetDev net_view(qdta_ctx* c) {
+    NetDev v;
+    v.row_ptr = c->row_ptr.p;
+    v.col = c->col.p;
+    v.c0 = c->c0.p;
+    v.cap = c->cap.p;
+    v.rptr = c->rptr.p;
+    v.rsrc = c->rsrc.p;
+    v.rlink = c->rlink.p;
+    v.revpos = c->revpos.p;
+    v.inst = c->d_inst.p;
+    v.blk_inst = c->blk_inst.p;
+    v.blk_start = c->blk_start.p;
+    v.ninst = (int32_t)c->inst.size();
+    v.nblk = c->nblk;
+    v.N = c->N;
+    v.M = c->M;
+    return v;
+}
+
+// Destination batches: destinations of an instance in ascending node order
+// (spatially coherent when nodes follow a space-filling curve), SB per batch.
+struct BatchPlan {
+    std::vector<int32_t> dest_node, dest_inst, b_inst, b_q, b_nq;
+    std::vector<int64_t> dest_lab, b_lab;
+    size_t label_floats = 0;
+};
+
+void plan_batches(const std::vector<InstDev>& hi, const std::vector<std::vector<int32_t>>& dests_per_inst, int sb,
+                  BatchPlan& bp) {
+    int64_t lab = 0;
+    for (size_t i = 0; i < dests_per_inst.size(); ++i) {
+        const auto& ds = dests_per_inst[i];
+        int n = hi[i].n;
+        for (size_t k = 0; k < ds.size(); k += sb) {
+            int cnt = (int)std::min<size_t>(sb, ds.size() - k);
+            bp.b_inst.push_back((int32_t)i);
+            bp.b_q.push_back((int32_t)bp.dest_node.size());
+            bp.b_nq.push_back(cnt);
+            bp.b_lab.push_back(lab);
+            for (int t = 0; t < cnt; ++t) {
+                bp.dest_node.push_back(hi[i].node0 + ds[k + t]);
+                bp.dest_inst.push_back((int32_t)i);
+                bp.dest_lab.push_back(lab + t);
+            }
+            lab += (int64_t)n * sb;
+        }
+    }
+    bp.label_floats = (size_t)lab;
+}
+
+int ensure_scratch(qdta_ctx* c, int64_t B, int64_t nmax) {
+    int slots = (int)std::min<int64_t>(std::max<int64_t>(B, 1), (int64_t)c->cus * 8);
+    c->slots = slots;
+    c->nmax = std::max<int64_t>(nmax, 1);
+    RC(dalloc(c, c->queues, (size_t)slots * 2 * c->nmax));
+    RC(dalloc(c, c->dirty, (size_t)slots * c->nmax));
+    RC(dalloc(c, c->stamp, (size_t)slots * c->nmax));
+    RC(dalloc(c, c->work, 1));
+    return QDTA_OK;
+}
+
+int ensure_demand(qdta_ctx* c, int sb) {
+    RC(ensure_network(c));
+    if (!c->dem_dirty && c->cur_sb == sb) return QDTA_OK;
+    int ni = (int)c->inst.size();
+    std::vector<std::vector<int32_t>> dests(ni);
+    std::vector<int32_t> qptr{0}, leg_orig, leg_q;
+    std::vector<int64_t> leg_dfx;
+    c->leg_off.assign(ni + 1, 0);
+    c->dest_off.assign(ni + 1, 0);
+    int64_t nmax = 0;
+    for (int i = 0; i < ni; ++i) {
+        Instance& I = c->inst[i];
+        InstDev& d = c->h_inst[i];
+        bool fin = std::isfinite(I.dt_s);
+        d.kappa = fin ? 3600.0 / I.dt_s : 1.0;
+        d.dt32 = (float)I.dt_s;
+        d.rule = QDTA_RULE_NONE;
+        d.q0 = (int32_t)qptr.size() - 1;
+        d.leg0 = (int32_t)leg_orig.size();
+        size_t p = 0;
+        while (p < I.orig.size()) {
+            int32_t q = I.dest[p];
+            dests[i].push_back(q);
+            int32_t qi = (int32_t)qptr.size() - 1;
+            while (p < I.orig.size() && I.dest[p] == q) {
+                leg_orig.push_back(d.node0 + I.orig[p]);
+                leg_dfx.push_back(I.dfx[p]);
+                leg_q.push_back(qi);
+                ++p;
+            }
+            qptr.push_back((int32_t)leg_orig.size());
+        }
+        d.nq = (int32_t)dests[i].size();
+        d.nleg = (int32_t)I.orig.size();
+        c->leg_off[i + 1] = c->leg_off[i] + d.nleg;
+        c->dest_off[i + 1] = c->dest_off[i] + d.nq;
+        nmax = std::max<int64_t>(nmax, I.n);
+    }
+    BatchPlan bp;
+    plan_batches(c->h_inst, dests, sb, bp);
+    c->Q = (int64_t)bp.dest_node.size();
+    c->P = (int64_t)leg_orig.size();
+    c->B = (int64_t)bp.b_inst.size();
+    c->label_floats = bp.label_floats;
+    c->h_dest_inst = bp.dest_inst;
+    c->h_dest_node = bp.dest_node;
+    RC(upload(c, c->dest_node, bp.dest_node));
+    RC(upload(c, c->dest_inst, bp.dest_inst));
+    RC(upload(c, c->dest_lab, bp.dest_lab));
+    RC(upload(c, c->qptr, qptr));
+    RC(upload(c, c->leg_orig, leg_orig));
+    RC(upload(c, c->leg_dfx, leg_dfx));
+    RC(upload(c, c->leg_q, leg_q));
+    RC(upload(c, c->b_inst, bp.b_inst));
+    RC(upload(c, c->b_q, bp.b_q));
+    RC(upload(c, c->b_nq, bp.b_nq));
+    RC(upload(c, c->b_lab, bp.b_lab));
+    RC(upload(c, c->d_inst, c->h_inst));
+    RC(dalloc(c, c->labels, c->label_floats));
+    RC(dalloc(c, c->absorb_q, (size_t)c->Q));
+    RC(dalloc(c, c->int_node, (size_t)c->P));
+    RC(dalloc(c, c->int_tau, (size_t)c->P));
+    RC(ensure_scratch(c, c->B, nmax));
+    c->dem_dirty = false;
+    c->cur_sb = sb;
+    c->solved = false;
+    return QDTA_OK;
+}
+
+// The truncation rule comes with the options; it is stored per instance
+// (NONE for plain intervals, dt = inf) in the device descriptors.
+int apply_rule(qdta_ctx* c, const qdta_opts* o) {
+    bool changed = false;
+    for (size_t i = 0; i < c->inst.size(); ++i) {
+        int32_t r = std::isfinite(c->inst[i].dt_s) ? o->trunc_rule : QDTA_RULE_NONE;
+        if (c->h_inst[i].rule != r) {
+            c->h_inst[i].rule = r;
+            changed = true;
+        }
+    }
+    if (changed) RC(upload(c, c->d_inst, c->h_inst));
+    return QDTA_OK;
+}
+
+DemDev dem_view(qdta_ctx* c) {
+    DemDev v;
+    v.dest_node = c->dest_node.p;
+    v.dest_inst = c->dest_inst.p;
+    v.dest_lab = c->dest_lab.p;
+    v.qptr = c->qptr.p;
+    v.leg_orig = c->leg_orig.p;
+    v.leg_dfx = c->leg_dfx.p;
+    v.leg_q = c->leg_q.p;
+    v.b_inst = c->b_inst.p;
+    v.b_q = c->b_q.p;
+    v.b_nq = c->b_nq.p;
+    v.b_lab = c->b_lab.p;
+    v.Q = (int32_t)c->Q;
+    v.P = (int32_t)c->P;
+    v.B = (int32_t)c->B;
+    v.sb = c->cur_sb;
+    return v;
+}
+
+Scratch scr_view(qdta_ctx* c) {
+    Scratch s;
+    s.queues = c->queues.p;
+    s.dirty = c->dirty.p;
+    s.stamp = c->stamp.p;
+    s.nmax = (int32_t)c->nmax;
+    s.work = c->work.p;
+    return s;
+}
+
+FlagsDev flags_view(qdta_ctx* c) {
+    FlagsDev f;
+    f.err_overflow = c->flags.p;
+    f.err_unreach = c->flags.p + 1;
+    f.absorb_count = c->flags.p + 2;
+    f.absorb_q = c->absorb_q.p;
+    f.int_node = c->int_node.p;
+    f.int_tau = c->int_tau.p;
+    return f;
+}
+
+int clear_flags(qdta_ctx* c) {
+    HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->flags.p), 0u, 4));
+    return QDTA_OK;
+}
+
+int read_flags(qdta_ctx* c, int* h) {
+    HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return QDTA_OK;
+}
+
+// One all-or-nothing assignment (A2 + A3) under `cost` (rcost already set).
+int aon_core(qdta_ctx* c, const float* cost, int64_t* y, int32_t* stop, const InstState* st) {
+    NetDev net = net_view(c);
+    DemDev dem = dem_view(c);
+    FlagsDev fl = flags_view(c);
+    HIPCHECK(c, launch_sssp(c->stream, net, dem, c->rcost.p, c->labels.p, scr_view(c), c->slots, st));
+    HIPCHECK(c, launch_fill_i64(c->stream, y, 0, c->M));
+    HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
+    HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
+                            nullptr, nullptr, nullptr, nullptr));
+    HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
+                                (int)std::min<int64_t>(c->slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0));
+    return QDTA_OK;
+}
+
+int init_state(qdta_ctx* c, bool all_instances, int iter) {
+    int ni = (int)c->inst.size();
+    for (int i = 0; i < ni; ++i) {
+        InstState s;
+        memset(&s, 0, sizeof(s));
+        s.active = all_instances ? (c->inst[i].m > 0) : (c->h_inst[i].nleg > 0);
+        s.iter = iter;
+        c->h_st[i] = s;
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(InstState) * ni, hipMemcpyHostToDevice, c->stream));
+    return QDTA_OK;
+}
+
+int pull_state(qdta_ctx* c) {
+    int ni = (int)c->inst.size();
+    HIPCHECK(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(InstState) * ni, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return QDTA_OK;
+}
+
+// Line search of the current iteration for every live instance (A5).
+int line_search_core(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_t* y) {
+    NetDev net = net_view(c);
+    int ni = (int)c->inst.size();
+    int* err = c->flags.p;
+    int K = o->ls_mode == QDTA_LS_QN ? 3 : o->K;
+    HIPCHECK(c, launch_ls_begin(c->stream, ni, c->st.p, c->alphas.p, K, o->ls_mode, o->dx, c->ls_acc.p, 0));
+    if (o->ls_mode == QDTA_LS_MSA) return QDTA_OK;
+    if (o->ls_mode == QDTA_LS_KSECTION) {
+        for (int p = 0; p < o->passes; ++p) {
+            HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, K, c->alphas.p, c->ls_acc.p, c->st.p, 1,
+                                       err));
+            HIPCHECK(c, launch_ls_decide(c->stream, ni, c->st.p, c->alphas.p, K, 0, o->passes, o->max_ls, o->T1, o->T2,
+                                         o->dx, c->ls_acc.p));
+        }
+        return QDTA_OK;
+    }
+    // quasi-Newton (Alg. 8): iterate until every live instance is done
+    for (int l = 0; l < o->max_ls; ++l) {
+        HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, 3, c->alphas.p, c->ls_acc.p, c->st.p, 1, err));
+        HIPCHECK(c, launch_ls_decide(c->stream, ni, c->st.p, c->alphas.p, 3, 1, o->passes, o->max_ls, o->T1, o->T2,
+                                     o->dx, c->ls_acc.p));
+        RC(pull_state(c));
+        bool pending = false, fallback = false;
+        for (int i = 0; i < ni; ++i) {
+            const InstState& s = c->h_st[i];
+            if (!s.active || s.converged) continue;
+            if (s.ls_done == 0) pending = true;
+            if (s.ls_done == 2) fallback = true;
+        }
+        if (!pending) {
+            if (fallback) {
+                // C'' <= 0: K-section for those instances (non-convex stencil)
+                HIPCHECK(c, launch_ls_begin(c->stream, ni, c->st.p, c->alphas.p, o->K, 0, o->dx, c->ls_acc.p, 1));
+                for (int p = 0; p < o->passes; ++p) {
+                    HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, o->K, c->alphas.p, c->ls_acc.p,
+                                               c->st.p, 1, err));
+                    HIPCHECK(c, launch_ls_decide(c->stream, ni, c->st.p, c->alphas.p, o->K, 0, o->passes, o->max_ls,
+                                                 o->T1, o->T2, o->dx, c->ls_acc.p));
+                }
+            }
+            break;
+        }
+    }
+    return QDTA_OK;
+}
+
+int flag_code(qdta_ctx* c, const int* h) {
+    if (h[0]) return set_err(c, QDTA_EOVF, "non-finite link cost or exact-sum overflow");
+    if (h[1]) return set_err(c, QDTA_EUNREACH, "a leg's destination is unreachable from its origin");
+    return QDTA_OK;
+}
+
+int ensure_history(qdta_ctx* c, size_t iters) {
+    if (c->hist_iters_cap >= iters) return QDTA_OK;
+    size_t want = std::max(iters, c->hist_iters_cap * 2);
+    DBuf<float> nb;
+    RC(dalloc(c, nb, want * (size_t)c->M));
+    if (c->hist_cost.p && c->hist_iters_cap)
+        HIPCHECK(c, hipMemcpyAsync(nb.p, c->hist_cost.p, c->hist_iters_cap * (size_t)c->M * sizeof(float),
+                                   hipMemcpyDeviceToDevice, c->stream));
+    if (c->hist_cost.p) {
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        hipFree(c->hist_cost.p);
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->hist_cost.p);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+    }
+    c->hist_cost = nb;
+    c->hist_iters_cap = want;
+    return QDTA_OK;
+}
+
+int64_t trips_fx(double t) { return (int64_t)std::nearbyint(t * 1048576.0); }
+
+// Sort legs by (dest, orig) and sum equal pairs; drop zero and orig == dest.
+void merge_legs(std::vector<int32_t>& o, std::vector<int32_t>& d, std::vector<int64_t>& w) {
+    std::vector<size_t> idx(o.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return d[a] != d[b] ? d[a] < d[b] : o[a] < o[b]; });
+    std::vector<int32_t> no, nd;
+    std::vector<int64_t> nw;
+    for (size_t k = 0; k < idx.size(); ++k) {
+        size_t i = idx[k];
+        if (!nd.empty() && nd.back() == d[i] && no.back() == o[i]) nw.back() += w[i];
+        else { no.push_back(o[i]); nd.push_back(d[i]); nw.push_back(w[i]); }
+    }
+    size_t j = 0;
+    for (size_t k = 0; k < no.size(); ++k) {
+        if (nw[k] > 0 && no[k] != nd[k]) { no[j] = no[k]; nd[j] = nd[k]; nw[j] = nw[k]; ++j; }
+    }
+    no.resize(j); nd.resize(j); nw.resize(j);
+    o.swap(no); d.swap(nd); w.swap(nw);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void qdta_default_opts(qdta_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->alpha = 0.15;
+    o->beta = 4;
+    o->trunc_rule = QDTA_RULE_CEIL;
+    o->ls_mode = QDTA_LS_KSECTION;
+    o->K = 32;
+    o->passes = 3;
+    o->max_ls = 20;
+    o->T1 = 1e-4;
+    o->T2 = 1e-4;
+    o->dx = 1e-4;
+    o->stop_rule = QDTA_STOP_GAP;
+    o->tol = 1e-4;
+    o->max_iter = 1000;
+    o->fixed_iters = 0;
+    o->keep_history = 0;
+    o->sources_per_block = 0;
+}
+
+const char* qdta_strerror(int code) {
+    switch (code) {
+        case QDTA_OK: return "ok";
+        case QDTA_EARG: return "bad argument";
+        case QDTA_ECSR: return "malformed CSR";
+        case QDTA_EVAL: return "free-flow time or capacity not positive and finite";
+        case QDTA_EUNREACH: return "destination unreachable from origin";
+        case QDTA_EOVF: return "overflow";
+        case QDTA_ENOMEM: return "device allocation failed";
+        case QDTA_EHIP: return "HIP runtime error";
+        case QDTA_ESTATE: return "call out of order";
+        case QDTA_WABSORB: return "FP32 absorption: tie-rule fallback used";
+        default: return "unknown code";
+    }
+}
+
+const char* qdta_last_error(const qdta_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int qdta_create(qdta_ctx** out, int device, void* stream) {
+    if (!out) return QDTA_EARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QDTA_EARG;
+    if (hipSetDevice(device) != hipSuccess) return QDTA_EHIP;
+    qdta_ctx* c = new qdta_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->cus = prop.multiProcessorCount;
+    *out = c;
+    return QDTA_OK;
+}
+
+int qdta_destroy(qdta_ctx* c) {
+    if (!c) return QDTA_EARG;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) hipFree(p);
+    if (c->h_st) hipHostFree(c->h_st);
+    delete c;
+    return QDTA_OK;
+}
+
+int qdta_set_stream(qdta_ctx* c, void* stream) {
+    if (!c) return QDTA_EARG;
+    c->stream = (hipStream_t)stream;
+    return QDTA_OK;
+}
+
+int qdta_add_network(qdta_ctx* c, int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col,
+                     const float* fftt, const float* cap, int32_t* inst_out) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (n <= 0 || m < 0 || !row_ptr || (m > 0 && (!col || !fftt || !cap)))
+        return set_err(c, QDTA_EARG, "bad sizes or null arrays");
+    if (row_ptr[0] != 0 || row_ptr[n] != m) return set_err(c, QDTA_ECSR, "row_ptr must start at 0 and end at m");
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return set_err(c, QDTA_ECSR, "row_ptr decreases at node %d", v);
+    for (int32_t a = 0; a < m; ++a) {
+        if (col[a] < 0 || col[a] >= n) return set_err(c, QDTA_ECSR, "col[%d] = %d out of range", a, col[a]);
+        if (!(fftt[a] > 0.0f) || !std::isfinite(fftt[a])) return set_err(c, QDTA_EVAL, "fftt[%d] not > 0 and finite", a);
+        if (!(cap[a] > 0.0f) || !std::isfinite(cap[a])) return set_err(c, QDTA_EVAL, "cap[%d] not > 0 and finite", a);
+    }
+    Instance I;
+    I.n = n;
+    I.m = m;
+    I.row_ptr.assign(row_ptr, row_ptr + n + 1);
+    I.col.assign(col, col + m);
+    I.fftt.assign(fftt, fftt + m);
+    I.cap.assign(cap, cap + m);
+    c->inst.push_back(std::move(I));
+    c->net_dirty = true;
+    c->dem_dirty = true;
+    if (inst_out) *inst_out = (int32_t)c->inst.size() - 1;
+    return QDTA_OK;
+}
+
+int qdta_set_demand(qdta_ctx* c, int32_t inst, int32_t P, const int32_t* orig, const int32_t* dest,
+                    const double* trips, double dt_s) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
+    if (P < 0 || (P > 0 && (!orig || !dest || !trips))) return set_err(c, QDTA_EARG, "bad legs");
+    if (!(dt_s > 0.0)) return set_err(c, QDTA_EARG, "dt must be > 0 (or +inf)");
+    Instance& I = c->inst[inst];
+    std::vector<int32_t> o, d;
+    std::vector<int64_t> w;
+    o.reserve(P + I.r_orig.size());
+    for (int32_t p = 0; p < P; ++p) {
+        if (orig[p] < 0 || orig[p] >= I.n || dest[p] < 0 || dest[p] >= I.n)
+            return set_err(c, QDTA_EARG, "leg %d: node out of range", p);
+        if (!(trips[p] >= 0.0) || !std::isfinite(trips[p])) return set_err(c, QDTA_EARG, "leg %d: bad trips", p);
+        if (trips[p] * 1048576.0 >= 9.0e18) return set_err(c, QDTA_EOVF, "leg %d: trips beyond fixed point", p);
+        o.push_back(orig[p]);
+        d.push_back(dest[p]);
+        w.push_back(trips_fx(trips[p]));
+    }
+    o.insert(o.end(), I.r_orig.begin(), I.r_orig.end());
+    d.insert(d.end(), I.r_dest.begin(), I.r_dest.end());
+    w.insert(w.end(), I.r_w.begin(), I.r_w.end());
+    merge_legs(o, d, w);
+    I.orig.swap(o);
+    I.dest.swap(d);
+    I.dfx.swap(w);
+    I.r_orig.clear();
+    I.r_dest.clear();
+    I.r_w.clear();
+    I.dt_s = dt_s;
+    I.has_demand = true;
+    I.solved_iters = -1;
+    c->dem_dirty = true;
+    c->solved = false;
+    return QDTA_OK;
+}
+
+int qdta_layout(qdta_ctx* c, qdta_layout_info* info) {
+    if (!c || !info) return QDTA_EARG;
+    RC(ensure_network(c));
+    if (c->dem_dirty) RC(ensure_demand(c, c->cur_sb ? c->cur_sb : 16));
+    info->n_instances = (int32_t)c->inst.size();
+    info->total_nodes = c->N;
+    info->total_links = c->M;
+    info->total_legs = c->P;
+    info->total_dests = c->Q;
+    return QDTA_OK;
+}
+
+int qdta_offsets(qdta_ctx* c, int64_t* node_off, int64_t* link_off, int64_t* leg_off, int64_t* dest_off) {
+    if (!c) return QDTA_EARG;
+    RC(ensure_network(c));
+    if (c->dem_dirty) RC(ensure_demand(c, c->cur_sb ? c->cur_sb : 16));
+    size_t k = c->inst.size() + 1;
+    if (node_off) std::copy(c->node_off.begin(), c->node_off.begin() + k, node_off);
+    if (link_off) std::copy(c->link_off.begin(), c->link_off.begin() + k, link_off);
+    if (leg_off) std::copy(c->leg_off.begin(), c->leg_off.begin() + k, leg_off);
+    if (dest_off) std::copy(c->dest_off.begin(), c->dest_off.begin() + k, dest_off);
+    return QDTA_OK;
+}
+
+int qdta_get_legs(qdta_ctx* c, int32_t* ho, int32_t* hd, int64_t* hw) {
+    if (!c) return QDTA_EARG;
+    size_t k = 0;
+    for (const Instance& I : c->inst) {
+        for (size_t p = 0; p < I.orig.size(); ++p, ++k) {
+            if (ho) ho[k] = I.orig[p];
+            if (hd) hd[k] = I.dest[p];
+            if (hw) hw[k] = I.dfx[p];
+        }
+    }
+    return QDTA_OK;
+}
+
+int qdta_bpr(qdta_ctx* c, const qdta_opts* o, const int64_t* f, float* cost) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!f || !cost) return set_err(c, QDTA_EARG, "null array");
+    RC(ensure_network(c));
+    if (c->dem_dirty) RC(ensure_demand(c, choose_sb(o)));   // kappa of each instance
+    RC(clear_flags(c));
+    HIPCHECK(c, launch_bpr(c->stream, net_view(c), f, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
+    int h[4];
+    RC(read_flags(c, h));
+    return flag_code(c, h);
+}
+
+int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost, int32_t nq, const int32_t* dest,
+               float* dist, int32_t* succ) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    RC(ensure_network(c));
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
+    if (nq < 0 || (nq > 0 && (!cost || !dest || !dist || !succ))) return set_err(c, QDTA_EARG, "bad arguments");
+    if (nq == 0) return QDTA_OK;
+    const InstDev& I = c->h_inst[inst];
+    std::vector<int32_t> hd(nq);
+    HIPCHECK(c, hipMemcpyAsync(hd.data(), dest, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (int t = 0; t < nq; ++t)
+        if (hd[t] < 0 || hd[t] >= I.n) return set_err(c, QDTA_EARG, "dest[%d] out of range", t);
+    int sb = choose_sb(o);
+    // ad-hoc batches: one tree per requested destination, in order
+    std::vector<std::vector<int32_t>> per(c->inst.size());
+    per[inst] = hd;
+    BatchPlan bp;
+    plan_batches(c->h_inst, per, sb, bp);
+    DBuf<int32_t> dn, di, bi, bq, bn, aq;
+    DBuf<int64_t> dl, bl;
+    DBuf<float> lab;
+    std::vector<void*> tmp;
+    auto cleanup = [&]() {
+        for (void* p : {(void*)dn.p, (void*)di.p, (void*)bi.p, (void*)bq.p, (void*)bn.p, (void*)aq.p, (void*)dl.p,
+                        (void*)bl.p, (void*)lab.p}) {
+            if (!p) continue;
+            hipFree(p);
+            auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+            if (it != c->allocs.end()) c->allocs.erase(it);
+        }
+    };
+    int rc = QDTA_OK;
+    do {
+        if ((rc = upload(c, dn, bp.dest_node))) break;
+        if ((rc = upload(c, di, bp.dest_inst))) break;
+        if ((rc = upload(c, dl, bp.dest_lab))) break;
+        if ((rc = upload(c, bi, bp.b_inst))) break;
+        if ((rc = upload(c, bq, bp.b_q))) break;
+        if ((rc = upload(c, bn, bp.b_nq))) break;
+        if ((rc = upload(c, bl, bp.b_lab))) break;
+        if ((rc = dalloc(c, lab, bp.label_floats))) break;
+        if ((rc = dalloc(c, aq, nq))) break;
+        if ((rc = ensure_scratch(c, std::max<int64_t>((int64_t)bp.b_inst.size(), c->B), std::max<int64_t>(c->nmax, I.n))))
+            break;
+        DemDev dem;
+        memset(&dem, 0, sizeof(dem));
+        dem.dest_node = dn.p;
+        dem.dest_inst = di.p;
+        dem.dest_lab = dl.p;
+        dem.b_inst = bi.p;
+        dem.b_q = bq.p;
+        dem.b_nq = bn.p;
+        dem.b_lab = bl.p;
+        dem.Q = nq;
+        dem.B = (int32_t)bp.b_inst.size();
+        dem.sb = sb;
+        NetDev net = net_view(c);
+        hipError_t e;
+        // place the instance's costs in the global link order
+        if ((e = hipMemcpyAsync(c->cost.p + I.link0, cost, sizeof(float) * I.m, hipMemcpyDeviceToDevice, c->stream)))
+            { rc = set_err(c, QDTA_EHIP, "copy cost: %s", hipGetErrorString(e)); break; }
+        if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p)))
+            { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
+        int slots = (int)std::min<int64_t>(c->slots, dem.B);
+        if ((e = launch_sssp(c->stream, net, dem, c->rcost.p, lab.p, scr_view(c), slots, nullptr)))
+            { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
+        if ((e = launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(aq.p), 0u, nq)))
+            { rc = set_err(c, QDTA_EHIP, "fill: %s", hipGetErrorString(e)); break; }
+        if ((e = launch_trees_out(c->stream, net, dem, lab.p, c->cost.p, inst, dist, succ, aq.p)))
+            { rc = set_err(c, QDTA_EHIP, "trees_out: %s", hipGetErrorString(e)); break; }
+        FlagsDev fl = flags_view(c);
+        fl.absorb_q = aq.p;
+        if ((e = launch_fallback(c->stream, net, dem, lab.p, c->cost.p, c->cost.p, nullptr, nullptr, nullptr, fl,
+                                 scr_view(c), (int)std::min<int64_t>(c->slots, nq), 0, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, 1, succ, I.n)))
+            { rc = set_err(c, QDTA_EHIP, "fallback: %s", hipGetErrorString(e)); break; }
+        std::vector<int32_t> ha(nq);
+        if ((e = hipMemcpyAsync(ha.data(), aq.p, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, c->stream)))
+            { rc = set_err(c, QDTA_EHIP, "copy: %s", hipGetErrorString(e)); break; }
+        if ((e = hipStreamSynchronize(c->stream))) { rc = set_err(c, QDTA_EHIP, "sync: %s", hipGetErrorString(e)); break; }
+        for (int t = 0; t < nq; ++t)
+            if (ha[t]) rc = QDTA_WABSORB;
+    } while (0);
+    hipStreamSynchronize(c->stream);
+    cleanup();
+    return rc;
+}
+
+int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!cost || !y) return set_err(c, QDTA_EARG, "null array");
+    RC(ensure_demand(c, choose_sb(o)));
+    RC(apply_rule(c, o));
+    RC(init_state(c, false, 0));
+    RC(clear_flags(c));
+    NetDev net = net_view(c);
+    HIPCHECK(c, hipMemcpyAsync(c->cost.p, cost, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(c, launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p));
+    if (stop) HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(stop), 0xffffffffu, c->P));
+    RC(aon_core(c, c->cost.p, y, stop, nullptr));
+    int h[4];
+    RC(read_flags(c, h));
+    RC(flag_code(c, h));
+    return h[2] ? QDTA_WABSORB : QDTA_OK;
+}
+
+int qdta_ls_eval(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_t* y, int32_t K, const double* alphas,
+                 int64_t* sums) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (K < 1 || K > kMaxK || !f || !y || !alphas || !sums) return set_err(c, QDTA_EARG, "bad arguments");
+    RC(ensure_network(c));
+    if (c->dem_dirty) RC(ensure_demand(c, choose_sb(o)));
+    int ni = (int)c->inst.size();
+    RC(clear_flags(c));
+    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->ls_acc.p), 0, (int64_t)ni * K * 6));
+    HIPCHECK(c, launch_ls_eval(c->stream, net_view(c), f, y, o->alpha, o->beta, K, alphas, c->ls_acc.p, nullptr, 0,
+                               c->flags.p));
+    HIPCHECK(c, launch_ls_export(c->stream, ni, c->ls_acc.p, K, sums));
+    int h[4];
+    RC(read_flags(c, h));
+    return flag_code(c, h);
+}
+
+int qdta_line_search(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_t* y, int32_t j,
+                     double* alpha_out) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!f || !y || !alpha_out || j < 1) return set_err(c, QDTA_EARG, "bad arguments");
+    RC(ensure_network(c));
+    if (c->dem_dirty) RC(ensure_demand(c, choose_sb(o)));
+    int ni = (int)c->inst.size();
+    RC(init_state(c, true, j));
+    RC(clear_flags(c));
+    RC(line_search_core(c, o, f, y));
+    HIPCHECK(c, launch_copy_alpha(c->stream, ni, c->st.p, alpha_out));
+    int h[4];
+    RC(read_flags(c, h));
+    RC(flag_code(c, h));
+    RC(pull_state(c));
+    return QDTA_OK;
+}
+
+int qdta_fw_update(qdta_ctx* c, int64_t* f, const int64_t* y, const double* alpha) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!f || !y || !alpha) return set_err(c, QDTA_EARG, "null array");
+    RC(ensure_network(c));
+    HIPCHECK(c, launch_fw_update(c->stream, net_view(c), f, y, alpha, nullptr));
+    return QDTA_OK;
+}
+
+int qdta_solve(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    for (const Instance& I : c->inst)
+        if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solve");
+    RC(ensure_demand(c, choose_sb(o)));
+    RC(apply_rule(c, o));
+    int ni = (int)c->inst.size();
+    NetDev net = net_view(c);
+    int* err = c->flags.p;
+    const int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
+    RC(init_state(c, false, 0));
+    RC(clear_flags(c));
+    if (o->keep_history) RC(ensure_history(c, 8));
+    for (Instance& I : c->inst) {
+        I.hist_alpha.assign(1, 1.0);
+        I.solved_iters = -1;
+    }
+    // initial AON at free flow: BPR(0) = c0 exactly (Alg. 6 first step)
+    HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, err));
+    RC(aon_core(c, c->cost.p, c->f.p, nullptr, c->st.p));
+    if (o->keep_history)
+        HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p, c->cost.p, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
+    int h[4];
+    for (int j = 1;; ++j) {
+        HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, err));
+        RC(aon_core(c, c->cost.p, c->y.p, nullptr, c->st.p));
+        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
+        HIPCHECK(c, launch_gap_sums(c->stream, net, c->cost.p, c->f.p, c->y.p, c->acc.p, c->st.p, err));
+        HIPCHECK(c, launch_gap_decide(c->stream, ni, c->acc.p, c->st.p, o->stop_rule, o->tol, o->fixed_iters, cap_iter,
+                                      j));
+        RC(line_search_core(c, o, c->f.p, c->y.p));
+        if (o->stop_rule == QDTA_STOP_OBJ && o->fixed_iters <= 0) {
+            HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
+            HIPCHECK(c, launch_obj_pair(c->stream, net, c->f.p, c->y.p, o->alpha, o->beta, c->acc.p, c->st.p, 1, err));
+            HIPCHECK(c, launch_obj_decide(c->stream, ni, c->acc.p, c->st.p, o->tol, 1));
+        }
+        HIPCHECK(c, launch_copy_alpha(c->stream, ni, c->st.p, c->alpha_arr.p));
+        HIPCHECK(c, launch_fw_update(c->stream, net, c->f.p, c->y.p, c->alpha_arr.p, c->st.p));
+        HIPCHECK(c, launch_after_update(c->stream, ni, c->st.p));
+        if (o->keep_history) {
+            RC(ensure_history(c, (size_t)j + 1));
+            HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p + (size_t)j * c->M, c->cost.p, sizeof(float) * c->M,
+                                       hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        RC(pull_state(c));
+        RC(flag_code(c, h));
+        bool live = false;
+        for (int i = 0; i < ni; ++i) {
+            const InstState& s = c->h_st[i];
+            if (!s.active) continue;
+            if (!s.converged) {
+                live = true;
+                c->inst[i].hist_alpha.push_back(s.alpha);
+            }
+        }
+        if (!live) break;
+    }
+    // objective of the returned iterates
+    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
+    HIPCHECK(c, launch_obj_pair(c->stream, net, c->f.p, c->y.p, o->alpha, o->beta, c->acc.p, c->st.p, 0, err));
+    HIPCHECK(c, launch_obj_decide(c->stream, ni, c->acc.p, c->st.p, o->tol, 0));
+    HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    RC(pull_state(c));
+    int worst = flag_code(c, h);
+    for (int i = 0; i < ni; ++i) {
+        const InstState& s = c->h_st[i];
+        c->inst[i].solved_iters = s.iters;
+        c->inst[i].hist_alpha.resize((size_t)s.iters + 1);
+        if (hs) {
+            qdta_stats& q = hs[i];
+            q.iters = s.iters;
+            q.ls_evals = s.ls_evals;
+            q.qn_iters = s.qn_iters;
+            q.absorb = h[2] ? 1 : 0;
+            q.stopped_by = s.stopped_by;
+            q.status = worst;
+            q.gap = s.active ? s.gap : 0.0;
+            q.objective = s.obj;
+            q.last_alpha = s.last_alpha;
+        }
+    }
+    c->solved = true;
+    if (worst < 0) return worst;
+    return h[2] ? QDTA_WABSORB : QDTA_OK;
+}
+
+int qdta_get_flows(qdta_ctx* c, int64_t* f) {
+    if (!c || !f) return QDTA_EARG;
+    if (!c->solved) return set_err(c, QDTA_ESTATE, "no solved interval");
+    HIPCHECK(c, hipMemcpyAsync(f, c->f.p, sizeof(int64_t) * c->M, hipMemcpyDeviceToDevice, c->stream));
+    return QDTA_OK;
+}
+
+int qdta_get_costs(qdta_ctx* c, const qdta_opts* o, float* cost) {
+    if (!c || !cost) return QDTA_EARG;
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!c->solved) return set_err(c, QDTA_ESTATE, "no solved interval");
+    HIPCHECK(c, launch_bpr(c->stream, net_view(c), c->f.p, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
+    return QDTA_OK;
+}
+
+int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!c->solved) return set_err(c, QDTA_ESTATE, "advance needs a solved interval");
+    if (!o->keep_history) return set_err(c, QDTA_ESTATE, "advance needs keep_history during solve");
+    RC(apply_rule(c, o));
+    int ni = (int)c->inst.size();
+    NetDev net = net_view(c);
+    DemDev dem = dem_view(c);
+    FlagsDev fl = flags_view(c);
+    RC(clear_flags(c));
+    // final costs c_fin = BPR(f)
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cfin.p, nullptr, nullptr, 0, c->flags.p));
+    int J = 0;
+    for (const Instance& I : c->inst) J = std::max(J, I.solved_iters);
+    RC(dalloc(c, c->r_orig, (size_t)std::max<int64_t>(c->P, 1)));
+    RC(dalloc(c, c->r_dest, (size_t)std::max<int64_t>(c->P, 1)));
+    RC(dalloc(c, c->r_w, (size_t)std::max<int64_t>(c->P, 1)));
+    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->done_fx.p), 0, ni));
+    std::vector<std::vector<int32_t>> ro(ni), rd(ni);
+    std::vector<std::vector<int64_t>> rw(ni);
+    std::vector<double> lam(ni);
+    for (int j = 0; j <= J; ++j) {
+        // lambda_j = alpha_j prod_{k>j} (1 - alpha_k), alpha_0 = 1; instances
+        // with fewer iterations sit out
+        bool any = false;
+        for (int i = 0; i < ni; ++i) {
+            const Instance& I = c->inst[i];
+            InstState s;
+            memset(&s, 0, sizeof(s));
+            lam[i] = 0.0;
+            if (I.solved_iters >= j && c->h_inst[i].nleg > 0) {
+                double l = (j == 0) ? 1.0 : I.hist_alpha[j];
+                for (int k = j + 1; k <= I.solved_iters; ++k) l = l * (1.0 - I.hist_alpha[k]);
+                lam[i] = l;
+                s.active = l > 0.0;
+            }
+            any |= s.active != 0;
+            c->h_st[i] = s;
+        }
+        if (!any) continue;
+        HIPCHECK(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(InstState) * ni, hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(c->lambda.p, lam.data(), sizeof(double) * ni, hipMemcpyHostToDevice, c->stream));
+        const float* cj = c->hist_cost.p + (size_t)j * c->M;
+        HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->rcost.p));
+        HIPCHECK(c, launch_sssp(c->stream, net, dem, c->rcost.p, c->labels.p, scr_view(c), c->slots, c->st.p));
+        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->r_count.p), 0, 1));
+        HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
+        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl, 1,
+                                c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p));
+        HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl,
+                                    scr_view(c), (int)std::min<int64_t>(c->slots, std::max<int64_t>(c->Q, 1)), 1,
+                                    c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p, 0,
+                                    nullptr, 0));
+        unsigned long long cnt = 0;
+        HIPCHECK(c, hipMemcpyAsync(&cnt, c->r_count.p, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        if (cnt > (unsigned long long)c->P) return set_err(c, QDTA_EHIP, "residual overflow");
+        std::vector<int32_t> ho(cnt), hd(cnt);
+        std::vector<int64_t> hw(cnt);
+        if (cnt) {
+            HIPCHECK(c, hipMemcpyAsync(ho.data(), c->r_orig.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(c, hipMemcpyAsync(hd.data(), c->r_dest.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(c, hipMemcpyAsync(hw.data(), c->r_w.p, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+        }
+        for (unsigned long long k = 0; k < cnt; ++k) {
+            int qi = hd[k];
+            int i = c->h_dest_inst[qi];
+            ro[i].push_back(ho[k]);
+            rd[i].push_back(c->h_dest_node[qi] - c->h_inst[i].node0);
+            rw[i].push_back(hw[k]);
+        }
+    }
+    std::vector<unsigned long long> done(ni);
+    HIPCHECK(c, hipMemcpyAsync(done.data(), c->done_fx.p, sizeof(unsigned long long) * ni, hipMemcpyDeviceToHost,
+                               c->stream));
+    int h[4];
+    RC(read_flags(c, h));
+    for (int i = 0; i < ni; ++i) {
+        Instance& I = c->inst[i];
+        merge_legs(ro[i], rd[i], rw[i]);
+        I.r_orig.swap(ro[i]);
+        I.r_dest.swap(rd[i]);
+        I.r_w.swap(rw[i]);
+        I.r_done = (int64_t)done[i];
+    }
+    c->solved = false;
+    RC(flag_code(c, h));
+    return h[2] ? QDTA_WABSORB : QDTA_OK;
+}
+
+int qdta_get_residual(qdta_ctx* c, int32_t inst, int64_t* count, int32_t* ho, int32_t* hd, int64_t* hw,
+                      int64_t* done) {
+    if (!c || !count) return QDTA_EARG;
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
+    const Instance& I = c->inst[inst];
+    *count = (int64_t)I.r_orig.size();
+    if (done) *done = I.r_done;
+    if (ho) std::copy(I.r_orig.begin(), I.r_orig.end(), ho);
+    if (hd) std::copy(I.r_dest.begin(), I.r_dest.end(), hd);
+    if (hw) std::copy(I.r_w.begin(), I.r_w.end(), hw);
+    return QDTA_OK;
+}
+
+}  // extern "C"

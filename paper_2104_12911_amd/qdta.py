@@ -1,0 +1,260 @@
+"""ctypes binding of libqdta.so (include/qdta.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device arrays are torch tensors on the context's device (their
+data_ptr() is passed); host arrays are numpy arrays.  The binding fails
+loudly when the library has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqdta.so")
+
+OK, EARG, ECSR, EVAL, EUNREACH, EOVF, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+WABSORB = 1
+RULE_NONE, RULE_CEIL, RULE_FLOOR = 0, 1, 2
+LS_KSECTION, LS_QN, LS_MSA = 0, 1, 2
+STOP_GAP, STOP_OBJ = 0, 1
+FX = 1 << 20
+
+EXPORTS = [
+    "qdta_default_opts", "qdta_strerror", "qdta_last_error", "qdta_create", "qdta_destroy", "qdta_set_stream",
+    "qdta_add_network", "qdta_set_demand", "qdta_layout", "qdta_offsets", "qdta_bpr", "qdta_trees", "qdta_aon",
+    "qdta_get_legs", "qdta_ls_eval", "qdta_line_search", "qdta_fw_update", "qdta_solve", "qdta_get_flows",
+    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual",
+]
+
+
+class Opts(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_int32), ("trunc_rule", C.c_int32), ("ls_mode", C.c_int32),
+                ("K", C.c_int32), ("passes", C.c_int32), ("max_ls", C.c_int32), ("T1", C.c_double),
+                ("T2", C.c_double), ("dx", C.c_double), ("stop_rule", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
+                ("sources_per_block", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("ls_evals", C.c_int32), ("qn_iters", C.c_int32), ("absorb", C.c_int32),
+                ("stopped_by", C.c_int32), ("status", C.c_int32), ("gap", C.c_double), ("objective", C.c_double),
+                ("last_alpha", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LayoutInfo(C.Structure):
+    _fields_ = [("n_instances", C.c_int32), ("total_nodes", C.c_int64), ("total_links", C.c_int64),
+                ("total_legs", C.c_int64), ("total_dests", C.c_int64)]
+
+
+class QdtaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qdta error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run paper_2104_12911_amd/build.py (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.qdta_default_opts.argtypes = [vp]
+        L.qdta_default_opts.restype = None
+        L.qdta_strerror.argtypes = [C.c_int]
+        L.qdta_strerror.restype = C.c_char_p
+        L.qdta_last_error.argtypes = [vp]
+        L.qdta_last_error.restype = C.c_char_p
+        L.qdta_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+        L.qdta_destroy.argtypes = [vp]
+        L.qdta_set_stream.argtypes = [vp, vp]
+        L.qdta_add_network.argtypes = [vp, i32, i32, vp, vp, vp, vp, C.POINTER(i32)]
+        L.qdta_set_demand.argtypes = [vp, i32, i32, vp, vp, vp, dbl]
+        L.qdta_layout.argtypes = [vp, vp]
+        L.qdta_offsets.argtypes = [vp, vp, vp, vp, vp]
+        L.qdta_bpr.argtypes = [vp, vp, vp, vp]
+        L.qdta_trees.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+        L.qdta_aon.argtypes = [vp, vp, vp, vp, vp]
+        L.qdta_get_legs.argtypes = [vp, vp, vp, vp]
+        L.qdta_ls_eval.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+        L.qdta_line_search.argtypes = [vp, vp, vp, vp, i32, vp]
+        L.qdta_fw_update.argtypes = [vp, vp, vp, vp]
+        L.qdta_solve.argtypes = [vp, vp, vp]
+        L.qdta_get_flows.argtypes = [vp, vp]
+        L.qdta_get_costs.argtypes = [vp, vp, vp]
+        L.qdta_advance_interval.argtypes = [vp, vp]
+        L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64)]
+        for name in EXPORTS:
+            if name not in ("qdta_default_opts", "qdta_strerror", "qdta_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().qdta_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    """Pointer of a numpy array (host) or torch tensor (device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())
+
+
+def _check_tensor(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{name}: need contiguous {dtype} with >= {numel} elements")
+
+
+class Context:
+    """One library context: a set of network instances, their demand and the
+    Frank-Wolfe state, on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = lib().qdta_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise QdtaError(rc, lib().qdta_strerror(rc).decode())
+        self._h = h
+        self.n_inst = 0
+        self._nets = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qdta_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _rc(self, rc, allow=(OK,)):
+        if rc in allow:
+            return rc
+        if rc > 0:
+            return rc
+        raise QdtaError(rc, lib().qdta_last_error(self._h).decode() or lib().qdta_strerror(rc).decode())
+
+    # --- setup (host arrays) ------------------------------------------------
+    def add_network(self, n, row_ptr, col, fftt, cap) -> int:
+        rp, cl = _np(row_ptr, np.int32), _np(col, np.int32)
+        ff, cp = _np(fftt, np.float32), _np(cap, np.float32)
+        out = C.c_int32()
+        self._rc(lib().qdta_add_network(self._h, int(n), int(cl.shape[0]), _ptr(rp), _ptr(cl), _ptr(ff), _ptr(cp),
+                                        C.byref(out)))
+        self.n_inst += 1
+        self._nets.append((int(n), int(cl.shape[0])))
+        return out.value
+
+    def add(self, net) -> int:
+        return self.add_network(net.n, net.row_ptr, net.col, net.fftt, net.cap)
+
+    def set_demand(self, inst, orig, dest, trips, dt_s):
+        o, d, t = _np(orig, np.int32), _np(dest, np.int32), _np(trips, np.float64)
+        self._rc(lib().qdta_set_demand(self._h, int(inst), int(o.shape[0]), _ptr(o), _ptr(d), _ptr(t), float(dt_s)))
+
+    def layout(self) -> LayoutInfo:
+        li = LayoutInfo()
+        self._rc(lib().qdta_layout(self._h, C.byref(li)))
+        return li
+
+    def offsets(self):
+        k = self.n_inst + 1
+        arrs = [np.zeros(k, np.int64) for _ in range(4)]
+        self._rc(lib().qdta_offsets(self._h, *[_ptr(a) for a in arrs]))
+        return dict(zip(["node", "link", "leg", "dest"], arrs))
+
+    def legs(self):
+        P = self.layout().total_legs
+        o, d, w = np.zeros(P, np.int32), np.zeros(P, np.int32), np.zeros(P, np.int64)
+        self._rc(lib().qdta_get_legs(self._h, _ptr(o), _ptr(d), _ptr(w)))
+        return o, d, w
+
+    # --- hot-path pieces (device tensors) ------------------------------------
+    def bpr(self, opts, f_fx, cost):
+        self._rc(lib().qdta_bpr(self._h, C.byref(opts), _ptr(f_fx), _ptr(cost)))
+
+    def trees(self, opts, inst, cost, dest, dist, succ):
+        return self._rc(lib().qdta_trees(self._h, C.byref(opts), int(inst), _ptr(cost), int(dest.numel()), _ptr(dest),
+                                         _ptr(dist), _ptr(succ)), allow=(OK, WABSORB))
+
+    def aon(self, opts, cost, y_fx, stop=None):
+        return self._rc(lib().qdta_aon(self._h, C.byref(opts), _ptr(cost), _ptr(y_fx), _ptr(stop)),
+                        allow=(OK, WABSORB))
+
+    def ls_eval(self, opts, f_fx, y_fx, alphas, sums):
+        K = alphas.shape[-1]
+        self._rc(lib().qdta_ls_eval(self._h, C.byref(opts), _ptr(f_fx), _ptr(y_fx), int(K), _ptr(alphas), _ptr(sums)))
+
+    def line_search(self, opts, f_fx, y_fx, j, alpha_out):
+        self._rc(lib().qdta_line_search(self._h, C.byref(opts), _ptr(f_fx), _ptr(y_fx), int(j), _ptr(alpha_out)))
+
+    def fw_update(self, f_fx, y_fx, alpha):
+        self._rc(lib().qdta_fw_update(self._h, _ptr(f_fx), _ptr(y_fx), _ptr(alpha)))
+
+    def solve(self, opts):
+        st = (Stats * max(self.n_inst, 1))()
+        rc = self._rc(lib().qdta_solve(self._h, C.byref(opts), st), allow=(OK, WABSORB))
+        return [st[i].as_dict() for i in range(self.n_inst)], rc
+
+    def get_flows(self, f_fx):
+        self._rc(lib().qdta_get_flows(self._h, _ptr(f_fx)))
+
+    def get_costs(self, opts, cost):
+        self._rc(lib().qdta_get_costs(self._h, C.byref(opts), _ptr(cost)))
+
+    def advance_interval(self, opts):
+        return self._rc(lib().qdta_advance_interval(self._h, C.byref(opts)), allow=(OK, WABSORB))
+
+    def residual(self, inst):
+        cnt, done = C.c_int64(), C.c_int64()
+        self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), None, None, None, C.byref(done)))
+        k = cnt.value
+        o, d, w = np.zeros(k, np.int32), np.zeros(k, np.int32), np.zeros(k, np.int64)
+        self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), _ptr(o), _ptr(d), _ptr(w), C.byref(done)))
+        return o, d, w, done.value
+
+
+def kappa(dt_s: float) -> float:
+    return 3600.0 / dt_s if math.isfinite(dt_s) else 1.0
