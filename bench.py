@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the QDTA hot path on one MI355X.
+
+One step = one Frank-Wolfe iteration of the link-flow form (Alg. 6): BPR link
+costs, the all-or-nothing assignment (destination-rooted shortest-path trees,
+truncation, loading), the relative-gap test, the K-section line search on the
+Beckmann objective and the flow update -- i.e. one AON plus everything around
+it.  No stop test ends the run early, so every timed step does the
+whole iteration (a fixed iteration count disables every stop test).  Default workload: the 08:00 interval of the Bay-Area-shaped
+synthetic network (550k nodes, 1.0M links, 5,000 zones).
+
+Prints one JSON line (rank 0, N = 1).  The SSSP kernel's duration comes from
+HIP events the library records on its own stream; its roofline uses the
+algorithmic bytes per tree 8n + 8m (plus the topology once per launch).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AON assignments/s + GTEPS at 1M links; time to rel. gap 1e-4 vs plain form"
+HBM_PEAK_GBS = 8000.0
+FX = 1 << 20
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import synth
+    if name == "config3":
+        return synth.config3()
+    if name == "config2":
+        return synth.config2()
+    if name == "config1":
+        return synth.config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def sssp_bytes_per_tree(n, m):
+    """Algorithmic HBM bytes of one destination tree: label init (4n) and
+    one label read per settled node (4n), one 4-byte label read and write per
+    relaxed in-link (8m).  The reverse topology (source and cost per link,
+    offsets per node: 8m + 4n bytes) is shared by every tree of the pass and
+    is counted once per launch."""
+    return 8.0 * n + 8.0 * m
+
+
+def traffic_entry(kernel_src_hash):
+    """HBM bytes per SSSP launch from the rocprofv3 PMC runs, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "sssp_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256") != kernel_src_hash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, target_s, nthreads):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    one AON over the legs of the first S destinations (S sized to about
+    `target_s` seconds), one K-section line search over a link sample, BPR
+    over all links; each extrapolated linearly to the full step."""
+    import oracle
+    net, dem = w.net, w.demand
+    d_fx = np.rint(dem.trips * FX).astype(np.int64)
+    dests = np.unique(dem.dest)
+    Q = dests.size
+    cost = net.fftt.copy()
+
+    def aon_sample(S):
+        sel = np.isin(dem.dest, dests[:S])
+        t0 = time.perf_counter()
+        oracle.aon(net, cost, dem.orig[sel], dem.dest[sel], d_fx[sel], dem.dt_s, oracle.RULE_CEIL, nthreads=nthreads)
+        return time.perf_counter() - t0
+
+    S = max(2, min(Q, nthreads))
+    t = aon_sample(S)
+    while t < 0.25 * target_s and S < Q:
+        S = min(Q, int(S * max(2.0, 0.3 * target_s / max(t, 1e-3))))
+        t = aon_sample(S)
+    t_aon = t * Q / S
+    # line search: 3 passes x 32 step sizes on a link sample
+    rng = np.random.default_rng(0)
+    mL = min(net.m, 200_000)
+    f = rng.integers(0, 300 * FX, mL).astype(np.int64)
+    y = rng.integers(0, 600 * FX, mL).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.line_search(f, y, net.fftt[:mL], net.cap[:mL], 0.15, 4, dem.dt_s, 1)
+    t_ls = (time.perf_counter() - t0) * net.m / mL
+    t0 = time.perf_counter()
+    oracle.bpr(np.zeros(net.m, np.int64), net.fftt, net.cap, 0.15, 4, dem.dt_s)
+    t_bpr = time.perf_counter() - t0
+    step = t_aon + t_ls + 2 * t_bpr
+    return {"value": 1.0 / step, "unit": "AON/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"AON over the legs of {S} of {Q} destinations ({t:.1f} s, {nthreads} threads), "
+                      f"K-section line search over {mL} of {net.m} links, BPR over all links; "
+                      f"extrapolated linearly to one full step ({step:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
+    ap.add_argument("--delta-scale", type=float, default=0.0, help="bucket width / mean link cost (0: library default)")
+    ap.add_argument("--waves-per-cu", type=int, default=0, help="trees in flight per CU (0: library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (MiB) once, for counter calibration")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_12911_amd import qdta
+
+    log(f"generating {args.workload}")
+    w = workload(args.workload)
+    net, dem = w.net, w.demand
+    log(f"network n={net.n} m={net.m}; legs={dem.P} trips={dem.total():.0f} dt={dem.dt_s}")
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = qdta.Context(0, stream)
+    ctx.add(net)
+    ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
+    opts = qdta.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=1 << 30, delta_scale=args.delta_scale,
+                             waves_per_cu=args.waves_per_cu)
+    li = ctx.layout()
+    Q = int(li.total_dests)
+    log(f"layout: destinations={Q} legs={li.total_legs}; initial AON")
+    t0 = time.perf_counter()
+    ctx.fw_begin(opts)
+    log(f"initial AON {time.perf_counter() - t0:.3f} s")
+    for i in range(args.warmup):
+        st, live = ctx.fw_step(opts)
+        log(f"warmup {i + 1}/{args.warmup}: gap={st[0]['gap']:.4e} alpha={st[0]['last_alpha']:.4f}")
+    if args.copy_calib_mib:
+        a = torch.empty(args.copy_calib_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gaps = []
+    for i in range(args.steps):
+        st, live = ctx.fw_step(opts)
+        gaps.append(st[0]["gap"])
+        log(f"step {i + 1}/{args.steps}: gap={st[0]['gap']:.4e} alpha={st[0]['last_alpha']:.4f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+
+    ms_step = elapsed / args.steps * 1e3
+    sssp_ms, sssp_n = prof["sssp"]
+    sssp_avg_s = sssp_ms / max(sssp_n, 1) / 1e3
+    bytes_launch = Q * sssp_bytes_per_tree(net.n, net.m) + 8.0 * net.m + 4.0 * net.n
+    achieved = bytes_launch / sssp_avg_s / 1e9
+    src = open(os.path.join(ROOT, "paper_2104_12911_amd", "csrc", "qdta_kernels.hip"), "rb").read()
+    traffic = traffic_entry(hashlib.sha256(src).hexdigest())
+    result = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "AON/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {net.n} nodes, {net.m} links, {Q} destinations, {li.total_legs} legs,"
+                               f" dt {dem.dt_s:g} s", "delta_scale": args.delta_scale or 3.0,
+                   "waves_per_cu": args.waves_per_cu or 16, "line_search": "K-section K=32 x3"},
+        "gteps": Q * net.m / sssp_avg_s / 1e9,
+        "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_sssp",
+                     "kernel_ms": sssp_avg_s * 1e3, "algorithmic_bytes_per_launch": bytes_launch},
+        "gap_last": gaps[-1] if gaps else None,
+    }
+    if not args.no_cpu_baseline:
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+        log(f"cpu baseline: oracle with {nthreads} threads")
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, nthreads)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,8 +88,10 @@ typedef struct {
     int32_t max_iter;      /* FW iteration cap */
     int32_t fixed_iters;   /* > 0: exactly this many updates, stop rule ignored */
     int32_t keep_history;  /* record (alpha_j, c_j) per iteration; needed by qdta_advance_interval */
-    int32_t sources_per_block; /* destinations per shortest-path batch: 0 auto, else 4, 8, 16 or 32 */
-    int32_t reserved[6];
+    int32_t waves_per_cu;  /* shortest-path trees in flight per compute unit: 0 auto (16), else 1..32 */
+    double delta_scale;    /* delta-stepping bucket width as a multiple of the instance's mean link
+                              cost: 0 auto (3.0); any value > 0 gives the same trees, only the speed changes */
+    int32_t reserved[4];
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */
@@ -98,7 +100,8 @@ typedef struct {
     int32_t ls_evals;      /* line-search passes over the links */
     int32_t qn_iters;      /* quasi-Newton iterations (QDTA_LS_QN) */
     int32_t absorb;        /* 1 when the FP32-absorption tie fallback was used */
-    int32_t stopped_by;    /* 0 iteration cap / fixed count, 1 gap, 2 objective change */
+    int32_t stopped_by;    /* 0 iteration cap / fixed count, 1 gap, 2 objective change,
+                              3 stalled: the line search returned alpha* = 0, so f cannot change */
     int32_t status;        /* QDTA_OK or an error code for this instance */
     double gap;            /* relative gap at the returned iterate */
     double objective;      /* Beckmann objective at the returned iterate (veh s) */
@@ -212,6 +215,15 @@ int qdta_fw_update(qdta_ctx *ctx, int64_t *f_fx, const int64_t *y_fx, const doub
  * Synchronises once per FW iteration.  Returns the worst per-instance code. */
 int qdta_solve(qdta_ctx *ctx, const qdta_opts *opts, qdta_stats *host_stats);
 
+/* The same Frank-Wolfe loop one iteration at a time.  qdta_fw_begin resets
+ * the state and runs the initial free-flow AON; each qdta_fw_step runs one
+ * iteration (BPR, AON, stop test, line search, update) for every instance
+ * whose stop rule has not fired, fills host_stats[n_instances] (host; may be
+ * NULL) and sets *live_out (host) to 0 once every instance has stopped.
+ * Synchronises once per call. */
+int qdta_fw_begin(qdta_ctx *ctx, const qdta_opts *opts);
+int qdta_fw_step(qdta_ctx *ctx, const qdta_opts *opts, qdta_stats *host_stats, int32_t *live_out);
+
 /* Copies of the solved link flows (int64 fx) and costs BPR(f) (float) over
  * all links, device outputs; either may be NULL. */
 int qdta_get_flows(qdta_ctx *ctx, int64_t *f_fx);
@@ -228,6 +240,20 @@ int qdta_advance_interval(qdta_ctx *ctx, const qdta_opts *opts);
  * NULL arrays to get *count; arrays then hold at least *count entries. */
 int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host_orig,
                       int32_t *host_dest, int64_t *host_w_fx, int64_t *host_done_fx);
+
+/* Per-phase timers: HIP events recorded on the context's stream around each
+ * phase of the Frank-Wolfe iteration; durations are added at the iteration's
+ * synchronisation.  Phases: 0 BPR costs, 1 shortest-path trees, 2 loading
+ * walk (with the tie fallback), 3 gap sums and stop test, 4 line search,
+ * 5 flow update.  qdta_profile_enable(ctx, 1) resets and starts the timers,
+ * 0 stops them; qdta_profile_read copies the totals (host output). */
+typedef struct {
+    double ms[8];        /* summed duration per phase, milliseconds */
+    int64_t count[8];    /* timed occurrences per phase */
+} qdta_profile;
+
+int qdta_profile_enable(qdta_ctx *ctx, int32_t on);
+int qdta_profile_read(qdta_ctx *ctx, qdta_profile *out);
 
 #ifdef __cplusplus
 }

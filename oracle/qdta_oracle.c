@@ -590,7 +590,7 @@ typedef struct {
     int32_t ls_evals;    /* line-search passes over the links */
     int32_t qn_iters;
     int32_t absorb;      /* absorption fallback used */
-    int32_t stopped_by;  /* 0 cap/fixed, 1 gap, 2 objective */
+    int32_t stopped_by;  /* 0 cap/fixed, 1 gap, 2 objective, 3 stalled (alpha* = 0) */
     double gap;          /* relative gap at the returned iterate */
     double objective;    /* Beckmann objective at the returned iterate (veh s) */
     double last_alpha;
@@ -649,6 +649,12 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
             double b1 = q2d(objective(m, fn, c0, cap, o->alpha_b, o->beta, kappa, &bad));
             free(fn);
             if (fabs((b0 - b1) / b0) < o->tol) { st->stopped_by = 2; break; }
+        }
+        if (o->fixed_iters <= 0 && li.alpha == 0.0) {
+            /* alpha* = 0 leaves f unchanged and the next iteration would repeat
+             * this one: under truncation the AON direction need not descend */
+            st->stopped_by = 3;
+            break;
         }
         orc_fw_update(m, f, y, li.alpha);
         st->iters = j;

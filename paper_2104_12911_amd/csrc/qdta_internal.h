@@ -28,7 +28,7 @@ struct InstState {
     int32_t converged;       // stop rule fired or cap reached: f is final
     int32_t ls_done;         // line search finished for this iteration
     int32_t iter;            // FW iteration j being computed (1-based)
-    int32_t stopped_by;      // 0 cap/fixed, 1 gap, 2 objective change
+    int32_t stopped_by;      // 0 cap/fixed, 1 gap, 2 objective change, 3 stalled (alpha* = 0)
     int32_t ls_evals;        // passes over the links (accumulated)
     int32_t qn_iters;        // quasi-Newton iterations (accumulated)
     int32_t iters;           // updates applied
@@ -64,24 +64,22 @@ struct NetDev {
 struct DemDev {
     const int32_t* dest_node;// [Q] global node of each destination
     const int32_t* dest_inst;// [Q]
-    const int64_t* dest_lab; // [Q] offset (floats) of slot 0 node 0 of its tree in the label array
+    const int64_t* dest_lab; // [Q] offset (floats) of the tree's label of node 0
     const int32_t* qptr;     // [Q+1] legs of each destination (global leg index)
     const int32_t* leg_orig; // [P] global origin node
     const int64_t* leg_dfx;  // [P]
     const int32_t* leg_q;    // [P] global destination index
-    const int32_t* b_inst;   // [B] batches: instance
-    const int32_t* b_q;      // [B] first destination
-    const int32_t* b_nq;     // [B] destinations in the batch (<= sources per block)
-    const int64_t* b_lab;    // [B] label-array offset of the batch
-    int32_t Q, P, B, sb;
+    int32_t Q, P, sb;        // sb: stride between a tree's labels of consecutive nodes
 };
 
+// Per-wavefront scratch of the shortest-path kernel (also the workgroup
+// scratch of the tie fallback, slot = workgroup there).
 struct Scratch {
-    int32_t* queues;         // [slots][2][nmax]
-    uint32_t* dirty;         // [slots][nmax]
-    int32_t* stamp;          // [slots][nmax] last round a node was queued for
-    int32_t nmax;
-    int32_t* work;           // batch work counter
+    int32_t* nearq;          // [slots][nmax] near queue (ring of n + 1)
+    int32_t* farq;           // [slots][nmax] far queue of (node, label) pairs (2 ints each)
+    uint32_t* bits;          // [slots][nwords] queued-node bitmap
+    int64_t nmax, nwords;    // nmax >= largest n + 1
+    int32_t* work;           // tree work counter
 };
 
 struct FlagsDev {
@@ -117,6 +115,7 @@ hipError_t launch_ls_eval(hipStream_t s, const NetDev& net, const int64_t* f, co
 hipError_t launch_ls_decide(hipStream_t s, int ninst, InstState* st, double* alphas, int K, int ls_mode,
                             int passes, int max_ls, double T1, double T2, double dx, long long* ls_acc);
 
+hipError_t launch_stall_check(hipStream_t s, int ninst, InstState* st, int fixed_iters);
 hipError_t launch_ls_export(hipStream_t s, int ninst, const long long* ls_acc, int K, int64_t* sums);
 
 hipError_t launch_obj_pair(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
@@ -133,8 +132,9 @@ hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, doub
 hipError_t launch_after_update(hipStream_t s, int ninst, InstState* st);
 hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, float* rcost);
 
-hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* rcost, float* labels,
-                       const Scratch& scr, int slots, const InstState* st);
+hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const float* rcost,
+                       float* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
+                       float* delta_inst);
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,

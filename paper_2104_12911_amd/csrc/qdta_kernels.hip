@@ -2,8 +2,8 @@
 //
 // One Frank-Wolfe iteration of the link-flow form (Alg. 6, section 5.1):
 //   k_bpr        link costs by the BPR curve (Eq. 1)
-//   k_sssp<SB>   destination-rooted FP32 shortest-path trees, SB trees per
-//                workgroup (Get_shortest_path of Alg. 3 / Alg. 7)
+//   k_sssp_ds    destination-rooted FP32 shortest-path trees, one wavefront
+//                per tree, delta-stepping (Get_shortest_path of Alg. 3 / Alg. 7)
 //   k_walk       route truncation (Eq. 2) and loading along the successor
 //                links (Eq. 5, Alg. 3), int64 fixed-point atomics
 //   k_gap_sums   exact sums for the relative gap / stop test
@@ -417,6 +417,21 @@ hipError_t launch_ls_decide(hipStream_t s, int ninst, InstState* st, double* alp
     return hipGetLastError();
 }
 
+// A zero step leaves f unchanged, so the next iteration would repeat this
+// one: stop there unless a fixed iteration count was asked for.
+__global__ void k_stall_check(int ninst, InstState* st, int fixed_iters) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || fixed_iters > 0) return;
+    InstState& S = st[i];
+    if (!S.active || S.converged) return;
+    if (S.alpha == 0.0) { S.converged = 1; S.stopped_by = 3; }
+}
+
+hipError_t launch_stall_check(hipStream_t s, int ninst, InstState* st, int fixed_iters) {
+    hipLaunchKernelGGL(k_stall_check, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, st, fixed_iters);
+    return hipGetLastError();
+}
+
 __global__ void k_ls_export(int ninst, const long long* ls_acc, int K, int64_t* sums) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ninst * K * 2) return;
@@ -556,131 +571,209 @@ hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, doub
 }
 
 // ---------------------------------------------------------------------------
-// A2: shortest-path trees, SB destinations per workgroup
+// A2: shortest-path trees, one wavefront per destination (delta-stepping)
 // ---------------------------------------------------------------------------
-// Persistent workgroups pull batches of up to SB destinations from a work
-// counter.  Labels of a batch are node-major, D[v * SB + t] for tree t, so
-// the SB lanes of a group read and write one contiguous row.  Each round
-// processes the current queue of nodes whose label improved in some tree
-// (dirty[v] holds those trees as a bit mask), relaxing the in-links of each
-// such node on the reverse graph: D[u] = min(D[u], fl32(D[w] + c)) by an
-// integer atomicMin on the FP32 bit pattern (labels are non-negative, so bit
-// order is value order).  An improved node enters the queue of round r+1
-// once: stamp[v] records the last round it was queued for (atomicMax), so a
-// queue never holds more than n entries.  Pushes are aggregated per
-// wavefront with a ballot and a prefix count.  The fixed point reached is the
-// least one, the FP32 min-plus distance, whatever the processing order.
-template <int SB>
-__global__ __launch_bounds__(kWG) void k_sssp(NetDev net, DemDev dem, const float* __restrict__ rcost,
-                                              float* labels, Scratch scr, const InstState* st) {
-    constexpr int GW = 64 / SB;           // groups per wavefront
-    constexpr int NG = kWG / SB;          // groups per workgroup
-    constexpr unsigned long long GMASK = (SB == 64) ? ~0ull : ((1ull << SB) - 1);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int slot = lane % SB;
-    const int gw = lane / SB;
-    const int gid = (tid >> 6) * GW + gw;
-    __shared__ int s_batch;
-    __shared__ int s_cnt[2];
-    int32_t* qbase = scr.queues + (int64_t)blockIdx.x * 2 * scr.nmax;
-    uint32_t* dirty = scr.dirty + (int64_t)blockIdx.x * scr.nmax;
-    int32_t* stamp = scr.stamp + (int64_t)blockIdx.x * scr.nmax;
+__device__ __forceinline__ unsigned long long lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ float wave_min(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Each wavefront owns one destination tree at a time (a work counter hands
+// out trees) and runs delta-stepping on the reverse graph: D[q] = 0, and the
+// nodes taken from the near queue relax their in-links (u, w):
+// D[u] = min(D[u], fl32(D[w] + c)) by an integer atomicMin on the FP32 bit
+// pattern (labels are non-negative, so bit order is value order).
+//   - Up to 64 nodes are popped per step (FIFO ring); their in-links are
+//     flattened across the lanes with a prefix sum of the in-degrees, so each
+//     step relaxes 64 links whatever the degree mix.
+//   - An improved node is queued once (a per-tree bitmap marks queued nodes):
+//     in the near queue when its label is below the bucket bound thr, else in
+//     the far queue together with that label.
+//   - When the near queue empties, thr moves to delta above the smallest far
+//     label (kept as a running minimum) and one pass moves the far entries
+//     below thr to the near queue.
+// Queue counters are wave-uniform values updated from ballots, so a tree
+// needs no barrier and no shared-memory atomics.  Whatever the order, the
+// labels reach the least fixed point of D(v) = min_e fl32(D(head e) + c_e),
+// the FP32 min-plus distance.
+__global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const float* __restrict__ rcost,
+                                                 float* labels, Scratch scr, const InstState* st,
+                                                 const float* __restrict__ delta_inst) {
+    __shared__ int s_pre[kWG / 64][65];
+    __shared__ float s_dw[kWG / 64][64];
+    __shared__ int s_e0[kWG / 64][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + wv;
+    const unsigned long long below = lanes_below(lane);
+    int32_t* nearq = scr.nearq + slot * scr.nmax;
+    uint2* farq = reinterpret_cast<uint2*>(scr.farq) + slot * scr.nmax;
+    uint32_t* bits = scr.bits + slot * scr.nwords;
+    int* pre = s_pre[wv];
+    float* sdw = s_dw[wv];
+    int* se0 = s_e0[wv];
 
     for (;;) {
-        if (tid == 0) s_batch = atomicAdd(scr.work, 1);
-        __syncthreads();
-        const int b = s_batch;
-        if (b >= dem.B) break;
-        const int inst = dem.b_inst[b];
-        if (!inst_live(st, inst)) { __syncthreads(); continue; }
+        int t = 0;
+        if (lane == 0) t = atomicAdd(scr.work, 1);
+        t = __shfl(t, 0);
+        if (t >= dem.Q) break;
+        const int inst = dem.dest_inst[t];
+        if (!inst_live(st, inst)) continue;
         const InstDev I = net.inst[inst];
         const int n = I.n, node0 = I.node0;
-        uint32_t* D = reinterpret_cast<uint32_t*>(labels + dem.b_lab[b]);
-        const int nq = dem.b_nq[b];
-        const int q_first = dem.b_q[b];
-
-        for (int64_t i = tid; i < (int64_t)n * SB; i += kWG) D[i] = kInfBits;
-        for (int i = tid; i < n; i += kWG) { dirty[i] = 0u; stamp[i] = 0; }
-        if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
-        __syncthreads();
-        if (tid < nq) {
-            int r = dem.dest_node[q_first + tid] - node0;
-            D[(int64_t)r * SB + tid] = 0u;
-            atomicOr(&dirty[r], 1u << tid);
-            if (atomicMax(&stamp[r], 1) < 1) { int pos = atomicAdd(&s_cnt[0], 1); qbase[pos] = r; }
+        const int* __restrict__ rptr = net.rptr + node0;
+        uint32_t* D = reinterpret_cast<uint32_t*>(labels + dem.dest_lab[t]);
+        const int root = dem.dest_node[t] - node0;
+        const float delta = delta_inst[inst];
+        const int nw = (n + 31) >> 5;
+        for (int i = lane; i < n; i += 64) D[i] = kInfBits;
+        for (int i = lane; i < nw; i += 64) bits[i] = 0u;
+        __threadfence_block();
+        if (lane == 0) {
+            D[root] = 0u;
+            bits[root >> 5] = 1u << (root & 31);
+            nearq[0] = root;
         }
-        __syncthreads();
-
-        int cur = 0;
-        for (int round = 1;; ++round) {
-            const int cnt = s_cnt[cur];
-            if (cnt == 0) break;
-            const int32_t* qc = qbase + (int64_t)cur * scr.nmax;
-            int32_t* qn = qbase + (int64_t)(cur ^ 1) * scr.nmax;
-            for (int base = 0; base < cnt; base += NG) {
-                const int i = base + gid;
-                const bool valid = i < cnt;
-                const int w = valid ? qc[i] : 0;
-                unsigned mask = 0u;
-                if (valid && slot == 0) mask = atomicExch(&dirty[w], 0u);
-                mask = __shfl(mask, lane - slot);
-                const bool act = (mask >> slot) & 1u;
+        __threadfence_block();
+        const int R = n + 1;                      // near ring capacity: at most n nodes are queued
+        int head = 0, ncnt = 1;                   // near ring: ncnt entries from head, modulo R
+        int fcnt = 0;
+        float thr = delta;
+        float fmin = __uint_as_float(kInfBits);   // smallest label pushed to far
+        for (;;) {
+            while (ncnt > 0) {
+                const int k = ncnt < 64 ? ncnt : 64;
+                int w = 0, deg = 0;
                 float dw = 0.0f;
-                if (act) dw = __uint_as_float(ld_coherent(&D[(int64_t)w * SB + slot]));
-                int e0 = 0, e1 = 0;
-                if (mask) { e0 = net.rptr[node0 + w]; e1 = net.rptr[node0 + w + 1]; }
-                for (int e = e0; e < e1; ++e) {
-                    const int v = net.rsrc[e] - node0;
-                    const float c = rcost[e];
-                    bool imp = false;
-                    if (act) {
-                        const uint32_t cb = __float_as_uint(dw + c);
-                        uint32_t* dv = &D[(int64_t)v * SB + slot];
-                        if (cb < *dv) {
-                            uint32_t old = atomicMin(dv, cb);
-                            imp = cb < old;
+                if (lane < k) {
+                    int pos = head + lane;
+                    if (pos >= R) pos -= R;
+                    w = nearq[pos];
+                    atomicAnd(&bits[w >> 5], ~(1u << (w & 31)));
+                    dw = __uint_as_float(ld_coherent(&D[w]));
+                    const int e0 = rptr[w];
+                    deg = rptr[w + 1] - e0;
+                    se0[lane] = e0;
+                    sdw[lane] = dw;
+                }
+                head += k;
+                if (head >= R) head -= R;
+                ncnt -= k;
+                // inclusive prefix sum of in-degrees across the wave
+                int incl = deg;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int x = __shfl_up(incl, o);
+                    if (lane >= o) incl += x;
+                }
+                pre[lane + 1] = incl;
+                if (lane == 0) pre[0] = 0;
+                const int total = __shfl(incl, 63);
+                __builtin_amdgcn_wave_barrier();
+                for (int g0 = 0; g0 < total; g0 += 64) {
+                    const int g = g0 + lane;
+                    bool pn = false, pf = false;
+                    int v = 0;
+                    float cand = 0.0f;
+                    if (g < total) {
+                        // owner: the lane whose [pre, pre + deg) holds g
+                        int lo = 0, hi = k;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pre[mid] <= g) lo = mid; else hi = mid;
+                        }
+                        const int e = se0[lo] + (g - pre[lo]);
+                        v = net.rsrc[e] - node0;
+                        cand = sdw[lo] + rcost[e];
+                        const uint32_t cb = __float_as_uint(cand);
+                        if (cb < D[v]) {
+                            atomicMin(&D[v], cb);
+                            const uint32_t mbit = 1u << (v & 31);
+                            if (!(atomicOr(&bits[v >> 5], mbit) & mbit)) {
+                                pn = cand < thr;
+                                pf = !pn;
+                            }
                         }
                     }
-                    const unsigned long long bal = __ballot(imp);
-                    const unsigned bits = (unsigned)((bal >> (gw * SB)) & GMASK);
-                    bool push = false;
-                    if (slot == 0 && bits) {
-                        atomicOr(&dirty[v], bits);
-                        push = atomicMax(&stamp[v], round + 1) < round + 1;
+                    const unsigned long long bn = __ballot(pn), bf = __ballot(pf);
+                    if (pn) {
+                        int pos = head + ncnt + __popcll(bn & below);
+                        if (pos >= R) pos -= R;
+                        nearq[pos] = v;
                     }
-                    const unsigned long long pb = __ballot(push);
-                    if (pb) {
-                        const int leader = __ffsll((long long)pb) - 1;
-                        int pos = 0;
-                        if (lane == leader) pos = atomicAdd(&s_cnt[cur ^ 1], __popcll(pb));
-                        pos = __shfl(pos, leader);
-                        if (push) qn[pos + __popcll(pb & ((1ull << lane) - 1ull))] = v;
-                    }
+                    if (pf) farq[fcnt + __popcll(bf & below)] = make_uint2((uint32_t)v, __float_as_uint(cand));
+                    ncnt += __popcll(bn);
+                    fcnt += __popcll(bf);
+                    fmin = fminf(fmin, wave_min(pf ? cand : __uint_as_float(kInfBits)));
                 }
+                __threadfence_block();
             }
-            __syncthreads();
-            if (tid == 0) s_cnt[cur] = 0;
-            cur ^= 1;
-            __syncthreads();
+            if (fcnt == 0) break;
+            // next bucket: delta above the smallest far label
+            thr = fmaxf(thr, fmin) + delta;
+            // FP32 absorption can make fmin + delta == fmin: always admit the minimum
+            if (!(thr > fmin)) thr = __uint_as_float(__float_as_uint(fmin) + 1u);
+            int keep = 0;
+            float kmin = __uint_as_float(kInfBits);
+            for (int i0 = 0; i0 < fcnt; i0 += 64) {
+                const int i = i0 + lane;
+                const bool h = i < fcnt;
+                const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                const float dv = __uint_as_float(ent.y);
+                const bool ton = h && dv < thr;
+                const bool tok = h && !ton;
+                const unsigned long long bn = __ballot(ton), bk = __ballot(tok);
+                if (ton) {
+                    int pos = head + ncnt + __popcll(bn & below);
+                    if (pos >= R) pos -= R;
+                    nearq[pos] = (int)ent.x;
+                }
+                if (tok) farq[keep + __popcll(bk & below)] = ent;
+                ncnt += __popcll(bn);
+                keep += __popcll(bk);
+                kmin = fminf(kmin, tok ? dv : __uint_as_float(kInfBits));
+            }
+            fcnt = keep;
+            fmin = wave_min(kmin);
+            __threadfence_block();
         }
-        __syncthreads();
     }
 }
 
-hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* rcost, float* labels,
-                       const Scratch& scr, int slots, const InstState* st) {
-    if (dem.B == 0) return hipSuccess;
+// Bucket width per instance: delta = scale * (mean link cost of the instance).
+__global__ __launch_bounds__(kWG) void k_delta(NetDev net, const float* __restrict__ cost, double scale,
+                                               float* delta_inst) {
+    __shared__ double part[kWG];
+    const int inst = blockIdx.x;
+    const InstDev I = net.inst[inst];
+    double s = 0.0;
+    for (int a = I.link0 + threadIdx.x; a < I.link0 + I.m; a += kWG) s += (double)cost[a];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kWG / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double d = I.m > 0 ? scale * part[0] / (double)I.m : 1.0;
+        if (!(d > 0.0) || !(d < 3.0e38)) d = 3.0e38;
+        delta_inst[inst] = (float)d;
+    }
+}
+
+hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const float* rcost,
+                       float* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
+                       float* delta_inst) {
+    if (dem.Q == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_delta, dim3(net.ninst), dim3(kWG), 0, s, net, cost, delta_scale, delta_inst);
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
-    dim3 g(slots), blk(kWG);
-    switch (dem.sb) {
-        case 4: hipLaunchKernelGGL(k_sssp<4>, g, blk, 0, s, net, dem, rcost, labels, scr, st); break;
-        case 8: hipLaunchKernelGGL(k_sssp<8>, g, blk, 0, s, net, dem, rcost, labels, scr, st); break;
-        case 16: hipLaunchKernelGGL(k_sssp<16>, g, blk, 0, s, net, dem, rcost, labels, scr, st); break;
-        case 32: hipLaunchKernelGGL(k_sssp<32>, g, blk, 0, s, net, dem, rcost, labels, scr, st); break;
-        default: return hipErrorInvalidValue;
-    }
+    const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
+    hipLaunchKernelGGL(k_sssp_ds, dim3(blocks), dim3(kWG), 0, s, net, dem, rcost, labels, scr, st, delta_inst);
     return hipGetLastError();
 }
 
@@ -799,8 +892,8 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                                                   FlagsDev fl, Scratch scr, WalkOut o, int trees_mode,
                                                   int32_t* succ_out, int32_t n_out) {
     __shared__ int s_cnt[2];
-    int32_t* hop = reinterpret_cast<int32_t*>(scr.dirty) + (int64_t)blockIdx.x * scr.nmax;
-    int32_t* qbase = scr.queues + (int64_t)blockIdx.x * 2 * scr.nmax;
+    int32_t* hop = scr.farq + (int64_t)blockIdx.x * scr.nmax;
+    int32_t* qbase = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
     for (int qi = blockIdx.x; qi < dem.Q; qi += gridDim.x) {
         if (!fl.absorb_q[qi]) continue;
         const int inst = dem.dest_inst[qi];
@@ -810,19 +903,18 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
         const float* lab = labels + dem.dest_lab[qi];
         const int sb = dem.sb;
         const int q = dem.dest_node[qi];
+        // breadth-first levels in one FIFO: level L occupies [s_cnt[0], s_cnt[1])
         for (int v = threadIdx.x; v < n; v += kWG) hop[v] = -1;
-        if (threadIdx.x == 0) { s_cnt[0] = 1; s_cnt[1] = 0; }
+        if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 1; }
         __syncthreads();
         if (threadIdx.x == 0) { hop[q - node0] = 0; qbase[0] = q - node0; }
         __syncthreads();
-        int cur = 0;
         for (int level = 0;; ++level) {
-            const int cnt = s_cnt[cur];
-            if (cnt == 0) break;
-            const int32_t* qc = qbase + (int64_t)cur * scr.nmax;
-            int32_t* qn = qbase + (int64_t)(cur ^ 1) * scr.nmax;
-            for (int i = threadIdx.x; i < cnt; i += kWG) {
-                const int u = qc[i];
+            const int lo = s_cnt[0], hi = s_cnt[1];
+            if (lo == hi) break;
+            __syncthreads();
+            for (int i = lo + threadIdx.x; i < hi; i += kWG) {
+                const int u = qbase[i];
                 const float du = lab[(int64_t)u * sb];
                 for (int e = net.rptr[node0 + u]; e < net.rptr[node0 + u + 1]; ++e) {
                     const int v = net.rsrc[e] - node0;
@@ -830,15 +922,14 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                     const float dv = lab[(int64_t)v * sb];
                     if (dv <= 3.4028234663852886e38f && du + tree_cost[link] == dv) {
                         if (atomicCAS(&hop[v], -1, level + 1) == -1) {
-                            int pos = atomicAdd(&s_cnt[cur ^ 1], 1);
-                            qn[pos] = v;
+                            int pos = atomicAdd(&s_cnt[1], 1);
+                            qbase[pos] = v;
                         }
                     }
                 }
             }
             __syncthreads();
-            if (threadIdx.x == 0) s_cnt[cur] = 0;
-            cur ^= 1;
+            if (threadIdx.x == 0) s_cnt[0] = hi;
             __syncthreads();
         }
         // successor with the hop rule where no strict tight link exists

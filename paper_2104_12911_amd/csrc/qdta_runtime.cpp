@@ -52,7 +52,6 @@ struct qdta_ctx {
     int cus = 256;
     std::vector<Instance> inst;
     bool net_dirty = true, dem_dirty = true;
-    int cur_sb = 0;
     std::vector<void*> allocs;
 
     // network layout
@@ -65,17 +64,18 @@ struct qdta_ctx {
     DBuf<InstDev> d_inst;
 
     // demand layout
-    int64_t Q = 0, P = 0, B = 0, nmax = 0;
-    int slots = 0;
+    int64_t Q = 0, P = 0, nmax = 0;
+    int slots = 0, scr_slots = 0;
+    int64_t scr_nmax = 0;
     size_t label_floats = 0;
-    DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q, b_inst, b_q, b_nq;
-    DBuf<int64_t> dest_lab, leg_dfx, b_lab;
+    DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q;
+    DBuf<int64_t> dest_lab, leg_dfx;
     std::vector<int32_t> h_dest_inst, h_dest_node;
     DBuf<float> labels;
-    DBuf<int32_t> queues;
-    DBuf<uint32_t> dirty;
-    DBuf<int32_t> stamp;
+    DBuf<int32_t> nearq, farq;
+    DBuf<uint32_t> bits;
     DBuf<int32_t> work;
+    DBuf<float> delta_inst;
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
@@ -95,6 +95,14 @@ struct qdta_ctx {
     InstState* h_st = nullptr;    // pinned mirror
     int h_st_n = 0;
     bool solved = false;
+    int fw_j = -1;                // FW iteration of the running solve (-1: none)
+    bool fw_live = false;
+    // per-phase HIP-event timers (qdta_profile_enable)
+    int prof_on = 0;
+    hipEvent_t prof_ev[8][2] = {};
+    int prof_open[8] = {};
+    double prof_ms[8] = {};
+    int64_t prof_n[8] = {};
 };
 
 namespace {
@@ -166,15 +174,16 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
         return false;
     }
     if (o->max_iter < 0 || o->fixed_iters < 0) { set_err(c, QDTA_EARG, "negative iteration count"); return false; }
-    int sb = o->sources_per_block;
-    if (!(sb == 0 || sb == 4 || sb == 8 || sb == 16 || sb == 32)) {
-        set_err(c, QDTA_EARG, "sources_per_block must be 0, 4, 8, 16 or 32");
+    if (o->waves_per_cu < 0 || o->waves_per_cu > 32) { set_err(c, QDTA_EARG, "waves_per_cu must be in 0..32"); return false; }
+    if (!(o->delta_scale >= 0.0) || !std::isfinite(o->delta_scale)) {
+        set_err(c, QDTA_EARG, "delta_scale must be finite and >= 0");
         return false;
     }
     return true;
 }
 
-int choose_sb(const qdta_opts* o) { return o->sources_per_block ? o->sources_per_block : 16; }
+int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 16; }
+double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 3.0; }
 
 // ---------------------------------------------------------------------------
 // network layout: instances concatenated, reverse CSR, link chunks
@@ -267,7 +276,6 @@ int ensure_network(qdta_ctx* c) {
     }
     c->net_dirty = false;
     c->dem_dirty = true;
-    c->cur_sb = 0;
     return QDTA_OK;
 }
 
@@ -291,58 +299,35 @@ NetDev net_view(qdta_ctx* c) {
     return v;
 }
 
-// Destination batches: destinations of an instance in ascending node order
-// (spatially coherent when nodes follow a space-filling curve), SB per batch.
-struct BatchPlan {
-    std::vector<int32_t> dest_node, dest_inst, b_inst, b_q, b_nq;
-    std::vector<int64_t> dest_lab, b_lab;
-    size_t label_floats = 0;
-};
-
-void plan_batches(const std::vector<InstDev>& hi, const std::vector<std::vector<int32_t>>& dests_per_inst, int sb,
-                  BatchPlan& bp) {
-    int64_t lab = 0;
-    for (size_t i = 0; i < dests_per_inst.size(); ++i) {
-        const auto& ds = dests_per_inst[i];
-        int n = hi[i].n;
-        for (size_t k = 0; k < ds.size(); k += sb) {
-            int cnt = (int)std::min<size_t>(sb, ds.size() - k);
-            bp.b_inst.push_back((int32_t)i);
-            bp.b_q.push_back((int32_t)bp.dest_node.size());
-            bp.b_nq.push_back(cnt);
-            bp.b_lab.push_back(lab);
-            for (int t = 0; t < cnt; ++t) {
-                bp.dest_node.push_back(hi[i].node0 + ds[k + t]);
-                bp.dest_inst.push_back((int32_t)i);
-                bp.dest_lab.push_back(lab + t);
-            }
-            lab += (int64_t)n * sb;
-        }
-    }
-    bp.label_floats = (size_t)lab;
-}
-
-int ensure_scratch(qdta_ctx* c, int64_t B, int64_t nmax) {
-    int slots = (int)std::min<int64_t>(std::max<int64_t>(B, 1), (int64_t)c->cus * 8);
+// Trees are stored tree-major: destination t's labels occupy n floats at
+// dest_lab[t].  Destinations of an instance are in ascending node order.
+int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
+    int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1), (int64_t)c->cus * wpc);
+    slots = (slots + 3) / 4 * 4;                 // whole workgroups of four wavefronts
     c->slots = slots;
-    c->nmax = std::max<int64_t>(nmax, 1);
-    RC(dalloc(c, c->queues, (size_t)slots * 2 * c->nmax));
-    RC(dalloc(c, c->dirty, (size_t)slots * c->nmax));
-    RC(dalloc(c, c->stamp, (size_t)slots * c->nmax));
+    nmax = std::max<int64_t>(nmax, 1) + 1;       // the near ring holds up to n nodes in n + 1 slots
+    if (slots > c->scr_slots || nmax > c->scr_nmax) {
+        int64_t ns = std::max<int64_t>(slots, c->scr_slots), nm = std::max<int64_t>(nmax, c->scr_nmax);
+        RC(dalloc(c, c->nearq, (size_t)ns * nm));
+        RC(dalloc(c, c->farq, (size_t)ns * nm * 2));
+        RC(dalloc(c, c->bits, (size_t)ns * ((nm + 31) / 32)));
+        c->scr_slots = (int)ns;
+        c->scr_nmax = nm;
+    }
     RC(dalloc(c, c->work, 1));
+    RC(dalloc(c, c->delta_inst, c->inst.size()));
     return QDTA_OK;
 }
 
-int ensure_demand(qdta_ctx* c, int sb) {
+int ensure_demand(qdta_ctx* c, int wpc) {
     RC(ensure_network(c));
-    if (!c->dem_dirty && c->cur_sb == sb) return QDTA_OK;
+    if (!c->dem_dirty) return ensure_scratch(c, c->Q, c->nmax, wpc);
     int ni = (int)c->inst.size();
-    std::vector<std::vector<int32_t>> dests(ni);
-    std::vector<int32_t> qptr{0}, leg_orig, leg_q;
-    std::vector<int64_t> leg_dfx;
+    std::vector<int32_t> qptr{0}, leg_orig, leg_q, dest_node, dest_inst;
+    std::vector<int64_t> leg_dfx, dest_lab;
     c->leg_off.assign(ni + 1, 0);
     c->dest_off.assign(ni + 1, 0);
-    int64_t nmax = 0;
+    int64_t nmax = 0, lab = 0;
     for (int i = 0; i < ni; ++i) {
         Instance& I = c->inst[i];
         InstDev& d = c->h_inst[i];
@@ -350,13 +335,16 @@ int ensure_demand(qdta_ctx* c, int sb) {
         d.kappa = fin ? 3600.0 / I.dt_s : 1.0;
         d.dt32 = (float)I.dt_s;
         d.rule = QDTA_RULE_NONE;
-        d.q0 = (int32_t)qptr.size() - 1;
+        d.q0 = (int32_t)dest_node.size();
         d.leg0 = (int32_t)leg_orig.size();
         size_t p = 0;
         while (p < I.orig.size()) {
             int32_t q = I.dest[p];
-            dests[i].push_back(q);
-            int32_t qi = (int32_t)qptr.size() - 1;
+            int32_t qi = (int32_t)dest_node.size();
+            dest_node.push_back(d.node0 + q);
+            dest_inst.push_back(i);
+            dest_lab.push_back(lab);
+            lab += I.n;
             while (p < I.orig.size() && I.dest[p] == q) {
                 leg_orig.push_back(d.node0 + I.orig[p]);
                 leg_dfx.push_back(I.dfx[p]);
@@ -365,39 +353,32 @@ int ensure_demand(qdta_ctx* c, int sb) {
             }
             qptr.push_back((int32_t)leg_orig.size());
         }
-        d.nq = (int32_t)dests[i].size();
+        d.nq = (int32_t)dest_node.size() - d.q0;
         d.nleg = (int32_t)I.orig.size();
         c->leg_off[i + 1] = c->leg_off[i] + d.nleg;
         c->dest_off[i + 1] = c->dest_off[i] + d.nq;
         nmax = std::max<int64_t>(nmax, I.n);
     }
-    BatchPlan bp;
-    plan_batches(c->h_inst, dests, sb, bp);
-    c->Q = (int64_t)bp.dest_node.size();
+    c->Q = (int64_t)dest_node.size();
     c->P = (int64_t)leg_orig.size();
-    c->B = (int64_t)bp.b_inst.size();
-    c->label_floats = bp.label_floats;
-    c->h_dest_inst = bp.dest_inst;
-    c->h_dest_node = bp.dest_node;
-    RC(upload(c, c->dest_node, bp.dest_node));
-    RC(upload(c, c->dest_inst, bp.dest_inst));
-    RC(upload(c, c->dest_lab, bp.dest_lab));
+    c->nmax = nmax;
+    c->label_floats = (size_t)lab;
+    c->h_dest_inst = dest_inst;
+    c->h_dest_node = dest_node;
+    RC(upload(c, c->dest_node, dest_node));
+    RC(upload(c, c->dest_inst, dest_inst));
+    RC(upload(c, c->dest_lab, dest_lab));
     RC(upload(c, c->qptr, qptr));
     RC(upload(c, c->leg_orig, leg_orig));
     RC(upload(c, c->leg_dfx, leg_dfx));
     RC(upload(c, c->leg_q, leg_q));
-    RC(upload(c, c->b_inst, bp.b_inst));
-    RC(upload(c, c->b_q, bp.b_q));
-    RC(upload(c, c->b_nq, bp.b_nq));
-    RC(upload(c, c->b_lab, bp.b_lab));
     RC(upload(c, c->d_inst, c->h_inst));
     RC(dalloc(c, c->labels, c->label_floats));
     RC(dalloc(c, c->absorb_q, (size_t)c->Q));
     RC(dalloc(c, c->int_node, (size_t)c->P));
     RC(dalloc(c, c->int_tau, (size_t)c->P));
-    RC(ensure_scratch(c, c->B, nmax));
+    RC(ensure_scratch(c, c->Q, nmax, wpc));
     c->dem_dirty = false;
-    c->cur_sb = sb;
     c->solved = false;
     return QDTA_OK;
 }
@@ -426,23 +407,19 @@ DemDev dem_view(qdta_ctx* c) {
     v.leg_orig = c->leg_orig.p;
     v.leg_dfx = c->leg_dfx.p;
     v.leg_q = c->leg_q.p;
-    v.b_inst = c->b_inst.p;
-    v.b_q = c->b_q.p;
-    v.b_nq = c->b_nq.p;
-    v.b_lab = c->b_lab.p;
     v.Q = (int32_t)c->Q;
     v.P = (int32_t)c->P;
-    v.B = (int32_t)c->B;
-    v.sb = c->cur_sb;
+    v.sb = 1;
     return v;
 }
 
 Scratch scr_view(qdta_ctx* c) {
     Scratch s;
-    s.queues = c->queues.p;
-    s.dirty = c->dirty.p;
-    s.stamp = c->stamp.p;
-    s.nmax = (int32_t)c->nmax;
+    s.nearq = c->nearq.p;
+    s.farq = c->farq.p;
+    s.bits = c->bits.p;
+    s.nmax = c->scr_nmax;
+    s.nwords = (c->scr_nmax + 31) / 32;
     s.work = c->work.p;
     return s;
 }
@@ -469,19 +446,49 @@ int read_flags(qdta_ctx* c, int* h) {
     return QDTA_OK;
 }
 
+constexpr int kPhases = 6;
+enum { PH_BPR = 0, PH_SSSP = 1, PH_WALK = 2, PH_GAP = 3, PH_LS = 4, PH_UPDATE = 5 };
+
+// Record the start (edge 0) or end (edge 1) of a phase on the stream.
+int prof_mark(qdta_ctx* c, int ph, int edge) {
+    if (!c->prof_on) return QDTA_OK;
+    HIPCHECK(c, hipEventRecord(c->prof_ev[ph][edge], c->stream));
+    if (edge == 1) c->prof_open[ph] = 1;
+    return QDTA_OK;
+}
+
+// After a stream synchronisation: add the closed phases' durations.
+void prof_collect(qdta_ctx* c) {
+    if (!c->prof_on) return;
+    for (int p = 0; p < kPhases; ++p) {
+        if (!c->prof_open[p]) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->prof_ev[p][0], c->prof_ev[p][1]) == hipSuccess) {
+            c->prof_ms[p] += ms;
+            c->prof_n[p] += 1;
+        }
+        c->prof_open[p] = 0;
+    }
+}
+
 // One all-or-nothing assignment (A2 + A3) under `cost` (rcost already set).
-int aon_core(qdta_ctx* c, const float* cost, int64_t* y, int32_t* stop, const InstState* st) {
+int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop, const InstState* st) {
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
     FlagsDev fl = flags_view(c);
-    HIPCHECK(c, launch_sssp(c->stream, net, dem, c->rcost.p, c->labels.p, scr_view(c), c->slots, st));
+    RC(prof_mark(c, PH_SSSP, 0));
+    HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->rcost.p, c->labels.p, scr_view(c), c->slots, st,
+                            delta_scale(o), c->delta_inst.p));
+    RC(prof_mark(c, PH_SSSP, 1));
+    RC(prof_mark(c, PH_WALK, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, y, 0, c->M));
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
     HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
                             nullptr, nullptr, nullptr, nullptr));
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
-                                (int)std::min<int64_t>(c->slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
+                                (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
                                 nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0));
+    RC(prof_mark(c, PH_WALK, 1));
     return QDTA_OK;
 }
 
@@ -624,7 +631,8 @@ void qdta_default_opts(qdta_opts* o) {
     o->max_iter = 1000;
     o->fixed_iters = 0;
     o->keep_history = 0;
-    o->sources_per_block = 0;
+    o->waves_per_cu = 0;
+    o->delta_scale = 0.0;
 }
 
 const char* qdta_strerror(int code) {
@@ -667,6 +675,9 @@ int qdta_destroy(qdta_ctx* c) {
     hipStreamSynchronize(c->stream);
     for (void* p : c->allocs) hipFree(p);
     if (c->h_st) hipHostFree(c->h_st);
+    for (int p = 0; p < 8; ++p)
+        for (int e = 0; e < 2; ++e)
+            if (c->prof_ev[p][e]) hipEventDestroy(c->prof_ev[p][e]);
     delete c;
     return QDTA_OK;
 }
@@ -746,7 +757,7 @@ int qdta_set_demand(qdta_ctx* c, int32_t inst, int32_t P, const int32_t* orig, c
 int qdta_layout(qdta_ctx* c, qdta_layout_info* info) {
     if (!c || !info) return QDTA_EARG;
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, c->cur_sb ? c->cur_sb : 16));
+    if (c->dem_dirty) RC(ensure_demand(c, 16));
     info->n_instances = (int32_t)c->inst.size();
     info->total_nodes = c->N;
     info->total_links = c->M;
@@ -758,7 +769,7 @@ int qdta_layout(qdta_ctx* c, qdta_layout_info* info) {
 int qdta_offsets(qdta_ctx* c, int64_t* node_off, int64_t* link_off, int64_t* leg_off, int64_t* dest_off) {
     if (!c) return QDTA_EARG;
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, c->cur_sb ? c->cur_sb : 16));
+    if (c->dem_dirty) RC(ensure_demand(c, 16));
     size_t k = c->inst.size() + 1;
     if (node_off) std::copy(c->node_off.begin(), c->node_off.begin() + k, node_off);
     if (link_off) std::copy(c->link_off.begin(), c->link_off.begin() + k, link_off);
@@ -786,7 +797,7 @@ int qdta_bpr(qdta_ctx* c, const qdta_opts* o, const int64_t* f, float* cost) {
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!f || !cost) return set_err(c, QDTA_EARG, "null array");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, choose_sb(o)));   // kappa of each instance
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o)));   // kappa of each instance
     RC(clear_flags(c));
     HIPCHECK(c, launch_bpr(c->stream, net_view(c), f, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
     int h[4];
@@ -803,25 +814,24 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
     if (nq < 0 || (nq > 0 && (!cost || !dest || !dist || !succ))) return set_err(c, QDTA_EARG, "bad arguments");
     if (nq == 0) return QDTA_OK;
-    const InstDev& I = c->h_inst[inst];
+    const InstDev I = c->h_inst[inst];
     std::vector<int32_t> hd(nq);
     HIPCHECK(c, hipMemcpyAsync(hd.data(), dest, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     for (int t = 0; t < nq; ++t)
         if (hd[t] < 0 || hd[t] >= I.n) return set_err(c, QDTA_EARG, "dest[%d] out of range", t);
-    int sb = choose_sb(o);
-    // ad-hoc batches: one tree per requested destination, in order
-    std::vector<std::vector<int32_t>> per(c->inst.size());
-    per[inst] = hd;
-    BatchPlan bp;
-    plan_batches(c->h_inst, per, sb, bp);
-    DBuf<int32_t> dn, di, bi, bq, bn, aq;
-    DBuf<int64_t> dl, bl;
+    // one tree per requested destination, in order, labels tree-major
+    std::vector<int32_t> dn(nq), di(nq, inst);
+    std::vector<int64_t> dl(nq);
+    for (int t = 0; t < nq; ++t) {
+        dn[t] = I.node0 + hd[t];
+        dl[t] = (int64_t)t * I.n;
+    }
+    DBuf<int32_t> ddn, ddi, aq;
+    DBuf<int64_t> ddl;
     DBuf<float> lab;
-    std::vector<void*> tmp;
     auto cleanup = [&]() {
-        for (void* p : {(void*)dn.p, (void*)di.p, (void*)bi.p, (void*)bq.p, (void*)bn.p, (void*)aq.p, (void*)dl.p,
-                        (void*)bl.p, (void*)lab.p}) {
+        for (void* p : {(void*)ddn.p, (void*)ddi.p, (void*)aq.p, (void*)ddl.p, (void*)lab.p}) {
             if (!p) continue;
             hipFree(p);
             auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
@@ -830,29 +840,22 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     };
     int rc = QDTA_OK;
     do {
-        if ((rc = upload(c, dn, bp.dest_node))) break;
-        if ((rc = upload(c, di, bp.dest_inst))) break;
-        if ((rc = upload(c, dl, bp.dest_lab))) break;
-        if ((rc = upload(c, bi, bp.b_inst))) break;
-        if ((rc = upload(c, bq, bp.b_q))) break;
-        if ((rc = upload(c, bn, bp.b_nq))) break;
-        if ((rc = upload(c, bl, bp.b_lab))) break;
-        if ((rc = dalloc(c, lab, bp.label_floats))) break;
+        if ((rc = upload(c, ddn, dn))) break;
+        if ((rc = upload(c, ddi, di))) break;
+        if ((rc = upload(c, ddl, dl))) break;
+        if ((rc = dalloc(c, lab, (size_t)nq * I.n))) break;
         if ((rc = dalloc(c, aq, nq))) break;
-        if ((rc = ensure_scratch(c, std::max<int64_t>((int64_t)bp.b_inst.size(), c->B), std::max<int64_t>(c->nmax, I.n))))
-            break;
+        int saved_slots = c->slots;
+        if ((rc = ensure_scratch(c, nq, std::max<int64_t>(c->nmax, I.n), waves_per_cu(o)))) break;
+        int slots = c->slots;
+        c->slots = saved_slots;
         DemDev dem;
         memset(&dem, 0, sizeof(dem));
-        dem.dest_node = dn.p;
-        dem.dest_inst = di.p;
-        dem.dest_lab = dl.p;
-        dem.b_inst = bi.p;
-        dem.b_q = bq.p;
-        dem.b_nq = bn.p;
-        dem.b_lab = bl.p;
+        dem.dest_node = ddn.p;
+        dem.dest_inst = ddi.p;
+        dem.dest_lab = ddl.p;
         dem.Q = nq;
-        dem.B = (int32_t)bp.b_inst.size();
-        dem.sb = sb;
+        dem.sb = 1;
         NetDev net = net_view(c);
         hipError_t e;
         // place the instance's costs in the global link order
@@ -860,8 +863,8 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
             { rc = set_err(c, QDTA_EHIP, "copy cost: %s", hipGetErrorString(e)); break; }
         if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p)))
             { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
-        int slots = (int)std::min<int64_t>(c->slots, dem.B);
-        if ((e = launch_sssp(c->stream, net, dem, c->rcost.p, lab.p, scr_view(c), slots, nullptr)))
+        if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->rcost.p, lab.p, scr_view(c), slots, nullptr,
+                             delta_scale(o), c->delta_inst.p)))
             { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
         if ((e = launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(aq.p), 0u, nq)))
             { rc = set_err(c, QDTA_EHIP, "fill: %s", hipGetErrorString(e)); break; }
@@ -870,7 +873,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         FlagsDev fl = flags_view(c);
         fl.absorb_q = aq.p;
         if ((e = launch_fallback(c->stream, net, dem, lab.p, c->cost.p, c->cost.p, nullptr, nullptr, nullptr, fl,
-                                 scr_view(c), (int)std::min<int64_t>(c->slots, nq), 0, nullptr, nullptr, nullptr,
+                                 scr_view(c), (int)std::min<int64_t>(c->scr_slots, nq), 0, nullptr, nullptr, nullptr,
                                  nullptr, nullptr, nullptr, 1, succ, I.n)))
             { rc = set_err(c, QDTA_EHIP, "fallback: %s", hipGetErrorString(e)); break; }
         std::vector<int32_t> ha(nq);
@@ -880,7 +883,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         for (int t = 0; t < nq; ++t)
             if (ha[t]) rc = QDTA_WABSORB;
     } while (0);
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     cleanup();
     return rc;
 }
@@ -890,7 +893,7 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!cost || !y) return set_err(c, QDTA_EARG, "null array");
-    RC(ensure_demand(c, choose_sb(o)));
+    RC(ensure_demand(c, waves_per_cu(o)));
     RC(apply_rule(c, o));
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
@@ -898,9 +901,10 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     HIPCHECK(c, hipMemcpyAsync(c->cost.p, cost, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(c, launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p));
     if (stop) HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(stop), 0xffffffffu, c->P));
-    RC(aon_core(c, c->cost.p, y, stop, nullptr));
+    RC(aon_core(c, o, c->cost.p, y, stop, nullptr));
     int h[4];
     RC(read_flags(c, h));
+    prof_collect(c);
     RC(flag_code(c, h));
     return h[2] ? QDTA_WABSORB : QDTA_OK;
 }
@@ -912,7 +916,7 @@ int qdta_ls_eval(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (K < 1 || K > kMaxK || !f || !y || !alphas || !sums) return set_err(c, QDTA_EARG, "bad arguments");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, choose_sb(o)));
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o)));
     int ni = (int)c->inst.size();
     RC(clear_flags(c));
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->ls_acc.p), 0, (int64_t)ni * K * 6));
@@ -931,7 +935,7 @@ int qdta_line_search(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const in
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!f || !y || !alpha_out || j < 1) return set_err(c, QDTA_EARG, "bad arguments");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, choose_sb(o)));
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o)));
     int ni = (int)c->inst.size();
     RC(init_state(c, true, j));
     RC(clear_flags(c));
@@ -953,18 +957,15 @@ int qdta_fw_update(qdta_ctx* c, int64_t* f, const int64_t* y, const double* alph
     return QDTA_OK;
 }
 
-int qdta_solve(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
+int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     if (!c) return QDTA_EARG;
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     for (const Instance& I : c->inst)
-        if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solve");
-    RC(ensure_demand(c, choose_sb(o)));
+        if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solving");
+    RC(ensure_demand(c, waves_per_cu(o)));
     RC(apply_rule(c, o));
-    int ni = (int)c->inst.size();
     NetDev net = net_view(c);
-    int* err = c->flags.p;
-    const int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
     if (o->keep_history) RC(ensure_history(c, 8));
@@ -972,51 +973,101 @@ int qdta_solve(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
         I.hist_alpha.assign(1, 1.0);
         I.solved_iters = -1;
     }
-    // initial AON at free flow: BPR(0) = c0 exactly (Alg. 6 first step)
+    // initial AON at free flow: BPR(0) = c0 exactly (first step of Alg. 6)
     HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
-    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, err));
-    RC(aon_core(c, c->cost.p, c->f.p, nullptr, c->st.p));
+    RC(prof_mark(c, PH_BPR, 0));
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, c->flags.p));
+    RC(prof_mark(c, PH_BPR, 1));
+    RC(aon_core(c, o, c->cost.p, c->f.p, nullptr, c->st.p));
     if (o->keep_history)
         HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p, c->cost.p, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
-    int h[4];
-    for (int j = 1;; ++j) {
-        HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, err));
-        RC(aon_core(c, c->cost.p, c->y.p, nullptr, c->st.p));
-        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
-        HIPCHECK(c, launch_gap_sums(c->stream, net, c->cost.p, c->f.p, c->y.p, c->acc.p, c->st.p, err));
-        HIPCHECK(c, launch_gap_decide(c->stream, ni, c->acc.p, c->st.p, o->stop_rule, o->tol, o->fixed_iters, cap_iter,
-                                      j));
-        RC(line_search_core(c, o, c->f.p, c->y.p));
-        if (o->stop_rule == QDTA_STOP_OBJ && o->fixed_iters <= 0) {
-            HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
-            HIPCHECK(c, launch_obj_pair(c->stream, net, c->f.p, c->y.p, o->alpha, o->beta, c->acc.p, c->st.p, 1, err));
-            HIPCHECK(c, launch_obj_decide(c->stream, ni, c->acc.p, c->st.p, o->tol, 1));
-        }
-        HIPCHECK(c, launch_copy_alpha(c->stream, ni, c->st.p, c->alpha_arr.p));
-        HIPCHECK(c, launch_fw_update(c->stream, net, c->f.p, c->y.p, c->alpha_arr.p, c->st.p));
-        HIPCHECK(c, launch_after_update(c->stream, ni, c->st.p));
-        if (o->keep_history) {
-            RC(ensure_history(c, (size_t)j + 1));
-            HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p + (size_t)j * c->M, c->cost.p, sizeof(float) * c->M,
-                                       hipMemcpyDeviceToDevice, c->stream));
-        }
-        HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        RC(pull_state(c));
-        RC(flag_code(c, h));
-        bool live = false;
-        for (int i = 0; i < ni; ++i) {
-            const InstState& s = c->h_st[i];
-            if (!s.active) continue;
-            if (!s.converged) {
-                live = true;
-                c->inst[i].hist_alpha.push_back(s.alpha);
-            }
-        }
-        if (!live) break;
+    c->fw_j = 0;
+    c->fw_live = true;
+    c->solved = false;
+    RC(pull_state(c));
+    prof_collect(c);
+    return QDTA_OK;
+}
+
+namespace {
+
+void fill_stats(qdta_ctx* c, qdta_stats* hs, int worst, const int* h) {
+    int ni = (int)c->inst.size();
+    for (int i = 0; i < ni && hs; ++i) {
+        const InstState& s = c->h_st[i];
+        qdta_stats& q = hs[i];
+        q.iters = s.iters;
+        q.ls_evals = s.ls_evals;
+        q.qn_iters = s.qn_iters;
+        q.absorb = h[2] ? 1 : 0;
+        q.stopped_by = s.stopped_by;
+        q.status = worst;
+        q.gap = s.active ? s.gap : 0.0;
+        q.objective = s.obj;
+        q.last_alpha = s.last_alpha;
     }
+}
+
+// One Frank-Wolfe iteration j (Alg. 6): BPR, AON, stop test, line search,
+// update, for every live instance; one host synchronisation at the end.
+int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
+    int ni = (int)c->inst.size();
+    NetDev net = net_view(c);
+    int* err = c->flags.p;
+    const int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
+    const int j = ++c->fw_j;
+    RC(prof_mark(c, PH_BPR, 0));
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, err));
+    RC(prof_mark(c, PH_BPR, 1));
+    RC(aon_core(c, o, c->cost.p, c->y.p, nullptr, c->st.p));
+    RC(prof_mark(c, PH_GAP, 0));
+    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
+    HIPCHECK(c, launch_gap_sums(c->stream, net, c->cost.p, c->f.p, c->y.p, c->acc.p, c->st.p, err));
+    HIPCHECK(c, launch_gap_decide(c->stream, ni, c->acc.p, c->st.p, o->stop_rule, o->tol, o->fixed_iters, cap_iter, j));
+    RC(prof_mark(c, PH_GAP, 1));
+    RC(prof_mark(c, PH_LS, 0));
+    RC(line_search_core(c, o, c->f.p, c->y.p));
+    if (o->stop_rule == QDTA_STOP_OBJ && o->fixed_iters <= 0) {
+        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
+        HIPCHECK(c, launch_obj_pair(c->stream, net, c->f.p, c->y.p, o->alpha, o->beta, c->acc.p, c->st.p, 1, err));
+        HIPCHECK(c, launch_obj_decide(c->stream, ni, c->acc.p, c->st.p, o->tol, 1));
+    }
+    HIPCHECK(c, launch_stall_check(c->stream, ni, c->st.p, o->fixed_iters));
+    RC(prof_mark(c, PH_LS, 1));
+    RC(prof_mark(c, PH_UPDATE, 0));
+    HIPCHECK(c, launch_copy_alpha(c->stream, ni, c->st.p, c->alpha_arr.p));
+    HIPCHECK(c, launch_fw_update(c->stream, net, c->f.p, c->y.p, c->alpha_arr.p, c->st.p));
+    HIPCHECK(c, launch_after_update(c->stream, ni, c->st.p));
+    RC(prof_mark(c, PH_UPDATE, 1));
+    if (o->keep_history) {
+        RC(ensure_history(c, (size_t)j + 1));
+        HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p + (size_t)j * c->M, c->cost.p, sizeof(float) * c->M,
+                                   hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    RC(pull_state(c));
+    prof_collect(c);
+    RC(flag_code(c, h));
+    bool live = false;
+    for (int i = 0; i < ni; ++i) {
+        const InstState& s = c->h_st[i];
+        if (!s.active) continue;
+        if (!s.converged) {
+            live = true;
+            c->inst[i].hist_alpha.push_back(s.alpha);
+        }
+    }
+    c->fw_live = live;
+    return QDTA_OK;
+}
+
+int fw_finish(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
+    int ni = (int)c->inst.size();
+    NetDev net = net_view(c);
+    int h[4];
     // objective of the returned iterates
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
-    HIPCHECK(c, launch_obj_pair(c->stream, net, c->f.p, c->y.p, o->alpha, o->beta, c->acc.p, c->st.p, 0, err));
+    HIPCHECK(c, launch_obj_pair(c->stream, net, c->f.p, c->y.p, o->alpha, o->beta, c->acc.p, c->st.p, 0, c->flags.p));
     HIPCHECK(c, launch_obj_decide(c->stream, ni, c->acc.p, c->st.p, o->tol, 0));
     HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     RC(pull_state(c));
@@ -1025,22 +1076,63 @@ int qdta_solve(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
         const InstState& s = c->h_st[i];
         c->inst[i].solved_iters = s.iters;
         c->inst[i].hist_alpha.resize((size_t)s.iters + 1);
-        if (hs) {
-            qdta_stats& q = hs[i];
-            q.iters = s.iters;
-            q.ls_evals = s.ls_evals;
-            q.qn_iters = s.qn_iters;
-            q.absorb = h[2] ? 1 : 0;
-            q.stopped_by = s.stopped_by;
-            q.status = worst;
-            q.gap = s.active ? s.gap : 0.0;
-            q.objective = s.obj;
-            q.last_alpha = s.last_alpha;
-        }
     }
+    fill_stats(c, hs, worst, h);
     c->solved = true;
     if (worst < 0) return worst;
     return h[2] ? QDTA_WABSORB : QDTA_OK;
+}
+
+}  // namespace
+
+int qdta_fw_step(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs, int32_t* live_out) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (c->fw_j < 0 || c->dem_dirty) return set_err(c, QDTA_ESTATE, "qdta_fw_step needs qdta_fw_begin");
+    int h[4] = {0, 0, 0, 0};
+    if (c->fw_live) RC(fw_iteration(c, o, h));
+    else {
+        HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        RC(pull_state(c));
+    }
+    for (int i = 0; i < (int)c->inst.size(); ++i) c->inst[i].solved_iters = c->h_st[i].iters;
+    fill_stats(c, hs, QDTA_OK, h);
+    c->solved = true;
+    if (live_out) *live_out = c->fw_live ? 1 : 0;
+    return h[2] ? QDTA_WABSORB : QDTA_OK;
+}
+
+int qdta_solve(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
+    RC(qdta_fw_begin(c, o));
+    int h[4];
+    while (c->fw_live) RC(fw_iteration(c, o, h));
+    return fw_finish(c, o, hs);
+}
+
+int qdta_profile_enable(qdta_ctx* c, int32_t on) {
+    if (!c) return QDTA_EARG;
+    for (int p = 0; p < kPhases; ++p) {
+        c->prof_ms[p] = 0.0;
+        c->prof_n[p] = 0;
+        c->prof_open[p] = 0;
+        if (on && !c->prof_ev[p][0]) {
+            HIPCHECK(c, hipEventCreate(&c->prof_ev[p][0]));
+            HIPCHECK(c, hipEventCreate(&c->prof_ev[p][1]));
+        }
+    }
+    c->prof_on = on ? 1 : 0;
+    return QDTA_OK;
+}
+
+int qdta_profile_read(qdta_ctx* c, qdta_profile* out) {
+    if (!c || !out) return QDTA_EARG;
+    memset(out, 0, sizeof(*out));
+    for (int p = 0; p < kPhases; ++p) {
+        out->ms[p] = c->prof_ms[p];
+        out->count[p] = c->prof_n[p];
+    }
+    return QDTA_OK;
 }
 
 int qdta_get_flows(qdta_ctx* c, int64_t* f) {
@@ -1104,13 +1196,14 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         HIPCHECK(c, hipMemcpyAsync(c->lambda.p, lam.data(), sizeof(double) * ni, hipMemcpyHostToDevice, c->stream));
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
         HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->rcost.p));
-        HIPCHECK(c, launch_sssp(c->stream, net, dem, c->rcost.p, c->labels.p, scr_view(c), c->slots, c->st.p));
+        HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->rcost.p, c->labels.p, scr_view(c), c->slots, c->st.p,
+                                delta_scale(o), c->delta_inst.p));
         HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->r_count.p), 0, 1));
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
         HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl, 1,
                                 c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p));
         HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl,
-                                    scr_view(c), (int)std::min<int64_t>(c->slots, std::max<int64_t>(c->Q, 1)), 1,
+                                    scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
                                     c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p, 0,
                                     nullptr, 0));
         unsigned long long cnt = 0;

@@ -27,8 +27,10 @@ EXPORTS = [
     "qdta_default_opts", "qdta_strerror", "qdta_last_error", "qdta_create", "qdta_destroy", "qdta_set_stream",
     "qdta_add_network", "qdta_set_demand", "qdta_layout", "qdta_offsets", "qdta_bpr", "qdta_trees", "qdta_aon",
     "qdta_get_legs", "qdta_ls_eval", "qdta_line_search", "qdta_fw_update", "qdta_solve", "qdta_get_flows",
-    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual",
+    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_fw_begin", "qdta_fw_step",
+    "qdta_profile_enable", "qdta_profile_read",
 ]
+PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update"]
 
 
 class Opts(C.Structure):
@@ -36,7 +38,7 @@ class Opts(C.Structure):
                 ("K", C.c_int32), ("passes", C.c_int32), ("max_ls", C.c_int32), ("T1", C.c_double),
                 ("T2", C.c_double), ("dx", C.c_double), ("stop_rule", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
-                ("sources_per_block", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):
@@ -51,6 +53,10 @@ class Stats(C.Structure):
 class LayoutInfo(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("total_nodes", C.c_int64), ("total_links", C.c_int64),
                 ("total_legs", C.c_int64), ("total_dests", C.c_int64)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("count", C.c_int64 * 8)]
 
 
 class QdtaError(RuntimeError):
@@ -95,6 +101,10 @@ def lib():
         L.qdta_get_costs.argtypes = [vp, vp, vp]
         L.qdta_advance_interval.argtypes = [vp, vp]
         L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64)]
+        L.qdta_fw_begin.argtypes = [vp, vp]
+        L.qdta_fw_step.argtypes = [vp, vp, vp, C.POINTER(i32)]
+        L.qdta_profile_enable.argtypes = [vp, i32]
+        L.qdta_profile_read.argtypes = [vp, vp]
         for name in EXPORTS:
             if name not in ("qdta_default_opts", "qdta_strerror", "qdta_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -237,6 +247,23 @@ class Context:
         st = (Stats * max(self.n_inst, 1))()
         rc = self._rc(lib().qdta_solve(self._h, C.byref(opts), st), allow=(OK, WABSORB))
         return [st[i].as_dict() for i in range(self.n_inst)], rc
+
+    def fw_begin(self, opts):
+        self._rc(lib().qdta_fw_begin(self._h, C.byref(opts)))
+
+    def fw_step(self, opts):
+        st = (Stats * max(self.n_inst, 1))()
+        live = C.c_int32()
+        self._rc(lib().qdta_fw_step(self._h, C.byref(opts), st, C.byref(live)), allow=(OK, WABSORB))
+        return [st[i].as_dict() for i in range(self.n_inst)], bool(live.value)
+
+    def profile(self, on: bool = True):
+        self._rc(lib().qdta_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        p = Profile()
+        self._rc(lib().qdta_profile_read(self._h, C.byref(p)))
+        return {name: (p.ms[i], p.count[i]) for i, name in enumerate(PHASES)}
 
     def get_flows(self, f_fx):
         self._rc(lib().qdta_get_flows(self._h, _ptr(f_fx)))

@@ -91,13 +91,13 @@ def test_bpr_worked_example(torch_dev, q, orc):
 # ---------------------------------------------------------------------------
 # A2 -- trees
 # ---------------------------------------------------------------------------
-def _trees(torch, q, net, cost, dests, sb=16):
+def _trees(torch, q, net, cost, dests, ds=0.0):
     with q.Context() as ctx:
         ctx.add(net)
         nq = len(dests)
         dist = torch.empty(nq * net.n, dtype=torch.float32, device="cuda")
         succ = torch.empty(nq * net.n, dtype=torch.int32, device="cuda")
-        rc = ctx.trees(q.default_opts(sources_per_block=sb), 0, dev(torch, cost.astype(np.float32)),
+        rc = ctx.trees(q.default_opts(delta_scale=ds), 0, dev(torch, cost.astype(np.float32)),
                        dev(torch, np.asarray(dests, np.int32)), dist, succ)
         return host(dist).reshape(nq, net.n), host(succ).reshape(nq, net.n), rc
 
@@ -108,7 +108,7 @@ def test_trees_tiny_all_destinations(torch_dev, q, orc, costs):
         rng = np.random.default_rng(500 + seed)
         n = int(rng.integers(3, 12))
         net = synth.tiny_network(n, int(rng.integers(2, 14)), rng, costs=costs)
-        D, S, rc = _trees(torch_dev, q, net, net.fftt, list(range(n)), sb=4)
+        D, S, rc = _trees(torch_dev, q, net, net.fftt, list(range(n)), ds=0.7)
         absorbed = False
         for t in range(n):
             Do, So, rco = orc.tree(net, net.fftt, t)
@@ -118,13 +118,15 @@ def test_trees_tiny_all_destinations(torch_dev, q, orc, costs):
         assert (rc == q.WABSORB) == absorbed
 
 
-@pytest.mark.parametrize("sb", [4, 8, 16, 32])
-def test_trees_grid_every_batch_width(torch_dev, q, orc, sb):
+@pytest.mark.parametrize("ds", [0.05, 1.0, 3.0, 40.0, 1e30])
+def test_trees_grid_every_bucket_width(torch_dev, q, orc, ds):
+    """Any bucket width gives the same least fixed point: tiny buckets (near
+    Dijkstra), the default, and one bucket (Bellman-Ford)."""
     w = synth.config1()
-    rng = np.random.default_rng(sb)
+    rng = np.random.default_rng(7)
     cost = (w.net.fftt * rng.uniform(1, 4, w.net.m)).astype(np.float32)
-    dests = list(range(0, w.net.n, 7))          # 58 trees: several batches plus a ragged one
-    D, S, _ = _trees(torch_dev, q, w.net, cost, dests, sb=sb)
+    dests = list(range(0, w.net.n, 7))          # 58 trees
+    D, S, _ = _trees(torch_dev, q, w.net, cost, dests, ds=ds)
     for k, t in enumerate(dests):
         Do, So, _ = orc.tree(w.net, cost, t)
         assert np.array_equal(D[k].view(np.uint32), Do.view(np.uint32))
@@ -137,7 +139,7 @@ def test_trees_metro_network_sample(torch_dev, q, orc):
     f = rng.integers(0, 300 * FX, w.net.m).astype(np.int64)
     cost, _ = orc.bpr(f, w.net.fftt, w.net.cap, 0.15, 4, 900.0)
     dests = list(w.extra["zones"][rng.choice(len(w.extra["zones"]), 20, replace=False)])
-    D, S, _ = _trees(torch_dev, q, w.net, cost, dests, sb=16)
+    D, S, _ = _trees(torch_dev, q, w.net, cost, dests)
     for k, t in enumerate(dests):
         Do, So, _ = orc.tree(w.net, cost, int(t))
         assert np.array_equal(D[k].view(np.uint32), Do.view(np.uint32))
@@ -147,14 +149,14 @@ def test_trees_metro_network_sample(torch_dev, q, orc):
 # ---------------------------------------------------------------------------
 # A2 + A3 -- all-or-nothing with truncation
 # ---------------------------------------------------------------------------
-def _aon(torch, q, net, cost, orig, dest, trips, dt, rule, sb=16):
+def _aon(torch, q, net, cost, orig, dest, trips, dt, rule, ds=0.0):
     with q.Context() as ctx:
         ctx.add(net)
         ctx.set_demand(0, orig, dest, trips, dt)
         o, d, wfx = ctx.legs()
         y = torch.empty(net.m, dtype=torch.int64, device="cuda")
         stop = torch.empty(max(len(o), 1), dtype=torch.int32, device="cuda")
-        rc = ctx.aon(q.default_opts(trunc_rule=rule, sources_per_block=sb), dev(torch, cost.astype(np.float32)), y,
+        rc = ctx.aon(q.default_opts(trunc_rule=rule, delta_scale=ds), dev(torch, cost.astype(np.float32)), y,
                      stop)
         return host(y), host(stop)[:len(o)], (o, d, wfx), rc
 
@@ -170,7 +172,7 @@ def test_aon_tiny(torch_dev, q, orc, rule):
         dest = rng.integers(0, n, P)
         trips = rng.uniform(0.1, 30, P)
         dt = float(rng.uniform(30, 150))
-        y, stop, (o, d, wfx), rc = _aon(torch_dev, q, net, net.fftt, orig, dest, trips, dt, rule, sb=4)
+        y, stop, (o, d, wfx), rc = _aon(torch_dev, q, net, net.fftt, orig, dest, trips, dt, rule, ds=0.5)
         yo, so, _ = orc.aon(net, net.fftt, o, d, wfx, dt, rule)
         assert np.array_equal(y, yo), seed
         assert np.array_equal(stop, so), seed
@@ -184,7 +186,7 @@ def test_aon_absorption_fallback(torch_dev, q, orc):
         orig = rng.integers(0, 8, 30)
         dest = rng.integers(0, 8, 30)
         trips = rng.uniform(1, 10, 30)
-        y, stop, (o, d, wfx), rc = _aon(torch_dev, q, net, net.fftt, orig, dest, trips, float("inf"), 1, sb=4)
+        y, stop, (o, d, wfx), rc = _aon(torch_dev, q, net, net.fftt, orig, dest, trips, float("inf"), 1, ds=0.5)
         yo, so, rco = orc.aon(net, net.fftt, o, d, wfx, float("inf"), 1)
         assert np.array_equal(y, yo) and np.array_equal(stop, so), seed
         hits += rc == q.WABSORB
