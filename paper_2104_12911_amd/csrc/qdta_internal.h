@@ -11,6 +11,11 @@ constexpr int kChunk = 2048;             // links per workgroup in link-parallel
 constexpr uint32_t kInfBits = 0x7f800000u;
 constexpr int kMaxK = 64;                // step sizes per line-search pass
 
+// One shortest-path label word: (0x7fffffff - epoch) << 33 | FP32 bits of
+// the distance << 1 | not-queued flag.
+typedef unsigned long long label_t;
+constexpr uint32_t kMaxEpoch = 0x7ffffffeu;
+
 // Static description of one instance inside the concatenated layout.
 struct InstDev {
     int32_t node0, n;        // first global node, node count
@@ -64,12 +69,12 @@ struct NetDev {
 struct DemDev {
     const int32_t* dest_node;// [Q] global node of each destination
     const int32_t* dest_inst;// [Q]
-    const int64_t* dest_lab; // [Q] offset (floats) of the tree's label of node 0
+    const int64_t* dest_lab; // [Q] offset (labels) of the tree's label of node 0
     const int32_t* qptr;     // [Q+1] legs of each destination (global leg index)
     const int32_t* leg_orig; // [P] global origin node
     const int64_t* leg_dfx;  // [P]
     const int32_t* leg_q;    // [P] global destination index
-    int32_t Q, P, sb;        // sb: stride between a tree's labels of consecutive nodes
+    int32_t Q, P;
 };
 
 // Per-wavefront scratch of the shortest-path kernel (also the workgroup
@@ -77,8 +82,7 @@ struct DemDev {
 struct Scratch {
     int32_t* nearq;          // [slots][nmax] near queue (ring of n + 1)
     int32_t* farq;           // [slots][nmax] far queue of (node, label) pairs (2 ints each)
-    uint32_t* bits;          // [slots][nwords] queued-node bitmap
-    int64_t nmax, nwords;    // nmax >= largest n + 1
+    int64_t nmax;            // >= largest n + 1
     int32_t* work;           // tree work counter
 };
 
@@ -133,24 +137,25 @@ hipError_t launch_after_update(hipStream_t s, int ninst, InstState* st);
 hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, float* rcost);
 
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const float* rcost,
-                       float* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst);
+                       label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
+                       float* delta_inst, double* logsum, int variant, uint32_t ecode, int early);
 
-hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int32_t* r_orig, int32_t* r_dest, int64_t* r_w, unsigned long long* r_count,
-                       unsigned long long* done_fx);
+                       unsigned long long* done_fx, uint32_t ecode);
 
-hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
                            unsigned long long* r_count, unsigned long long* done_fx,
-                           int trees_mode, int32_t* succ_out, int32_t n_out);
+                           int trees_mode, int32_t* succ_out, int32_t n_out, uint32_t ecode);
 
-hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                             const float* cost_local, int32_t inst, float* dist, int32_t* succ,
-                            int32_t* absorb_q);
+                            int32_t* absorb_q,
+                            uint32_t ecode);
 
 }  // namespace qdta

@@ -44,6 +44,9 @@ __device__ __forceinline__ uint32_t ld_coherent(const uint32_t* p) {
 __device__ __forceinline__ int32_t ld_coherent(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned long long ld_coherent64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // round-half-even(x * 2^16) as int128; flags values that are not finite or
 // beyond the int128 range.
@@ -573,6 +576,25 @@ hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, doub
 // ---------------------------------------------------------------------------
 // A2: shortest-path trees, one wavefront per destination (delta-stepping)
 // ---------------------------------------------------------------------------
+// A tree's label of node v is one 64-bit word
+//     (E << 33) | (FP32 bits of D(v) << 1) | f,   E = 0x7fffffff - epoch,
+// where f = 1 when v is NOT queued.  Each shortest-path launch uses a new
+// epoch, so a word written by an earlier launch compares above every word of
+// the current one and reads as +inf, not queued: no per-launch reset.  Within
+// an epoch, unsigned order is (value, flag) order, so one atomicMin both
+// lowers the value and marks the node queued, and its return value tells
+// whether this relaxation was the one that queued it; one atomicOr(1) takes
+// a node off the queue and returns its current value.
+__device__ __forceinline__ label_t lab_word(uint32_t ecode, uint32_t vbits, uint32_t notq) {
+    return ((label_t)ecode << 33) | ((label_t)vbits << 1) | (label_t)notq;
+}
+__device__ __forceinline__ uint32_t word_vbits(label_t w, uint32_t ecode) {
+    return (uint32_t)(w >> 33) == ecode ? (uint32_t)(w >> 1) : kInfBits;
+}
+__device__ __forceinline__ float lab_val(const label_t* lab, int64_t i, uint32_t ecode) {
+    return __uint_as_float(word_vbits(lab[i], ecode));
+}
+
 __device__ __forceinline__ unsigned long long lanes_below(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
@@ -585,14 +607,13 @@ __device__ __forceinline__ float wave_min(float x) {
 // Each wavefront owns one destination tree at a time (a work counter hands
 // out trees) and runs delta-stepping on the reverse graph: D[q] = 0, and the
 // nodes taken from the near queue relax their in-links (u, w):
-// D[u] = min(D[u], fl32(D[w] + c)) by an integer atomicMin on the FP32 bit
-// pattern (labels are non-negative, so bit order is value order).
+// D[u] = min(D[u], fl32(D[w] + c)).
 //   - Up to 64 nodes are popped per step (FIFO ring); their in-links are
 //     flattened across the lanes with a prefix sum of the in-degrees, so each
 //     step relaxes 64 links whatever the degree mix.
-//   - An improved node is queued once (a per-tree bitmap marks queued nodes):
-//     in the near queue when its label is below the bucket bound thr, else in
-//     the far queue together with that label.
+//   - A relaxation that queues a node (the label word's flag was 1) puts it in
+//     the near queue when its label is below the bucket bound thr, else in the
+//     far queue together with that label.  A node is in at most one queue.
 //   - When the near queue empties, thr moves to delta above the smallest far
 //     label (kept as a running minimum) and one pass moves the far entries
 //     below thr to the near queue.
@@ -600,19 +621,27 @@ __device__ __forceinline__ float wave_min(float x) {
 // needs no barrier and no shared-memory atomics.  Whatever the order, the
 // labels reach the least fixed point of D(v) = min_e fl32(D(head e) + c_e),
 // the FP32 min-plus distance.
+
+// U: nodes popped per lane per step (up to 64 U per step); V: in-links each
+// lane relaxes per chunk, their loads, label checks and atomics issued back
+// to back.
+// early: stop a tree once every origin of its legs is settled (AON and
+// residual walks read nothing beyond); 0 builds complete trees.
+template <int U, int V>
 __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const float* __restrict__ rcost,
-                                                 float* labels, Scratch scr, const InstState* st,
-                                                 const float* __restrict__ delta_inst) {
-    __shared__ int s_pre[kWG / 64][65];
-    __shared__ float s_dw[kWG / 64][64];
-    __shared__ int s_e0[kWG / 64][64];
+                                                 label_t* labels, Scratch scr, const InstState* st,
+                                                 const float* __restrict__ delta_inst, uint32_t ecode, int early) {
+    constexpr int W = kWG / 64;
+    constexpr int NP = 64 * U;                    // nodes per step
+    __shared__ int s_pre[W][NP + 1];
+    __shared__ float s_dw[W][NP];
+    __shared__ int s_e0[W][NP];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + wv;
+    const int64_t slot = (int64_t)blockIdx.x * W + wv;
     const unsigned long long below = lanes_below(lane);
     int32_t* nearq = scr.nearq + slot * scr.nmax;
     uint2* farq = reinterpret_cast<uint2*>(scr.farq) + slot * scr.nmax;
-    uint32_t* bits = scr.bits + slot * scr.nwords;
     int* pre = s_pre[wv];
     float* sdw = s_dw[wv];
     int* se0 = s_e0[wv];
@@ -627,19 +656,15 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const f
         const InstDev I = net.inst[inst];
         const int n = I.n, node0 = I.node0;
         const int* __restrict__ rptr = net.rptr + node0;
-        uint32_t* D = reinterpret_cast<uint32_t*>(labels + dem.dest_lab[t]);
+        label_t* D = labels + dem.dest_lab[t];
         const int root = dem.dest_node[t] - node0;
         const float delta = delta_inst[inst];
-        const int nw = (n + 31) >> 5;
-        for (int i = lane; i < n; i += 64) D[i] = kInfBits;
-        for (int i = lane; i < nw; i += 64) bits[i] = 0u;
-        __threadfence_block();
         if (lane == 0) {
-            D[root] = 0u;
-            bits[root >> 5] = 1u << (root & 31);
+            D[root] = lab_word(ecode, 0u, 0u);    // value 0, queued
             nearq[0] = root;
         }
         __threadfence_block();
+        const int l0 = early ? dem.qptr[t] : 0, l1 = early ? dem.qptr[t + 1] : 0;
         const int R = n + 1;                      // near ring capacity: at most n nodes are queued
         int head = 0, ncnt = 1;                   // near ring: ncnt entries from head, modulo R
         int fcnt = 0;
@@ -647,70 +672,144 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const f
         float fmin = __uint_as_float(kInfBits);   // smallest label pushed to far
         for (;;) {
             while (ncnt > 0) {
-                const int k = ncnt < 64 ? ncnt : 64;
-                int w = 0, deg = 0;
-                float dw = 0.0f;
-                if (lane < k) {
-                    int pos = head + lane;
-                    if (pos >= R) pos -= R;
-                    w = nearq[pos];
-                    atomicAnd(&bits[w >> 5], ~(1u << (w & 31)));
-                    dw = __uint_as_float(ld_coherent(&D[w]));
-                    const int e0 = rptr[w];
-                    deg = rptr[w + 1] - e0;
-                    se0[lane] = e0;
-                    sdw[lane] = dw;
+                const int k = ncnt < NP ? ncnt : NP;
+                // pop: slot j = u * 64 + lane
+                int deg[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = u * 64 + lane;
+                    deg[u] = 0;
+                    if (j < k) {
+                        int pos = head + j;
+                        if (pos >= R) pos -= R;
+                        const int w = nearq[pos];
+                        const label_t lw = atomicOr(&D[w], 1ull);      // dequeue, read the label
+                        const int e0 = rptr[w];
+                        deg[u] = rptr[w + 1] - e0;
+                        se0[j] = e0;
+                        sdw[j] = __uint_as_float((uint32_t)(lw >> 1));
+                    }
                 }
                 head += k;
                 if (head >= R) head -= R;
                 ncnt -= k;
-                // inclusive prefix sum of in-degrees across the wave
-                int incl = deg;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int x = __shfl_up(incl, o);
-                    if (lane >= o) incl += x;
+                // exclusive prefix of in-degrees in slot order
+                int base = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    int incl = deg[u];
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int x = __shfl_up(incl, o);
+                        if (lane >= o) incl += x;
+                    }
+                    pre[u * 64 + lane] = base + incl - deg[u];
+                    base += __shfl(incl, 63);
                 }
-                pre[lane + 1] = incl;
-                if (lane == 0) pre[0] = 0;
-                const int total = __shfl(incl, 63);
+                if (lane == 0) pre[k] = base;
+                const int total = base;
                 __builtin_amdgcn_wave_barrier();
-                for (int g0 = 0; g0 < total; g0 += 64) {
-                    const int g = g0 + lane;
-                    bool pn = false, pf = false;
-                    int v = 0;
-                    float cand = 0.0f;
-                    if (g < total) {
-                        // owner: the lane whose [pre, pre + deg) holds g
-                        int lo = 0, hi = k;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (pre[mid] <= g) lo = mid; else hi = mid;
+                for (int g0 = 0; g0 < total; g0 += 64 * V) {
+                    int vv[V];
+                    float cd[V];
+                    bool ok[V];
+#pragma unroll
+                    for (int x = 0; x < V; ++x) {
+                        const int g = g0 + x * 64 + lane;
+                        ok[x] = g < total;
+                        vv[x] = 0;
+                        cd[x] = 0.0f;
+                        if (ok[x]) {
+                            int lo = 0, hi = k;   // owner slot: pre[lo] <= g < pre[lo + 1]
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (pre[mid] <= g) lo = mid; else hi = mid;
+                            }
+                            const int e = se0[lo] + (g - pre[lo]);
+                            vv[x] = net.rsrc[e] - node0;
+                            cd[x] = sdw[lo] + rcost[e];
                         }
-                        const int e = se0[lo] + (g - pre[lo]);
-                        v = net.rsrc[e] - node0;
-                        cand = sdw[lo] + rcost[e];
-                        const uint32_t cb = __float_as_uint(cand);
-                        if (cb < D[v]) {
-                            atomicMin(&D[v], cb);
-                            const uint32_t mbit = 1u << (v & 31);
-                            if (!(atomicOr(&bits[v >> 5], mbit) & mbit)) {
-                                pn = cand < thr;
-                                pf = !pn;
+                    }
+                    uint32_t cur[V];
+#pragma unroll
+                    for (int x = 0; x < V; ++x) cur[x] = ok[x] ? word_vbits(D[vv[x]], ecode) : 0u;
+                    bool pn[V], pf[V];
+#pragma unroll
+                    for (int x = 0; x < V; ++x) {
+                        pn[x] = pf[x] = false;
+                        const uint32_t cb = __float_as_uint(cd[x]);
+                        if (ok[x] && cb < cur[x]) {
+                            const label_t old = atomicMin(&D[vv[x]], lab_word(ecode, cb, 0u));
+                            // this relaxation queued v: the word it replaced was of an
+                            // earlier epoch, or not queued and not below cb
+                            const bool fresh = (uint32_t)(old >> 33) != ecode;
+                            if (fresh || ((old & 1ull) && cb <= (uint32_t)(old >> 1))) {
+                                pn[x] = cd[x] < thr;
+                                pf[x] = !pn[x];
                             }
                         }
                     }
-                    const unsigned long long bn = __ballot(pn), bf = __ballot(pf);
-                    if (pn) {
-                        int pos = head + ncnt + __popcll(bn & below);
-                        if (pos >= R) pos -= R;
-                        nearq[pos] = v;
+                    float fm = __uint_as_float(kInfBits);
+#pragma unroll
+                    for (int x = 0; x < V; ++x) {
+                        const unsigned long long bn = __ballot(pn[x]), bf = __ballot(pf[x]);
+                        if (pn[x]) {
+                            int pos = head + ncnt + __popcll(bn & below);
+                            if (pos >= R) pos -= R;
+                            nearq[pos] = vv[x];
+                        }
+                        if (pf[x]) {
+                            farq[fcnt + __popcll(bf & below)] = make_uint2((uint32_t)vv[x], __float_as_uint(cd[x]));
+                            fm = fminf(fm, cd[x]);
+                        }
+                        ncnt += __popcll(bn);
+                        fcnt += __popcll(bf);
                     }
-                    if (pf) farq[fcnt + __popcll(bf & below)] = make_uint2((uint32_t)v, __float_as_uint(cand));
-                    ncnt += __popcll(bn);
-                    fcnt += __popcll(bf);
-                    fmin = fminf(fmin, wave_min(pf ? cand : __uint_as_float(kInfBits)));
+                    fmin = fminf(fmin, wave_min(fm));
                 }
                 __threadfence_block();
+            }
+            // Bucket [.., thr) is drained.  Far entries carry the label they had
+            // when queued; one improved since may now lie below thr.
+            if (early) {
+                // all origins below thr?  (cheap test before the exact one)
+                bool pend = false;
+                for (int l = l0 + lane; l < l1; l += 64) {
+                    const int o = dem.leg_orig[l] - node0;
+                    if (!(__uint_as_float(word_vbits(ld_coherent64(&D[o]), ecode)) < thr)) pend = true;
+                }
+                if (__ballot(pend) == 0ull) {
+                    // exact: move far entries whose current label is below thr
+                    int moved = 0;
+                    for (int i0 = 0; i0 < fcnt; i0 += 64) {
+                        const int i = i0 + lane;
+                        const bool h = i < fcnt;
+                        const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                        const float dv = h ? __uint_as_float(word_vbits(ld_coherent64(&D[ent.x]), ecode)) : 0.0f;
+                        const bool late = h && dv < thr;
+                        const unsigned long long bl = __ballot(late);
+                        if (late) {
+                            int pos = head + ncnt + __popcll(bl & below);
+                            if (pos >= R) pos -= R;
+                            nearq[pos] = (int)ent.x;
+                        }
+                        // keep the rest, in order
+                        const unsigned long long bk = __ballot(h && !late);
+                        if (h && !late) farq[i0 - moved + __popcll(bk & below)] = ent;
+                        ncnt += __popcll(bl);
+                        moved += __popcll(bl);
+                    }
+                    fcnt -= moved;
+                    __threadfence_block();
+                    if (moved == 0) break;            // every node below thr is settled
+                    if (fcnt > 0) {
+                        float km = __uint_as_float(kInfBits);
+                        for (int i = lane; i < fcnt; i += 64) km = fminf(km, __uint_as_float(farq[i].y));
+                        fmin = wave_min(km);
+                    } else {
+                        fmin = __uint_as_float(kInfBits);
+                    }
+                    continue;
+                }
             }
             if (fcnt == 0) break;
             // next bucket: delta above the smallest far label
@@ -744,50 +843,71 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const f
     }
 }
 
-// Bucket width per instance: delta = scale * (mean link cost of the instance).
-__global__ __launch_bounds__(kWG) void k_delta(NetDev net, const float* __restrict__ cost, double scale,
-                                               float* delta_inst) {
+// Bucket width per instance: delta = scale * (geometric mean link cost of the
+// instance).  The geometric mean follows the typical link; the arithmetic
+// mean is dominated by the few links that congestion makes very slow.
+// Partial sums of log(cost) per link chunk, then one division per instance.
+__global__ __launch_bounds__(kWG) void k_logcost(NetDev net, const float* __restrict__ cost, double* logsum) {
     __shared__ double part[kWG];
-    const int inst = blockIdx.x;
+    const int b = blockIdx.x;
+    const int inst = net.blk_inst[b];
     const InstDev I = net.inst[inst];
+    const int a0 = net.blk_start[b];
+    const int a1 = min(a0 + kChunk, I.link0 + I.m);
     double s = 0.0;
-    for (int a = I.link0 + threadIdx.x; a < I.link0 + I.m; a += kWG) s += (double)cost[a];
+    for (int a = a0 + threadIdx.x; a < a1; a += kWG) s += log((double)cost[a]);
     part[threadIdx.x] = s;
     __syncthreads();
     for (int k = kWG / 2; k > 0; k >>= 1) {
         if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        double d = I.m > 0 ? scale * part[0] / (double)I.m : 1.0;
-        if (!(d > 0.0) || !(d < 3.0e38)) d = 3.0e38;
-        delta_inst[inst] = (float)d;
-    }
+    if (threadIdx.x == 0) atomicAdd(&logsum[inst], part[0]);
+}
+
+__global__ void k_delta(NetDev net, const double* logsum, double scale, float* delta_inst) {
+    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= net.ninst) return;
+    const InstDev I = net.inst[inst];
+    double d = I.m > 0 ? scale * exp(logsum[inst] / (double)I.m) : 1.0;
+    if (!(d > 0.0) || !(d < 3.0e38)) d = 3.0e38;
+    delta_inst[inst] = (float)d;
 }
 
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const float* rcost,
-                       float* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst) {
+                       label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
+                       float* delta_inst, double* logsum, int variant, uint32_t ecode, int early) {
     if (dem.Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_delta, dim3(net.ninst), dim3(kWG), 0, s, net, cost, delta_scale, delta_inst);
+    hipError_t e0 = launch_fill_i64(s, reinterpret_cast<int64_t*>(logsum), 0, net.ninst);
+    if (e0 != hipSuccess) return e0;
+    if (net.nblk > 0) hipLaunchKernelGGL(k_logcost, dim3(net.nblk), dim3(kWG), 0, s, net, cost, logsum);
+    hipLaunchKernelGGL(k_delta, dim3((net.ninst + 63) / 64), dim3(64), 0, s, net, logsum, delta_scale, delta_inst);
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
     const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
-    hipLaunchKernelGGL(k_sssp_ds, dim3(blocks), dim3(kWG), 0, s, net, dem, rcost, labels, scr, st, delta_inst);
+    dim3 g(blocks), b(kWG);
+    switch (variant) {
+        case 0: hipLaunchKernelGGL((k_sssp_ds<1, 4>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+        case 1: hipLaunchKernelGGL((k_sssp_ds<2, 4>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+        case 2: hipLaunchKernelGGL((k_sssp_ds<4, 4>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+        case 3: hipLaunchKernelGGL((k_sssp_ds<4, 8>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+        case 4: hipLaunchKernelGGL((k_sssp_ds<8, 8>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+        default: hipLaunchKernelGGL((k_sssp_ds<1, 1>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+    }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // A3: truncation + loading, and the residual walk of Alg. 4
 // ---------------------------------------------------------------------------
-// Successor of u on the tree whose labels are lab[(node - node0) * sb]: the
+// Successor of u on the tree whose labels are lab[node - node0]: the
 // lowest-uid out-link (u, w) that is tight, fl32(D(w) + c) == D(u), and
 // strict, D(w) < D(u).  -1 when FP32 absorption leaves none.
-__device__ __forceinline__ int succ_strict(const NetDev& net, const float* lab, int sb, int node0, int u, float du,
-                                          const float* tree_cost) {
+__device__ __forceinline__ int succ_strict(const NetDev& net, const label_t* lab, uint32_t ecode, int node0, int u,
+                                          float du, const float* tree_cost) {
     const int e1 = net.row_ptr[u + 1];
     for (int e = net.row_ptr[u]; e < e1; ++e) {
-        const float dw = lab[(int64_t)(net.col[e] - node0) * sb];
+        const float dw = lab_val(lab, net.col[e] - node0, ecode);
         if (dw < du && dw + tree_cost[e] == du) return e;
     }
     return -1;
@@ -823,10 +943,10 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
     o.r_w[k] = w;
 }
 
-__global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const float* __restrict__ labels,
+__global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                               const float* __restrict__ tree_cost,
                                               const float* __restrict__ time_cost, const InstState* st,
-                                              FlagsDev fl, WalkOut o) {
+                                              FlagsDev fl, WalkOut o, uint32_t ecode) {
     const int l = blockIdx.x * kWG + threadIdx.x;
     if (l >= dem.P) return;
     const int qi = dem.leg_q[l];
@@ -835,11 +955,10 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const floa
     const InstDev I = net.inst[inst];
     const int node0 = I.node0;
     const int q = dem.dest_node[qi];
-    const float* lab = labels + dem.dest_lab[qi];
-    const int sb = dem.sb;
+    const label_t* lab = labels + dem.dest_lab[qi];
     const int64_t d = dem.leg_dfx[l];
     int u = dem.leg_orig[l];
-    float du = lab[(int64_t)(u - node0) * sb];
+    float du = lab_val(lab, u - node0, ecode);
     fl.int_node[l] = -1;
     if (!(du <= 3.4028234663852886e38f)) {       // origin cannot reach q
         atomicOr(fl.err_unreach, 1);
@@ -849,7 +968,7 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const floa
     float tau = 0.0f;
     for (int hops = 0; u != q; ++hops) {
         if (I.rule == RULE_CEIL && tau >= I.dt32) break;
-        const int e = succ_strict(net, lab, sb, node0, u, du, tree_cost);
+        const int e = succ_strict(net, lab, ecode, node0, u, du, tree_cost);
         if (e < 0 || hops > I.n) {                // absorption: finish in the fallback
             fl.int_node[l] = u;
             fl.int_tau[l] = tau;
@@ -862,19 +981,20 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const floa
         if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
         tau = nt;
         u = net.col[e];
-        du = lab[(int64_t)(u - node0) * sb];
+        du = lab_val(lab, u - node0, ecode);
     }
     finish_leg(o, l, u, q, qi, inst, node0, d);
 }
 
-hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda, int32_t* r_orig,
-                       int32_t* r_dest, int64_t* r_w, unsigned long long* r_count, unsigned long long* done_fx) {
+                       int32_t* r_dest, int64_t* r_w, unsigned long long* r_count, unsigned long long* done_fx,
+                       uint32_t ecode) {
     if (dem.P == 0) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_orig, r_dest, r_w, r_count, done_fx};
     hipLaunchKernelGGL(k_walk, dim3((dem.P + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost,
-                       st, fl, o);
+                       st, fl, o, ecode);
     return hipGetLastError();
 }
 
@@ -886,11 +1006,11 @@ hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, cons
 // tight link then takes the lowest-uid tight link to a node with h - 1.
 // Trees mode fills the missing successors; walk mode finishes the legs that
 // the walk interrupted.  One workgroup per flagged tree.
-__global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const float* __restrict__ labels,
+__global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                                   const float* __restrict__ tree_cost,
                                                   const float* __restrict__ time_cost, const InstState* st,
                                                   FlagsDev fl, Scratch scr, WalkOut o, int trees_mode,
-                                                  int32_t* succ_out, int32_t n_out) {
+                                                  int32_t* succ_out, int32_t n_out, uint32_t ecode) {
     __shared__ int s_cnt[2];
     int32_t* hop = scr.farq + (int64_t)blockIdx.x * scr.nmax;
     int32_t* qbase = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
@@ -900,8 +1020,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
         if (!inst_live(st, inst)) continue;
         const InstDev I = net.inst[inst];
         const int n = I.n, node0 = I.node0;
-        const float* lab = labels + dem.dest_lab[qi];
-        const int sb = dem.sb;
+        const label_t* lab = labels + dem.dest_lab[qi];
         const int q = dem.dest_node[qi];
         // breadth-first levels in one FIFO: level L occupies [s_cnt[0], s_cnt[1])
         for (int v = threadIdx.x; v < n; v += kWG) hop[v] = -1;
@@ -915,11 +1034,11 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
             __syncthreads();
             for (int i = lo + threadIdx.x; i < hi; i += kWG) {
                 const int u = qbase[i];
-                const float du = lab[(int64_t)u * sb];
+                const float du = lab_val(lab, u, ecode);
                 for (int e = net.rptr[node0 + u]; e < net.rptr[node0 + u + 1]; ++e) {
                     const int v = net.rsrc[e] - node0;
                     const int link = net.rlink[e];
-                    const float dv = lab[(int64_t)v * sb];
+                    const float dv = lab_val(lab, v, ecode);
                     if (dv <= 3.4028234663852886e38f && du + tree_cost[link] == dv) {
                         if (atomicCAS(&hop[v], -1, level + 1) == -1) {
                             int pos = atomicAdd(&s_cnt[1], 1);
@@ -934,12 +1053,12 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
         }
         // successor with the hop rule where no strict tight link exists
         auto succ_full = [&](int u, float du) -> int {
-            int e = succ_strict(net, lab, sb, node0, u, du, tree_cost);
+            int e = succ_strict(net, lab, ecode, node0, u, du, tree_cost);
             if (e >= 0) return e;
             const int hu = ld_coherent(&hop[u - node0]);
             for (int k = net.row_ptr[u]; k < net.row_ptr[u + 1]; ++k) {
                 const int w = net.col[k];
-                const float dw = lab[(int64_t)(w - node0) * sb];
+                const float dw = lab_val(lab, w - node0, ecode);
                 if (dw + tree_cost[k] == du && ld_coherent(&hop[w - node0]) == hu - 1) return k;
             }
             return -1;
@@ -948,7 +1067,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
             const int t = qi;
             for (int v = threadIdx.x; v < n; v += kWG) {
                 const int g = node0 + v;
-                const float dv = lab[(int64_t)v * sb];
+                const float dv = lab_val(lab, v, ecode);
                 if (g == q || !(dv <= 3.4028234663852886e38f)) continue;
                 if (succ_out[(int64_t)t * n_out + v] >= 0) continue;
                 const int e = succ_full(g, dv);
@@ -959,7 +1078,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                 int u = fl.int_node[l];
                 if (u < 0) continue;
                 float tau = fl.int_tau[l];
-                float du = lab[(int64_t)(u - node0) * sb];
+                float du = lab_val(lab, u - node0, ecode);
                 const int64_t d = dem.leg_dfx[l];
                 for (int hops = 0; u != q && hops <= n; ++hops) {
                     if (I.rule == RULE_CEIL && tau >= I.dt32) break;
@@ -970,7 +1089,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                     if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
                     tau = nt;
                     u = net.col[e];
-                    du = lab[(int64_t)(u - node0) * sb];
+                    du = lab_val(lab, u - node0, ecode);
                 }
                 fl.int_node[l] = -1;
                 finish_leg(o, l, u, q, qi, inst, node0, d);
@@ -980,48 +1099,50 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
     }
 }
 
-hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
+hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
                            unsigned long long* r_count, unsigned long long* done_fx, int trees_mode,
-                           int32_t* succ_out, int32_t n_out) {
+                           int32_t* succ_out, int32_t n_out, uint32_t ecode) {
     if (dem.Q == 0) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_orig, r_dest, r_w, r_count, done_fx};
     hipLaunchKernelGGL(k_fallback, dim3(slots), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost, st, fl, scr,
-                       o, trees_mode, succ_out, n_out);
+                       o, trees_mode, succ_out, n_out, ecode);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Parity output of trees: dist[t][v], succ[t][v] (local uid)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_trees_out(NetDev net, DemDev dem, const float* __restrict__ labels,
+__global__ __launch_bounds__(kWG) void k_trees_out(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                                    const float* __restrict__ cost, int32_t inst, float* dist,
-                                                   int32_t* succ, int32_t* absorb_q) {
+                                                   int32_t* succ, int32_t* absorb_q, uint32_t ecode) {
     const InstDev I = net.inst[inst];
     const int n = I.n;
     const int64_t total = (int64_t)dem.Q * n;
     for (int64_t i = blockIdx.x * (int64_t)kWG + threadIdx.x; i < total; i += (int64_t)gridDim.x * kWG) {
         const int t = (int)(i / n);
         const int v = (int)(i - (int64_t)t * n);
-        const float* lab = labels + dem.dest_lab[t];
-        const float dv = lab[(int64_t)v * dem.sb];
+        const label_t* lab = labels + dem.dest_lab[t];
+        const float dv = lab_val(lab, v, ecode);
         dist[i] = dv;
         const int g = I.node0 + v;
         int e = -1;
         if (g != dem.dest_node[t] && dv <= 3.4028234663852886e38f) {
-            e = succ_strict(net, lab, dem.sb, I.node0, g, dv, cost);   // cost: global link order
+            e = succ_strict(net, lab, ecode, I.node0, g, dv, cost);   // cost: global link order
             if (e < 0) absorb_q[t] = 1;
         }
         succ[i] = e >= 0 ? e - I.link0 : -1;
     }
 }
 
-hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const float* labels,
-                            const float* cost, int32_t inst, float* dist, int32_t* succ, int32_t* absorb_q) {
+hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
+                            const float* cost, int32_t inst, float* dist, int32_t* succ, int32_t* absorb_q,
+                            uint32_t ecode) {
     if (dem.Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trees_out, dim3(2048), dim3(kWG), 0, s, net, dem, labels, cost, inst, dist, succ, absorb_q);
+    hipLaunchKernelGGL(k_trees_out, dim3(2048), dim3(kWG), 0, s, net, dem, labels, cost, inst, dist, succ, absorb_q,
+                       ecode);
     return hipGetLastError();
 }
 

@@ -67,15 +67,15 @@ struct qdta_ctx {
     int64_t Q = 0, P = 0, nmax = 0;
     int slots = 0, scr_slots = 0;
     int64_t scr_nmax = 0;
-    size_t label_floats = 0;
+    size_t label_count = 0;
     DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q;
     DBuf<int64_t> dest_lab, leg_dfx;
     std::vector<int32_t> h_dest_inst, h_dest_node;
-    DBuf<float> labels;
+    DBuf<label_t> labels;
     DBuf<int32_t> nearq, farq;
-    DBuf<uint32_t> bits;
     DBuf<int32_t> work;
     DBuf<float> delta_inst;
+    DBuf<double> logsum;
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
@@ -92,6 +92,7 @@ struct qdta_ctx {
     DBuf<int32_t> r_orig, r_dest;
     DBuf<int64_t> r_w;
     DBuf<unsigned long long> r_count, done_fx;
+    uint32_t epoch = 0;           // epoch of the last shortest-path launch on `labels`
     InstState* h_st = nullptr;    // pinned mirror
     int h_st_n = 0;
     bool solved = false;
@@ -184,6 +185,10 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 
 int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 16; }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 3.0; }
+// Shortest-path kernel shape (nodes per lane per step, links per lane per
+// chunk): 0 (1,4), 1 (2,4), 2 (4,4), 3 (4,8), 4 (8,8), 5 (1,1).  reserved[0]
+// of the options selects it; -1 there means the default.
+int sssp_variant(const qdta_opts* o) { return (o->reserved[0] >= 1 && o->reserved[0] <= 6) ? o->reserved[0] - 1 : 2; }
 
 // ---------------------------------------------------------------------------
 // network layout: instances concatenated, reverse CSR, link chunks
@@ -299,7 +304,7 @@ NetDev net_view(qdta_ctx* c) {
     return v;
 }
 
-// Trees are stored tree-major: destination t's labels occupy n floats at
+// Trees are stored tree-major: destination t's labels occupy n label words at
 // dest_lab[t].  Destinations of an instance are in ascending node order.
 int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
     int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1), (int64_t)c->cus * wpc);
@@ -310,12 +315,12 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
         int64_t ns = std::max<int64_t>(slots, c->scr_slots), nm = std::max<int64_t>(nmax, c->scr_nmax);
         RC(dalloc(c, c->nearq, (size_t)ns * nm));
         RC(dalloc(c, c->farq, (size_t)ns * nm * 2));
-        RC(dalloc(c, c->bits, (size_t)ns * ((nm + 31) / 32)));
         c->scr_slots = (int)ns;
         c->scr_nmax = nm;
     }
     RC(dalloc(c, c->work, 1));
     RC(dalloc(c, c->delta_inst, c->inst.size()));
+    RC(dalloc(c, c->logsum, c->inst.size()));
     return QDTA_OK;
 }
 
@@ -362,7 +367,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     c->Q = (int64_t)dest_node.size();
     c->P = (int64_t)leg_orig.size();
     c->nmax = nmax;
-    c->label_floats = (size_t)lab;
+    c->label_count = (size_t)lab;
     c->h_dest_inst = dest_inst;
     c->h_dest_node = dest_node;
     RC(upload(c, c->dest_node, dest_node));
@@ -373,7 +378,11 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     RC(upload(c, c->leg_dfx, leg_dfx));
     RC(upload(c, c->leg_q, leg_q));
     RC(upload(c, c->d_inst, c->h_inst));
-    RC(dalloc(c, c->labels, c->label_floats));
+    {
+        label_t* before = c->labels.p;
+        RC(dalloc(c, c->labels, c->label_count));
+        if (c->labels.p != before) c->epoch = 0;      // fresh memory: reset on the next launch
+    }
     RC(dalloc(c, c->absorb_q, (size_t)c->Q));
     RC(dalloc(c, c->int_node, (size_t)c->P));
     RC(dalloc(c, c->int_tau, (size_t)c->P));
@@ -409,7 +418,6 @@ DemDev dem_view(qdta_ctx* c) {
     v.leg_q = c->leg_q.p;
     v.Q = (int32_t)c->Q;
     v.P = (int32_t)c->P;
-    v.sb = 1;
     return v;
 }
 
@@ -417,9 +425,7 @@ Scratch scr_view(qdta_ctx* c) {
     Scratch s;
     s.nearq = c->nearq.p;
     s.farq = c->farq.p;
-    s.bits = c->bits.p;
     s.nmax = c->scr_nmax;
-    s.nwords = (c->scr_nmax + 31) / 32;
     s.work = c->work.p;
     return s;
 }
@@ -443,6 +449,18 @@ int clear_flags(qdta_ctx* c) {
 int read_flags(qdta_ctx* c, int* h) {
     HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return QDTA_OK;
+}
+
+// A new epoch for the next shortest-path launch on the label buffer; after
+// kMaxEpoch launches the buffer is reset to the oldest epoch (all ones).
+int next_epoch(qdta_ctx* c, DBuf<label_t>& lab, uint32_t& epoch, uint32_t* ecode) {
+    if (epoch == 0 || epoch >= kMaxEpoch) {
+        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(lab.p), -1, (int64_t)lab.n));
+        epoch = 0;
+    }
+    epoch += 1;
+    *ecode = 0x7fffffffu - epoch;
     return QDTA_OK;
 }
 
@@ -476,18 +494,20 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
     FlagsDev fl = flags_view(c);
+    uint32_t ecode;
+    RC(next_epoch(c, c->labels, c->epoch, &ecode));
     RC(prof_mark(c, PH_SSSP, 0));
     HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->rcost.p, c->labels.p, scr_view(c), c->slots, st,
-                            delta_scale(o), c->delta_inst.p));
+                            delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
     RC(prof_mark(c, PH_SSSP, 1));
     RC(prof_mark(c, PH_WALK, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, y, 0, c->M));
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
     HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
-                            nullptr, nullptr, nullptr, nullptr));
+                            nullptr, nullptr, nullptr, nullptr, ecode));
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
                                 (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0));
+                                nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0, ecode));
     RC(prof_mark(c, PH_WALK, 1));
     return QDTA_OK;
 }
@@ -829,7 +849,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     }
     DBuf<int32_t> ddn, ddi, aq;
     DBuf<int64_t> ddl;
-    DBuf<float> lab;
+    DBuf<label_t> lab;
     auto cleanup = [&]() {
         for (void* p : {(void*)ddn.p, (void*)ddi.p, (void*)aq.p, (void*)ddl.p, (void*)lab.p}) {
             if (!p) continue;
@@ -855,7 +875,6 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         dem.dest_inst = ddi.p;
         dem.dest_lab = ddl.p;
         dem.Q = nq;
-        dem.sb = 1;
         NetDev net = net_view(c);
         hipError_t e;
         // place the instance's costs in the global link order
@@ -863,18 +882,20 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
             { rc = set_err(c, QDTA_EHIP, "copy cost: %s", hipGetErrorString(e)); break; }
         if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p)))
             { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
+        uint32_t ecode, tep = 0;
+        if ((rc = next_epoch(c, lab, tep, &ecode))) break;
         if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->rcost.p, lab.p, scr_view(c), slots, nullptr,
-                             delta_scale(o), c->delta_inst.p)))
+                             delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 0)))
             { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
         if ((e = launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(aq.p), 0u, nq)))
             { rc = set_err(c, QDTA_EHIP, "fill: %s", hipGetErrorString(e)); break; }
-        if ((e = launch_trees_out(c->stream, net, dem, lab.p, c->cost.p, inst, dist, succ, aq.p)))
+        if ((e = launch_trees_out(c->stream, net, dem, lab.p, c->cost.p, inst, dist, succ, aq.p, ecode)))
             { rc = set_err(c, QDTA_EHIP, "trees_out: %s", hipGetErrorString(e)); break; }
         FlagsDev fl = flags_view(c);
         fl.absorb_q = aq.p;
         if ((e = launch_fallback(c->stream, net, dem, lab.p, c->cost.p, c->cost.p, nullptr, nullptr, nullptr, fl,
                                  scr_view(c), (int)std::min<int64_t>(c->scr_slots, nq), 0, nullptr, nullptr, nullptr,
-                                 nullptr, nullptr, nullptr, 1, succ, I.n)))
+                                 nullptr, nullptr, nullptr, 1, succ, I.n, ecode)))
             { rc = set_err(c, QDTA_EHIP, "fallback: %s", hipGetErrorString(e)); break; }
         std::vector<int32_t> ha(nq);
         if ((e = hipMemcpyAsync(ha.data(), aq.p, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, c->stream)))
@@ -1196,16 +1217,18 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         HIPCHECK(c, hipMemcpyAsync(c->lambda.p, lam.data(), sizeof(double) * ni, hipMemcpyHostToDevice, c->stream));
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
         HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->rcost.p));
+        uint32_t ecode;
+        RC(next_epoch(c, c->labels, c->epoch, &ecode));
         HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->rcost.p, c->labels.p, scr_view(c), c->slots, c->st.p,
-                                delta_scale(o), c->delta_inst.p));
+                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
         HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->r_count.p), 0, 1));
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
         HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl, 1,
-                                c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p));
+                                c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p, ecode));
         HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl,
                                     scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
                                     c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p, 0,
-                                    nullptr, 0));
+                                    nullptr, 0, ecode));
         unsigned long long cnt = 0;
         HIPCHECK(c, hipMemcpyAsync(&cnt, c->r_count.p, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
         HIPCHECK(c, hipStreamSynchronize(c->stream));
