@@ -101,7 +101,7 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t count
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t count);
 
 hipError_t launch_bpr(hipStream_t s, const NetDev& net, const int64_t* f, double alpha, int beta,
-                      float* cost, float* rcost, const InstState* st, int only_active, int* err);
+                      float* cost, uint2* radj, const InstState* st, int only_active, int* err);
 
 hipError_t launch_gap_sums(hipStream_t s, const NetDev& net, const float* cost, const int64_t* f,
                            const int64_t* y, long long* acc /*[ninst][2][3]*/, const InstState* st, int* err);
@@ -134,9 +134,9 @@ hipError_t launch_fw_update(hipStream_t s, const NetDev& net, int64_t* f, const 
 
 hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, double* out);
 hipError_t launch_after_update(hipStream_t s, int ninst, InstState* st);
-hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, float* rcost);
+hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, uint2* radj);
 
-hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const float* rcost,
+hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
                        float* delta_inst, double* logsum, int variant, uint32_t ecode, int early);
 

@@ -156,7 +156,7 @@ __device__ __forceinline__ bool inst_live(const InstState* st, int i) {
 }
 
 __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restrict__ f, double alpha, int beta,
-                                             float* __restrict__ cost, float* __restrict__ rcost,
+                                             float* __restrict__ cost, uint2* __restrict__ radj,
                                              const InstState* st, int only_active, int* err) {
     const int b = blockIdx.x;
     const int inst = net.blk_inst[b];
@@ -170,15 +170,15 @@ __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restri
         float c32 = (float)c;
         if (!(c32 <= 3.4028234663852886e38f)) bad = 1;
         cost[a] = c32;
-        if (rcost) rcost[net.revpos[a]] = c32;
+        if (radj) radj[net.revpos[a]].y = __float_as_uint(c32);
     }
     if (bad) atomicOr(err, 1);
 }
 
 hipError_t launch_bpr(hipStream_t s, const NetDev& net, const int64_t* f, double alpha, int beta, float* cost,
-                      float* rcost, const InstState* st, int only_active, int* err) {
+                      uint2* radj, const InstState* st, int only_active, int* err) {
     if (net.nblk == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bpr, dim3(net.nblk), dim3(kWG), 0, s, net, f, alpha, beta, cost, rcost, st, only_active,
+    hipLaunchKernelGGL(k_bpr, dim3(net.nblk), dim3(kWG), 0, s, net, f, alpha, beta, cost, radj, st, only_active,
                        err);
     return hipGetLastError();
 }
@@ -536,15 +536,17 @@ hipError_t launch_fw_update(hipStream_t s, const NetDev& net, int64_t* f, const 
     return hipGetLastError();
 }
 
+// Costs into the reverse adjacency records (source node, cost) read by the
+// shortest-path kernel: one 8-byte record per in-link.
 __global__ __launch_bounds__(kWG) void k_scatter_rcost(NetDev net, const float* __restrict__ cost,
-                                                       float* __restrict__ rcost) {
+                                                       uint2* __restrict__ radj) {
     for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG)
-        rcost[net.revpos[a]] = cost[a];
+        radj[net.revpos[a]].y = __float_as_uint(cost[a]);
 }
 
-hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, float* rcost) {
+hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, uint2* radj) {
     if (net.M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter_rcost, dim3(grid_for(net.M)), dim3(kWG), 0, s, net, cost, rcost);
+    hipLaunchKernelGGL(k_scatter_rcost, dim3(grid_for(net.M)), dim3(kWG), 0, s, net, cost, radj);
     return hipGetLastError();
 }
 
@@ -628,7 +630,7 @@ __device__ __forceinline__ float wave_min(float x) {
 // early: stop a tree once every origin of its legs is settled (AON and
 // residual walks read nothing beyond); 0 builds complete trees.
 template <int U, int V>
-__global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const float* __restrict__ rcost,
+__global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const uint2* __restrict__ radj,
                                                  label_t* labels, Scratch scr, const InstState* st,
                                                  const float* __restrict__ delta_inst, uint32_t ecode, int early) {
     constexpr int W = kWG / 64;
@@ -725,8 +727,9 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const f
                                 if (pre[mid] <= g) lo = mid; else hi = mid;
                             }
                             const int e = se0[lo] + (g - pre[lo]);
-                            vv[x] = net.rsrc[e] - node0;
-                            cd[x] = sdw[lo] + rcost[e];
+                            const uint2 r = radj[e];
+                            vv[x] = (int)r.x - node0;
+                            cd[x] = sdw[lo] + __uint_as_float(r.y);
                         }
                     }
                     uint32_t cur[V];
@@ -874,7 +877,7 @@ __global__ void k_delta(NetDev net, const double* logsum, double scale, float* d
     delta_inst[inst] = (float)d;
 }
 
-hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const float* rcost,
+hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
                        float* delta_inst, double* logsum, int variant, uint32_t ecode, int early) {
     if (dem.Q == 0) return hipSuccess;
@@ -887,12 +890,12 @@ hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, cons
     const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
     dim3 g(blocks), b(kWG);
     switch (variant) {
-        case 0: hipLaunchKernelGGL((k_sssp_ds<1, 4>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
-        case 1: hipLaunchKernelGGL((k_sssp_ds<2, 4>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
-        case 2: hipLaunchKernelGGL((k_sssp_ds<4, 4>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
-        case 3: hipLaunchKernelGGL((k_sssp_ds<4, 8>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
-        case 4: hipLaunchKernelGGL((k_sssp_ds<8, 8>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
-        default: hipLaunchKernelGGL((k_sssp_ds<1, 1>), g, b, 0, s, net, dem, rcost, labels, scr, st, delta_inst, ecode, early); break;
+        case 0: hipLaunchKernelGGL((k_sssp_ds<1, 4>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
+        case 1: hipLaunchKernelGGL((k_sssp_ds<2, 4>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
+        case 2: hipLaunchKernelGGL((k_sssp_ds<4, 4>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
+        case 3: hipLaunchKernelGGL((k_sssp_ds<4, 8>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
+        case 4: hipLaunchKernelGGL((k_sssp_ds<8, 8>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
+        default: hipLaunchKernelGGL((k_sssp_ds<1, 1>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
     }
     return hipGetLastError();
 }

@@ -79,7 +79,8 @@ struct qdta_ctx {
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
-    DBuf<float> cost, rcost, cfin;
+    DBuf<float> cost, cfin;
+    DBuf<uint2> radj;             // reverse adjacency records (source node, cost)
     DBuf<InstState> st;
     DBuf<long long> acc, ls_acc;
     DBuf<double> alphas, alpha_arr, lambda;
@@ -184,7 +185,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 }
 
 int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 16; }
-double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 3.0; }
+double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 5.0; }
 // Shortest-path kernel shape (nodes per lane per step, links per lane per
 // chunk): 0 (1,4), 1 (2,4), 2 (4,4), 3 (4,8), 4 (8,8), 5 (1,1).  reserved[0]
 // of the options selects it; -1 there means the default.
@@ -263,7 +264,11 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->f, c->M));
     RC(dalloc(c, c->y, c->M));
     RC(dalloc(c, c->cost, c->M));
-    RC(dalloc(c, c->rcost, c->M));
+    {
+        std::vector<uint2> ra(c->M);
+        for (int64_t k = 0; k < c->M; ++k) ra[k] = make_uint2((uint32_t)rsrc[k], 0u);
+        RC(upload(c, c->radj, ra));
+    }
     RC(dalloc(c, c->cfin, c->M));
     RC(dalloc(c, c->st, ni));
     RC(dalloc(c, c->acc, (size_t)ni * 6));
@@ -489,7 +494,7 @@ void prof_collect(qdta_ctx* c) {
     }
 }
 
-// One all-or-nothing assignment (A2 + A3) under `cost` (rcost already set).
+// One all-or-nothing assignment (A2 + A3) under `cost` (reverse records already set).
 int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop, const InstState* st) {
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
@@ -497,7 +502,7 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     uint32_t ecode;
     RC(next_epoch(c, c->labels, c->epoch, &ecode));
     RC(prof_mark(c, PH_SSSP, 0));
-    HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->rcost.p, c->labels.p, scr_view(c), c->slots, st,
+    HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->radj.p, c->labels.p, scr_view(c), c->slots, st,
                             delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
     RC(prof_mark(c, PH_SSSP, 1));
     RC(prof_mark(c, PH_WALK, 0));
@@ -880,11 +885,11 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         // place the instance's costs in the global link order
         if ((e = hipMemcpyAsync(c->cost.p + I.link0, cost, sizeof(float) * I.m, hipMemcpyDeviceToDevice, c->stream)))
             { rc = set_err(c, QDTA_EHIP, "copy cost: %s", hipGetErrorString(e)); break; }
-        if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p)))
+        if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p)))
             { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
         uint32_t ecode, tep = 0;
         if ((rc = next_epoch(c, lab, tep, &ecode))) break;
-        if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->rcost.p, lab.p, scr_view(c), slots, nullptr,
+        if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, lab.p, scr_view(c), slots, nullptr,
                              delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 0)))
             { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
         if ((e = launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(aq.p), 0u, nq)))
@@ -920,7 +925,7 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     RC(clear_flags(c));
     NetDev net = net_view(c);
     HIPCHECK(c, hipMemcpyAsync(c->cost.p, cost, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHECK(c, launch_scatter_rcost(c->stream, net, c->cost.p, c->rcost.p));
+    HIPCHECK(c, launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p));
     if (stop) HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(stop), 0xffffffffu, c->P));
     RC(aon_core(c, o, c->cost.p, y, stop, nullptr));
     int h[4];
@@ -997,7 +1002,7 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     // initial AON at free flow: BPR(0) = c0 exactly (first step of Alg. 6)
     HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
     RC(prof_mark(c, PH_BPR, 0));
-    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, c->flags.p));
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, c->flags.p));
     RC(prof_mark(c, PH_BPR, 1));
     RC(aon_core(c, o, c->cost.p, c->f.p, nullptr, c->st.p));
     if (o->keep_history)
@@ -1038,7 +1043,7 @@ int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
     const int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
     const int j = ++c->fw_j;
     RC(prof_mark(c, PH_BPR, 0));
-    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->rcost.p, c->st.p, 1, err));
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, err));
     RC(prof_mark(c, PH_BPR, 1));
     RC(aon_core(c, o, c->cost.p, c->y.p, nullptr, c->st.p));
     RC(prof_mark(c, PH_GAP, 0));
@@ -1216,10 +1221,10 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         HIPCHECK(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(InstState) * ni, hipMemcpyHostToDevice, c->stream));
         HIPCHECK(c, hipMemcpyAsync(c->lambda.p, lam.data(), sizeof(double) * ni, hipMemcpyHostToDevice, c->stream));
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
-        HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->rcost.p));
+        HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
         uint32_t ecode;
         RC(next_epoch(c, c->labels, c->epoch, &ecode));
-        HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->rcost.p, c->labels.p, scr_view(c), c->slots, c->st.p,
+        HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, c->st.p,
                                 delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
         HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->r_count.p), 0, 1));
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
