@@ -92,7 +92,13 @@ typedef struct {
     double delta_scale;    /* delta-stepping bucket width as a multiple of the instance's geometric-mean
                               link cost: 0 auto (5.0); any value > 0 gives the same trees, only the speed
                               changes */
-    int32_t reserved[4];
+    int32_t sssp_shape;    /* shortest-path kernel shape, nodes per lane per step x links per lane per
+                              chunk: 0 auto, 1 (1,4), 2 (2,4), 3 (4,4), 4 (4,8), 5 (8,8), 6 (1,1) */
+    int32_t launch_form;   /* 0 batched: every tree of every instance in one launch, all K step sizes in
+                              one pass, one FW iteration replayed as a captured HIP graph when possible
+                              (K-section or MSA); 1 batched with direct launches; 2 plain: one launch per
+                              destination tree and per step size (same results, for comparison) */
+    int32_t reserved[2];
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */
@@ -246,7 +252,8 @@ int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host
  * phase of the Frank-Wolfe iteration; durations are added at the iteration's
  * synchronisation.  Phases: 0 BPR costs, 1 shortest-path trees, 2 loading
  * walk (with the tie fallback), 3 gap sums and stop test, 4 line search,
- * 5 flow update.  qdta_profile_enable(ctx, 1) resets and starts the timers,
+ * 5 flow update, 6 a whole iteration replayed as a HIP graph (the phases
+ * inside a graph are not timed separately).  qdta_profile_enable(ctx, 1) resets and starts the timers,
  * 0 stops them; qdta_profile_read copies the totals (host output). */
 typedef struct {
     double ms[8];        /* summed duration per phase, milliseconds */

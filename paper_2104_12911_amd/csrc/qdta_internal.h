@@ -107,14 +107,15 @@ hipError_t launch_gap_sums(hipStream_t s, const NetDev& net, const float* cost, 
                            const int64_t* y, long long* acc /*[ninst][2][3]*/, const InstState* st, int* err);
 
 hipError_t launch_gap_decide(hipStream_t s, int ninst, const long long* acc, InstState* st, int stop_rule,
-                             double tol, int fixed_iters, int cap_iter, int j);
+                             double tol, int fixed_iters, int cap_iter);
+hipError_t launch_epoch_next(hipStream_t s, uint32_t* ecode);
 
 hipError_t launch_ls_begin(hipStream_t s, int ninst, InstState* st, double* alphas, int K, int ls_mode,
                            double dx, long long* ls_acc, int only_fallback);
 
 hipError_t launch_ls_eval(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
                           double alpha_b, int beta, int K, const double* alphas, long long* ls_acc,
-                          const InstState* st, int only_pending, int* err);
+                          const InstState* st, int only_pending, int* err, int k0 = 0, int kstride = 0);
 
 hipError_t launch_ls_decide(hipStream_t s, int ninst, InstState* st, double* alphas, int K, int ls_mode,
                             int passes, int max_ls, double T1, double T2, double dx, long long* ls_acc);
@@ -136,26 +137,31 @@ hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, doub
 hipError_t launch_after_update(hipStream_t s, int ninst, InstState* st);
 hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, uint2* radj);
 
+hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, double delta_scale, float* delta_inst,
+                        double* logsum);
+hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, const uint2* radj, label_t* labels,
+                        const Scratch& scr, int slots, const InstState* st, const float* delta_inst, int variant,
+                        const uint32_t* ecode, int early, int t_begin, int t_end);
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst, double* logsum, int variant, uint32_t ecode, int early);
+                       float* delta_inst, double* logsum, int variant, const uint32_t* ecode, int early);
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int32_t* r_orig, int32_t* r_dest, int64_t* r_w, unsigned long long* r_count,
-                       unsigned long long* done_fx, uint32_t ecode);
+                       unsigned long long* done_fx, const uint32_t* ecode, int l_begin = 0, int l_end = -1);
 
 hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
                            unsigned long long* r_count, unsigned long long* done_fx,
-                           int trees_mode, int32_t* succ_out, int32_t n_out, uint32_t ecode);
+                           int trees_mode, int32_t* succ_out, int32_t n_out, const uint32_t* ecode);
 
 hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                             const float* cost_local, int32_t inst, float* dist, int32_t* succ,
                             int32_t* absorb_q,
-                            uint32_t ecode);
+                            const uint32_t* ecode);
 
 }  // namespace qdta

@@ -216,13 +216,15 @@ hipError_t launch_gap_sums(hipStream_t s, const NetDev& net, const float* cost, 
 }
 
 // Stop test of iteration j (Alg. 6): relative gap, or the iteration cap.
+// Also advances the iteration index j of each live instance, so a captured
+// iteration replays with the right j.
 __global__ void k_gap_decide(int ninst, const long long* acc, InstState* st, int stop_rule, double tol,
-                             int fixed_iters, int cap_iter, int j) {
+                             int fixed_iters, int cap_iter) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst) return;
     InstState& S = st[i];
     if (!S.active || S.converged) return;
-    S.iter = j;
+    S.iter += 1;
     i128 scf = acc3_value(acc + i * 6), scy = acc3_value(acc + i * 6 + 3);
     S.gap = (double)(scf - scy) / (double)scf;
     if (fixed_iters <= 0 && stop_rule == 0 && __builtin_fabs(S.gap) < tol) {
@@ -235,9 +237,9 @@ __global__ void k_gap_decide(int ninst, const long long* acc, InstState* st, int
 }
 
 hipError_t launch_gap_decide(hipStream_t s, int ninst, const long long* acc, InstState* st, int stop_rule,
-                             double tol, int fixed_iters, int cap_iter, int j) {
+                             double tol, int fixed_iters, int cap_iter) {
     hipLaunchKernelGGL(k_gap_decide, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, acc, st, stop_rule, tol,
-                       fixed_iters, cap_iter, j);
+                       fixed_iters, cap_iter);
     return hipGetLastError();
 }
 
@@ -289,7 +291,7 @@ template <int GK>
 __global__ __launch_bounds__(kWG) void k_ls_eval(NetDev net, const int64_t* __restrict__ f,
                                                  const int64_t* __restrict__ y, double alpha_b, int beta, int K,
                                                  const double* __restrict__ alphas, long long* ls_acc,
-                                                 const InstState* st, int only_pending, int* err) {
+                                                 const InstState* st, int only_pending, int* err, int k0, int kstride) {
     __shared__ i128 ldsC[kWG];
     __shared__ i128 ldsD[kWG];
     constexpr int LPB = kWG / GK;
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(kWG) void k_ls_eval(NetDev net, const int64_t* __re
     const int k = threadIdx.x % GK;
     const int g = threadIdx.x / GK;
     const bool live = k < K;
-    const double alpha = live ? alphas[(long long)inst * K + k] : 0.0;
+    const double alpha = live ? alphas[(long long)inst * kstride + k0 + k] : 0.0;
     i128 sc = 0, sd = 0;
     int bad = 0;
     if (live) {
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(kWG) void k_ls_eval(NetDev net, const int64_t* __re
         __syncthreads();
     }
     if (g == 0 && live) {
-        long long* acc = ls_acc + ((long long)inst * K + k) * 6;
+        long long* acc = ls_acc + ((long long)inst * kstride + k0 + k) * 6;
         if (ldsC[threadIdx.x] != 0) acc3_add(acc, ldsC[threadIdx.x]);
         if (ldsD[threadIdx.x] != 0) acc3_add(acc + 3, ldsD[threadIdx.x]);
     }
@@ -334,24 +336,28 @@ __global__ __launch_bounds__(kWG) void k_ls_eval(NetDev net, const int64_t* __re
 
 hipError_t launch_ls_eval(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y, double alpha_b,
                           int beta, int K, const double* alphas, long long* ls_acc, const InstState* st,
-                          int only_pending, int* err) {
+                          int only_pending, int* err, int k0, int kstride) {
     if (net.nblk == 0) return hipSuccess;
+    if (kstride <= 0) kstride = K;
     dim3 g(net.nblk), blk(kWG);
-    if (K <= 4)
+    if (K <= 1)
+        hipLaunchKernelGGL(k_ls_eval<1>, g, blk, 0, s, net, f, y, alpha_b, beta, K, alphas, ls_acc, st, only_pending,
+                           err, k0, kstride);
+    else if (K <= 4)
         hipLaunchKernelGGL(k_ls_eval<4>, g, blk, 0, s, net, f, y, alpha_b, beta, K, alphas, ls_acc, st, only_pending,
-                           err);
+                           err, k0, kstride);
     else if (K <= 8)
         hipLaunchKernelGGL(k_ls_eval<8>, g, blk, 0, s, net, f, y, alpha_b, beta, K, alphas, ls_acc, st, only_pending,
-                           err);
+                           err, k0, kstride);
     else if (K <= 16)
         hipLaunchKernelGGL(k_ls_eval<16>, g, blk, 0, s, net, f, y, alpha_b, beta, K, alphas, ls_acc, st,
-                           only_pending, err);
+                           only_pending, err, k0, kstride);
     else if (K <= 32)
         hipLaunchKernelGGL(k_ls_eval<32>, g, blk, 0, s, net, f, y, alpha_b, beta, K, alphas, ls_acc, st,
-                           only_pending, err);
+                           only_pending, err, k0, kstride);
     else
         hipLaunchKernelGGL(k_ls_eval<64>, g, blk, 0, s, net, f, y, alpha_b, beta, K, alphas, ls_acc, st,
-                           only_pending, err);
+                           only_pending, err, k0, kstride);
     return hipGetLastError();
 }
 
@@ -632,8 +638,10 @@ __device__ __forceinline__ float wave_min(float x) {
 template <int U, int V>
 __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const uint2* __restrict__ radj,
                                                  label_t* labels, Scratch scr, const InstState* st,
-                                                 const float* __restrict__ delta_inst, uint32_t ecode, int early) {
+                                                 const float* __restrict__ delta_inst, const uint32_t* ecode_p,
+                                                 int early, int t_begin, int t_end) {
     constexpr int W = kWG / 64;
+    const uint32_t ecode = *ecode_p;
     constexpr int NP = 64 * U;                    // nodes per step
     __shared__ int s_pre[W][NP + 1];
     __shared__ float s_dw[W][NP];
@@ -650,9 +658,9 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
 
     for (;;) {
         int t = 0;
-        if (lane == 0) t = atomicAdd(scr.work, 1);
+        if (lane == 0) t = t_begin + atomicAdd(scr.work, 1);
         t = __shfl(t, 0);
-        if (t >= dem.Q) break;
+        if (t >= t_end) break;
         const int inst = dem.dest_inst[t];
         if (!inst_live(st, inst)) continue;
         const InstDev I = net.inst[inst];
@@ -877,27 +885,54 @@ __global__ void k_delta(NetDev net, const double* logsum, double scale, float* d
     delta_inst[inst] = (float)d;
 }
 
-hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
-                       label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst, double* logsum, int variant, uint32_t ecode, int early) {
-    if (dem.Q == 0) return hipSuccess;
+// Next label epoch: the code 0x7fffffff - epoch is kept in device memory so
+// a captured iteration advances it on every replay.
+__global__ void k_epoch_next(uint32_t* ecode) { *ecode = *ecode - 1u; }
+
+hipError_t launch_epoch_next(hipStream_t s, uint32_t* ecode) {
+    hipLaunchKernelGGL(k_epoch_next, dim3(1), dim3(1), 0, s, ecode);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, double delta_scale, float* delta_inst,
+                        double* logsum) {
     hipError_t e0 = launch_fill_i64(s, reinterpret_cast<int64_t*>(logsum), 0, net.ninst);
     if (e0 != hipSuccess) return e0;
     if (net.nblk > 0) hipLaunchKernelGGL(k_logcost, dim3(net.nblk), dim3(kWG), 0, s, net, cost, logsum);
     hipLaunchKernelGGL(k_delta, dim3((net.ninst + 63) / 64), dim3(64), 0, s, net, logsum, delta_scale, delta_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, const uint2* radj, label_t* labels,
+                        const Scratch& scr, int slots, const InstState* st, const float* delta_inst, int variant,
+                        const uint32_t* ecode, int early, int t_begin, int t_end) {
+    if (t_end <= t_begin) return hipSuccess;
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
     const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
     dim3 g(blocks), b(kWG);
+#define QDTA_SSSP(U, V) \
+    hipLaunchKernelGGL((k_sssp_ds<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early, \
+                       t_begin, t_end)
     switch (variant) {
-        case 0: hipLaunchKernelGGL((k_sssp_ds<1, 4>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
-        case 1: hipLaunchKernelGGL((k_sssp_ds<2, 4>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
-        case 2: hipLaunchKernelGGL((k_sssp_ds<4, 4>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
-        case 3: hipLaunchKernelGGL((k_sssp_ds<4, 8>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
-        case 4: hipLaunchKernelGGL((k_sssp_ds<8, 8>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
-        default: hipLaunchKernelGGL((k_sssp_ds<1, 1>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early); break;
+        case 0: QDTA_SSSP(1, 4); break;
+        case 1: QDTA_SSSP(2, 4); break;
+        case 2: QDTA_SSSP(4, 4); break;
+        case 3: QDTA_SSSP(4, 8); break;
+        case 4: QDTA_SSSP(8, 8); break;
+        default: QDTA_SSSP(1, 1); break;
     }
+#undef QDTA_SSSP
     return hipGetLastError();
+}
+
+hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
+                       label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
+                       float* delta_inst, double* logsum, int variant, const uint32_t* ecode, int early) {
+    if (dem.Q == 0) return hipSuccess;
+    hipError_t e = launch_delta(s, net, cost, delta_scale, delta_inst, logsum);
+    if (e != hipSuccess) return e;
+    return launch_trees(s, net, dem, radj, labels, scr, slots, st, delta_inst, variant, ecode, early, 0, dem.Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -949,9 +984,10 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                               const float* __restrict__ tree_cost,
                                               const float* __restrict__ time_cost, const InstState* st,
-                                              FlagsDev fl, WalkOut o, uint32_t ecode) {
-    const int l = blockIdx.x * kWG + threadIdx.x;
-    if (l >= dem.P) return;
+                                              FlagsDev fl, WalkOut o, const uint32_t* ecode_p, int l_begin, int l_end) {
+    const int l = l_begin + blockIdx.x * kWG + threadIdx.x;
+    const uint32_t ecode = *ecode_p;
+    if (l >= l_end) return;
     const int qi = dem.leg_q[l];
     const int inst = dem.dest_inst[qi];
     if (!inst_live(st, inst)) return;
@@ -993,11 +1029,12 @@ hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, cons
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda, int32_t* r_orig,
                        int32_t* r_dest, int64_t* r_w, unsigned long long* r_count, unsigned long long* done_fx,
-                       uint32_t ecode) {
-    if (dem.P == 0) return hipSuccess;
+                       const uint32_t* ecode, int l_begin, int l_end) {
+    if (l_end < 0) l_end = dem.P;
+    if (l_end <= l_begin) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_orig, r_dest, r_w, r_count, done_fx};
-    hipLaunchKernelGGL(k_walk, dim3((dem.P + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost,
-                       st, fl, o, ecode);
+    hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, tree_cost,
+                       time_cost, st, fl, o, ecode, l_begin, l_end);
     return hipGetLastError();
 }
 
@@ -1013,8 +1050,9 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                                                   const float* __restrict__ tree_cost,
                                                   const float* __restrict__ time_cost, const InstState* st,
                                                   FlagsDev fl, Scratch scr, WalkOut o, int trees_mode,
-                                                  int32_t* succ_out, int32_t n_out, uint32_t ecode) {
+                                                  int32_t* succ_out, int32_t n_out, const uint32_t* ecode_p) {
     __shared__ int s_cnt[2];
+    const uint32_t ecode = *ecode_p;
     int32_t* hop = scr.farq + (int64_t)blockIdx.x * scr.nmax;
     int32_t* qbase = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
     for (int qi = blockIdx.x; qi < dem.Q; qi += gridDim.x) {
@@ -1107,7 +1145,7 @@ hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, 
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
                            unsigned long long* r_count, unsigned long long* done_fx, int trees_mode,
-                           int32_t* succ_out, int32_t n_out, uint32_t ecode) {
+                           int32_t* succ_out, int32_t n_out, const uint32_t* ecode) {
     if (dem.Q == 0) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_orig, r_dest, r_w, r_count, done_fx};
     hipLaunchKernelGGL(k_fallback, dim3(slots), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost, st, fl, scr,
@@ -1120,8 +1158,9 @@ hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_trees_out(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                                    const float* __restrict__ cost, int32_t inst, float* dist,
-                                                   int32_t* succ, int32_t* absorb_q, uint32_t ecode) {
+                                                   int32_t* succ, int32_t* absorb_q, const uint32_t* ecode_p) {
     const InstDev I = net.inst[inst];
+    const uint32_t ecode = *ecode_p;
     const int n = I.n;
     const int64_t total = (int64_t)dem.Q * n;
     for (int64_t i = blockIdx.x * (int64_t)kWG + threadIdx.x; i < total; i += (int64_t)gridDim.x * kWG) {
@@ -1142,7 +1181,7 @@ __global__ __launch_bounds__(kWG) void k_trees_out(NetDev net, DemDev dem, const
 
 hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                             const float* cost, int32_t inst, float* dist, int32_t* succ, int32_t* absorb_q,
-                            uint32_t ecode) {
+                            const uint32_t* ecode) {
     if (dem.Q == 0) return hipSuccess;
     hipLaunchKernelGGL(k_trees_out, dim3(2048), dim3(kWG), 0, s, net, dem, labels, cost, inst, dist, succ, absorb_q,
                        ecode);

@@ -70,12 +70,13 @@ struct qdta_ctx {
     size_t label_count = 0;
     DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q;
     DBuf<int64_t> dest_lab, leg_dfx;
-    std::vector<int32_t> h_dest_inst, h_dest_node;
+    std::vector<int32_t> h_dest_inst, h_dest_node, h_qptr;
     DBuf<label_t> labels;
     DBuf<int32_t> nearq, farq;
     DBuf<int32_t> work;
     DBuf<float> delta_inst;
     DBuf<double> logsum;
+    DBuf<uint32_t> ecode;         // [0] epoch code of `labels`, [1] of temporary label buffers
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
@@ -94,6 +95,13 @@ struct qdta_ctx {
     DBuf<int64_t> r_w;
     DBuf<unsigned long long> r_count, done_fx;
     uint32_t epoch = 0;           // epoch of the last shortest-path launch on `labels`
+    uint64_t gen = 0;             // bumped whenever device memory is (re)allocated
+    // captured FW iteration
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_gen = 0;
+    qdta_opts graph_opts;
     InstState* h_st = nullptr;    // pinned mirror
     int h_st_n = 0;
     bool solved = false;
@@ -108,6 +116,8 @@ struct qdta_ctx {
 };
 
 namespace {
+
+void drop_graph(qdta_ctx* c);
 
 int set_err(qdta_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
@@ -144,6 +154,7 @@ int dalloc(qdta_ctx* c, DBuf<T>& b, size_t n) {
     }
     b.n = std::max<size_t>(n, 1);
     c->allocs.push_back((void*)b.p);
+    c->gen++;
     return QDTA_OK;
 }
 
@@ -177,6 +188,8 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     }
     if (o->max_iter < 0 || o->fixed_iters < 0) { set_err(c, QDTA_EARG, "negative iteration count"); return false; }
     if (o->waves_per_cu < 0 || o->waves_per_cu > 32) { set_err(c, QDTA_EARG, "waves_per_cu must be in 0..32"); return false; }
+    if (o->sssp_shape < 0 || o->sssp_shape > 6) { set_err(c, QDTA_EARG, "sssp_shape must be in 0..6"); return false; }
+    if (o->launch_form < 0 || o->launch_form > 2) { set_err(c, QDTA_EARG, "launch_form must be 0, 1 or 2"); return false; }
     if (!(o->delta_scale >= 0.0) || !std::isfinite(o->delta_scale)) {
         set_err(c, QDTA_EARG, "delta_scale must be finite and >= 0");
         return false;
@@ -186,10 +199,8 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 
 int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 16; }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 5.0; }
-// Shortest-path kernel shape (nodes per lane per step, links per lane per
-// chunk): 0 (1,4), 1 (2,4), 2 (4,4), 3 (4,8), 4 (8,8), 5 (1,1).  reserved[0]
-// of the options selects it; -1 there means the default.
-int sssp_variant(const qdta_opts* o) { return (o->reserved[0] >= 1 && o->reserved[0] <= 6) ? o->reserved[0] - 1 : 2; }
+// Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
+int sssp_variant(const qdta_opts* o) { return (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2; }
 
 // ---------------------------------------------------------------------------
 // network layout: instances concatenated, reverse CSR, link chunks
@@ -277,6 +288,7 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->alpha_arr, ni));
     RC(dalloc(c, c->lambda, ni));
     RC(dalloc(c, c->flags, 4));
+    RC(dalloc(c, c->ecode, 2));
     RC(dalloc(c, c->done_fx, ni));
     RC(dalloc(c, c->r_count, 1));
     if (c->h_st_n < ni) {
@@ -375,6 +387,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     c->label_count = (size_t)lab;
     c->h_dest_inst = dest_inst;
     c->h_dest_node = dest_node;
+    c->h_qptr = qptr;
     RC(upload(c, c->dest_node, dest_node));
     RC(upload(c, c->dest_inst, dest_inst));
     RC(upload(c, c->dest_lab, dest_lab));
@@ -457,20 +470,25 @@ int read_flags(qdta_ctx* c, int* h) {
     return QDTA_OK;
 }
 
-// A new epoch for the next shortest-path launch on the label buffer; after
-// kMaxEpoch launches the buffer is reset to the oldest epoch (all ones).
-int next_epoch(qdta_ctx* c, DBuf<label_t>& lab, uint32_t& epoch, uint32_t* ecode) {
+// A new epoch for the next shortest-path launch on a label buffer.  The
+// epoch code (0x7fffffff - epoch) lives in device memory so a captured
+// iteration can advance it; `epoch` counts launches on the host, and after
+// kMaxEpoch of them (or on fresh memory, epoch = 0) the buffer is reset to
+// the oldest epoch (all ones).
+int next_epoch(qdta_ctx* c, DBuf<label_t>& lab, uint32_t& epoch, uint32_t* ecode_dev) {
     if (epoch == 0 || epoch >= kMaxEpoch) {
         HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(lab.p), -1, (int64_t)lab.n));
-        epoch = 0;
+        HIPCHECK(c, launch_fill_u32(c->stream, ecode_dev, 0x7fffffffu - 1u, 1));
+        epoch = 1;
+        return QDTA_OK;
     }
+    HIPCHECK(c, launch_epoch_next(c->stream, ecode_dev));
     epoch += 1;
-    *ecode = 0x7fffffffu - epoch;
     return QDTA_OK;
 }
 
-constexpr int kPhases = 6;
-enum { PH_BPR = 0, PH_SSSP = 1, PH_WALK = 2, PH_GAP = 3, PH_LS = 4, PH_UPDATE = 5 };
+constexpr int kPhases = 7;
+enum { PH_BPR = 0, PH_SSSP = 1, PH_WALK = 2, PH_GAP = 3, PH_LS = 4, PH_UPDATE = 5, PH_GRAPH = 6 };
 
 // Record the start (edge 0) or end (edge 1) of a phase on the stream.
 int prof_mark(qdta_ctx* c, int ph, int edge) {
@@ -495,25 +513,40 @@ void prof_collect(qdta_ctx* c) {
 }
 
 // One all-or-nothing assignment (A2 + A3) under `cost` (reverse records already set).
-int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop, const InstState* st) {
+int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop, const InstState* st,
+             bool marks = true) {
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
     FlagsDev fl = flags_view(c);
-    uint32_t ecode;
-    RC(next_epoch(c, c->labels, c->epoch, &ecode));
-    RC(prof_mark(c, PH_SSSP, 0));
-    HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->radj.p, c->labels.p, scr_view(c), c->slots, st,
-                            delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
-    RC(prof_mark(c, PH_SSSP, 1));
-    RC(prof_mark(c, PH_WALK, 0));
+    uint32_t* ecode = c->ecode.p;
+    RC(next_epoch(c, c->labels, c->epoch, ecode));
+    if (marks) RC(prof_mark(c, PH_SSSP, 0));
+    if (o->launch_form == 2) {
+        // plain form: one launch per destination tree (one workgroup each)
+        HIPCHECK(c, launch_delta(c->stream, net, cost, delta_scale(o), c->delta_inst.p, c->logsum.p));
+        for (int64_t t = 0; t < c->Q; ++t)
+            HIPCHECK(c, launch_trees(c->stream, net, dem, c->radj.p, c->labels.p, scr_view(c), 4, st, c->delta_inst.p,
+                                     sssp_variant(o), ecode, 1, (int)t, (int)t + 1));
+    } else {
+        HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->radj.p, c->labels.p, scr_view(c), c->slots, st,
+                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
+    }
+    if (marks) RC(prof_mark(c, PH_SSSP, 1));
+    if (marks) RC(prof_mark(c, PH_WALK, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, y, 0, c->M));
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
-    HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
-                            nullptr, nullptr, nullptr, nullptr, ecode));
+    if (o->launch_form == 2) {
+        for (int64_t qi = 0; qi < c->Q; ++qi)
+            HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr, ecode, c->h_qptr[qi], c->h_qptr[qi + 1]));
+    } else {
+        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, ecode));
+    }
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
                                 (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
                                 nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0, ecode));
-    RC(prof_mark(c, PH_WALK, 1));
+    if (marks) RC(prof_mark(c, PH_WALK, 1));
     return QDTA_OK;
 }
 
@@ -545,10 +578,17 @@ int line_search_core(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const in
     int K = o->ls_mode == QDTA_LS_QN ? 3 : o->K;
     HIPCHECK(c, launch_ls_begin(c->stream, ni, c->st.p, c->alphas.p, K, o->ls_mode, o->dx, c->ls_acc.p, 0));
     if (o->ls_mode == QDTA_LS_MSA) return QDTA_OK;
+    const bool plain = o->launch_form == 2;
     if (o->ls_mode == QDTA_LS_KSECTION) {
         for (int p = 0; p < o->passes; ++p) {
-            HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, K, c->alphas.p, c->ls_acc.p, c->st.p, 1,
-                                       err));
+            if (plain) {
+                for (int k = 0; k < K; ++k)
+                    HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, 1, c->alphas.p, c->ls_acc.p,
+                                               c->st.p, 1, err, k, K));
+            } else {
+                HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, K, c->alphas.p, c->ls_acc.p,
+                                           c->st.p, 1, err));
+            }
             HIPCHECK(c, launch_ls_decide(c->stream, ni, c->st.p, c->alphas.p, K, 0, o->passes, o->max_ls, o->T1, o->T2,
                                          o->dx, c->ls_acc.p));
         }
@@ -556,7 +596,14 @@ int line_search_core(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const in
     }
     // quasi-Newton (Alg. 8): iterate until every live instance is done
     for (int l = 0; l < o->max_ls; ++l) {
-        HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, 3, c->alphas.p, c->ls_acc.p, c->st.p, 1, err));
+        if (plain) {
+            for (int k = 0; k < 3; ++k)
+                HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, 1, c->alphas.p, c->ls_acc.p, c->st.p,
+                                           1, err, k, 3));
+        } else {
+            HIPCHECK(c, launch_ls_eval(c->stream, net, f, y, o->alpha, o->beta, 3, c->alphas.p, c->ls_acc.p, c->st.p, 1,
+                                       err));
+        }
         HIPCHECK(c, launch_ls_decide(c->stream, ni, c->st.p, c->alphas.p, 3, 1, o->passes, o->max_ls, o->T1, o->T2,
                                      o->dx, c->ls_acc.p));
         RC(pull_state(c));
@@ -703,6 +750,8 @@ int qdta_destroy(qdta_ctx* c) {
     for (int p = 0; p < 8; ++p)
         for (int e = 0; e < 2; ++e)
             if (c->prof_ev[p][e]) hipEventDestroy(c->prof_ev[p][e]);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return QDTA_OK;
 }
@@ -887,8 +936,9 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
             { rc = set_err(c, QDTA_EHIP, "copy cost: %s", hipGetErrorString(e)); break; }
         if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p)))
             { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
-        uint32_t ecode, tep = 0;
-        if ((rc = next_epoch(c, lab, tep, &ecode))) break;
+        uint32_t tep = 0;
+        uint32_t* ecode = c->ecode.p + 1;
+        if ((rc = next_epoch(c, lab, tep, ecode))) break;
         if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, lab.p, scr_view(c), slots, nullptr,
                              delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 0)))
             { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
@@ -1034,24 +1084,24 @@ void fill_stats(qdta_ctx* c, qdta_stats* hs, int worst, const int* h) {
     }
 }
 
-// One Frank-Wolfe iteration j (Alg. 6): BPR, AON, stop test, line search,
-// update, for every live instance; one host synchronisation at the end.
-int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
+// The kernels of one Frank-Wolfe iteration (Alg. 6): BPR, AON, stop test,
+// line search, update, for every live instance.  No host synchronisation
+// unless the quasi-Newton search is selected.
+int enqueue_iteration(qdta_ctx* c, const qdta_opts* o, bool marks) {
     int ni = (int)c->inst.size();
     NetDev net = net_view(c);
     int* err = c->flags.p;
     const int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
-    const int j = ++c->fw_j;
-    RC(prof_mark(c, PH_BPR, 0));
+    if (marks) RC(prof_mark(c, PH_BPR, 0));
     HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, err));
-    RC(prof_mark(c, PH_BPR, 1));
-    RC(aon_core(c, o, c->cost.p, c->y.p, nullptr, c->st.p));
-    RC(prof_mark(c, PH_GAP, 0));
+    if (marks) RC(prof_mark(c, PH_BPR, 1));
+    RC(aon_core(c, o, c->cost.p, c->y.p, nullptr, c->st.p, marks));
+    if (marks) RC(prof_mark(c, PH_GAP, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
     HIPCHECK(c, launch_gap_sums(c->stream, net, c->cost.p, c->f.p, c->y.p, c->acc.p, c->st.p, err));
-    HIPCHECK(c, launch_gap_decide(c->stream, ni, c->acc.p, c->st.p, o->stop_rule, o->tol, o->fixed_iters, cap_iter, j));
-    RC(prof_mark(c, PH_GAP, 1));
-    RC(prof_mark(c, PH_LS, 0));
+    HIPCHECK(c, launch_gap_decide(c->stream, ni, c->acc.p, c->st.p, o->stop_rule, o->tol, o->fixed_iters, cap_iter));
+    if (marks) RC(prof_mark(c, PH_GAP, 1));
+    if (marks) RC(prof_mark(c, PH_LS, 0));
     RC(line_search_core(c, o, c->f.p, c->y.p));
     if (o->stop_rule == QDTA_STOP_OBJ && o->fixed_iters <= 0) {
         HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
@@ -1059,12 +1109,70 @@ int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
         HIPCHECK(c, launch_obj_decide(c->stream, ni, c->acc.p, c->st.p, o->tol, 1));
     }
     HIPCHECK(c, launch_stall_check(c->stream, ni, c->st.p, o->fixed_iters));
-    RC(prof_mark(c, PH_LS, 1));
-    RC(prof_mark(c, PH_UPDATE, 0));
+    if (marks) RC(prof_mark(c, PH_LS, 1));
+    if (marks) RC(prof_mark(c, PH_UPDATE, 0));
     HIPCHECK(c, launch_copy_alpha(c->stream, ni, c->st.p, c->alpha_arr.p));
     HIPCHECK(c, launch_fw_update(c->stream, net, c->f.p, c->y.p, c->alpha_arr.p, c->st.p));
     HIPCHECK(c, launch_after_update(c->stream, ni, c->st.p));
-    RC(prof_mark(c, PH_UPDATE, 1));
+    if (marks) RC(prof_mark(c, PH_UPDATE, 1));
+    return QDTA_OK;
+}
+
+bool graph_form(const qdta_opts* o) { return o->launch_form == 0 && o->ls_mode != QDTA_LS_QN; }
+
+void drop_graph(qdta_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Capture one iteration on a side stream; the graph is then launched on the
+// context's stream (which may be the null stream, which cannot capture).
+int capture_iteration(qdta_ctx* c, const qdta_opts* o) {
+    drop_graph(c);
+    if (!c->cap_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    uint32_t saved_epoch = c->epoch;
+    c->stream = c->cap_stream;
+    c->epoch = 1;                      // inside the graph the epoch only advances
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? enqueue_iteration(c, o, false) : QDTA_EHIP;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = saved;
+    c->epoch = saved_epoch;
+    if (e != hipSuccess) return set_err(c, QDTA_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    if (rc < 0) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e2 != hipSuccess) return set_err(c, QDTA_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    c->graph = g;
+    HIPCHECK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    c->graph_gen = c->gen;
+    c->graph_opts = *o;
+    return QDTA_OK;
+}
+
+// One Frank-Wolfe iteration j, then one host synchronisation.
+int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
+    int ni = (int)c->inst.size();
+    const int j = ++c->fw_j;
+    if (graph_form(o)) {
+        if (!c->graph_exec || c->graph_gen != c->gen || memcmp(&c->graph_opts, o, sizeof(qdta_opts)) != 0)
+            RC(capture_iteration(c, o));
+        if (c->epoch == 0 || c->epoch + 1 >= kMaxEpoch) {
+            c->epoch = 0;                  // reset outside the graph
+            RC(next_epoch(c, c->labels, c->epoch, c->ecode.p));
+        }
+        RC(prof_mark(c, PH_GRAPH, 0));
+        HIPCHECK(c, hipGraphLaunch(c->graph_exec, c->stream));
+        RC(prof_mark(c, PH_GRAPH, 1));
+        c->epoch += 1;
+    } else {
+        RC(enqueue_iteration(c, o, true));
+    }
     if (o->keep_history) {
         RC(ensure_history(c, (size_t)j + 1));
         HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p + (size_t)j * c->M, c->cost.p, sizeof(float) * c->M,
@@ -1222,8 +1330,8 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         HIPCHECK(c, hipMemcpyAsync(c->lambda.p, lam.data(), sizeof(double) * ni, hipMemcpyHostToDevice, c->stream));
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
         HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
-        uint32_t ecode;
-        RC(next_epoch(c, c->labels, c->epoch, &ecode));
+        uint32_t* ecode = c->ecode.p;
+        RC(next_epoch(c, c->labels, c->epoch, ecode));
         HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, c->st.p,
                                 delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
         HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->r_count.p), 0, 1));

@@ -30,7 +30,7 @@ EXPORTS = [
     "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_fw_begin", "qdta_fw_step",
     "qdta_profile_enable", "qdta_profile_read",
 ]
-PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update"]
+PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
 
 
 class Opts(C.Structure):
@@ -38,7 +38,8 @@ class Opts(C.Structure):
                 ("K", C.c_int32), ("passes", C.c_int32), ("max_ls", C.c_int32), ("T1", C.c_double),
                 ("T2", C.c_double), ("dx", C.c_double), ("stop_rule", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("reserved", C.c_int32 * 4)]
+                ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("sssp_shape", C.c_int32),
+                ("launch_form", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):

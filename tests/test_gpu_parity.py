@@ -423,3 +423,68 @@ def test_day_small_network_chain(torch_dev, q, orc):
         for x, y in zip(a["res"], b["res"]):
             assert np.array_equal(x, y)
         assert a["done"] == b["done_fx"]
+
+
+# ---------------------------------------------------------------------------
+# A9 -- launch structure: graph replay, plain form, kernel shapes
+# ---------------------------------------------------------------------------
+def _step_flows(torch, q, nets_dems, opts, steps):
+    """Flows and stats after each FW step (one entry per replayed iteration)."""
+    out = []
+    with q.Context() as ctx:
+        for net, dem in nets_dems:
+            i = ctx.add(net)
+            ctx.set_demand(i, dem.orig, dem.dest, dem.trips, dem.dt_s)
+        ctx.fw_begin(opts)
+        li = ctx.layout()
+        f = torch.empty(li.total_links, dtype=torch.int64, device="cuda")
+        for _ in range(steps):
+            st, live = ctx.fw_step(opts)
+            ctx.get_flows(f)
+            out.append((host(f).copy(), [(s["iters"], s["gap"], s["last_alpha"]) for s in st]))
+    return out
+
+
+def test_graph_replay_matches_direct_launches(torch_dev, q):
+    """One FW iteration captured as a HIP graph and replayed (with the host's
+    state copy and synchronisation between replays) gives, after every
+    replay, exactly what direct launches give."""
+    insts = synth.config4(count=3, k_lo=10, k_hi=16, z_lo=12, z_hi=30)
+    nd = [(x.net, x.demand) for x in insts]
+    for mode in (q.LS_KSECTION, q.LS_MSA):
+        g = _step_flows(torch_dev, q, nd, q.default_opts(fixed_iters=1000, ls_mode=mode, launch_form=0), 12)
+        d = _step_flows(torch_dev, q, nd, q.default_opts(fixed_iters=1000, ls_mode=mode, launch_form=1), 12)
+        for (fg, sg), (fd, sd) in zip(g, d):
+            assert np.array_equal(fg, fd)
+            assert sg == sd
+
+
+def test_plain_form_matches_batched(torch_dev, q, orc):
+    w = synth.config1()
+    for mode in (q.LS_KSECTION, q.LS_QN):
+        st_p, f_p, _, (o, d, wfx), _ = _solve(torch_dev, q, [(w.net, w.demand)],
+                                              q.default_opts(fixed_iters=8, ls_mode=mode, launch_form=2))
+        st_b, f_b, _, _, _ = _solve(torch_dev, q, [(w.net, w.demand)],
+                                    q.default_opts(fixed_iters=8, ls_mode=mode, launch_form=0))
+        assert np.array_equal(f_p, f_b) and st_p[0]["gap"] == st_b[0]["gap"]
+        ref = orc.fw_solve(w.net, o, d, wfx, fixed_iters=8, ls_mode=mode, keep_history=False)
+        assert np.array_equal(f_p, ref.f)
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6])
+def test_sssp_shapes_identical(torch_dev, q, orc, shape):
+    w = synth.config2()
+    rng = np.random.default_rng(40 + shape)
+    f = rng.integers(0, 600 * FX, w.net.m).astype(np.int64)
+    cost, _ = orc.bpr(f, w.net.fftt, w.net.cap, 0.15, 4, 900.0)
+    sel = np.isin(w.demand.dest, w.extra["zones"][:25])
+    y, stop, (o, d, wfx), _ = _aon(torch_dev, q, w.net, cost, w.demand.orig[sel], w.demand.dest[sel],
+                                   w.demand.trips[sel], 900.0, 1)
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_demand(0, w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel], 900.0)
+        yy = torch_dev.empty(w.net.m, dtype=torch_dev.int64, device="cuda")
+        ctx.aon(q.default_opts(sssp_shape=shape), dev(torch_dev, cost), yy)
+        assert np.array_equal(host(yy), y)
+    yo, so, _ = orc.aon(w.net, cost, o, d, wfx, 900.0, 1)
+    assert np.array_equal(y, yo)
