@@ -115,6 +115,126 @@ def cpu_baseline(w, target_s, nthreads):
                       f"extrapolated linearly to one full step ({step:.1f} s)"}
 
 
+def _ctx_for(qdta, stream, pairs):
+    ctx = qdta.Context(0, stream)
+    for net, dem in pairs:
+        i = ctx.add(net)
+        ctx.set_demand(i, dem.orig, dem.dest, dem.trips, dem.dt_s)
+    return ctx
+
+
+def _solve_timed(torch, ctx, opts):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rc = ctx.solve(opts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st
+
+
+def mode_plain(args, torch, qdta):
+    """M3 on config 2: per-iteration time of the batched form (every tree in
+    one launch, all step sizes in one pass, iteration replayed as a HIP graph)
+    against the plain form (one launch per destination tree and per step
+    size).  Both give bit-identical iterates, so they take the same number of
+    iterations to any gap; time to gap = iterations x per-iteration time."""
+    w = workload("config2")
+    stream = torch.cuda.current_stream()
+    ctx = _ctx_for(qdta, stream, [(w.net, w.demand)])
+    out = {"mode": "plain", "workload": "config2"}
+    opts_b = qdta.default_opts(tol=1e-4, max_iter=args.steps)
+    t_solve, st = _solve_timed(torch, ctx, opts_b)
+    out.update(batched_solve_s=t_solve, iterations=st[0]["iters"], gap=st[0]["gap"], stopped_by=st[0]["stopped_by"])
+    log(f"batched solve: {t_solve:.2f} s, {st[0]['iters']} iterations, gap {st[0]['gap']:.3e}, "
+        f"stopped_by {st[0]['stopped_by']}")
+    per = {}
+    for form in (0, 2):
+        o = qdta.default_opts(fixed_iters=1 << 30, launch_form=form)
+        ctx.fw_begin(o)
+        ctx.fw_step(o)
+        torch.cuda.synchronize()
+        n = 3 if form == 0 else 1
+        t0 = time.perf_counter()
+        for _ in range(n):
+            ctx.fw_step(o)
+        torch.cuda.synchronize()
+        per[form] = (time.perf_counter() - t0) / n
+        log(f"form {form}: {per[form] * 1e3:.1f} ms per FW iteration")
+    out.update(batched_iter_ms=per[0] * 1e3, plain_iter_ms=per[2] * 1e3, speedup=per[2] / per[0],
+               plain_time_to_gap_s_extrapolated=per[2] * max(st[0]["iters"] + 1, 1))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def mode_batch(args, torch, qdta):
+    """Config 4: 64 uneven grids advanced together (one launch sequence and
+    one HIP graph per FW iteration for all of them) against the same grids
+    solved one after another.  Both run the same fixed number of iterations
+    (the iterates are bit-identical, so the work is the same)."""
+    import synth
+    insts = synth.config4()
+    stream = torch.cuda.current_stream()
+    iters = args.steps
+    opts = qdta.default_opts(fixed_iters=iters)
+    ctx = _ctx_for(qdta, stream, [(x.net, x.demand) for x in insts])
+    li = ctx.layout()
+    log(f"config4: {len(insts)} instances, {li.total_links} links, {li.total_dests} destinations, {li.total_legs} legs")
+    _solve_timed(torch, ctx, qdta.default_opts(fixed_iters=1))
+    ctx.profile(True)
+    t_b, st_b = _solve_timed(torch, ctx, opts)
+    prof = ctx.profile_read()
+    ctx.close()
+    log(f"batched: {t_b:.2f} s for {iters} iterations; phases {json.dumps({k: round(v[0], 1) for k, v in prof.items()})}")
+    t_s = 0.0
+    for i, x in enumerate(insts):
+        c1 = _ctx_for(qdta, stream, [(x.net, x.demand)])
+        _solve_timed(torch, c1, qdta.default_opts(fixed_iters=1))
+        t, st = _solve_timed(torch, c1, opts)
+        t_s += t
+        c1.close()
+        log(f"sequential instance {i}: {t:.3f} s (total {t_s:.2f} s)")
+    print(json.dumps({"mode": "batch", "workload": "config4", "instances": len(insts),
+                      "links": int(li.total_links), "destinations": int(li.total_dests), "legs": int(li.total_legs),
+                      "iterations": iters, "batched_s": t_b, "sequential_s": t_s, "speedup": t_s / t_b,
+                      "gap_max_batched": max(s["gap"] for s in st_b)}), flush=True)
+
+
+def mode_day(args, torch, qdta):
+    """Full-day QDTA (Alg. 1): for each 15-min interval, d(i) = d^o(i) +
+    d^r(i), Frank-Wolfe to relative gap 1e-4 (or stall / cap), then the
+    residual demand of Alg. 4 carried into the next interval."""
+    import synth
+    w = synth.config3_day(args.scale)
+    net = w.net
+    days = w.demand[:args.intervals]
+    stream = torch.cuda.current_stream()
+    ctx = qdta.Context(0, stream)
+    ctx.add(net)
+    stop = qdta.STOP_OBJ if args.stop == "obj" else qdta.STOP_GAP
+    opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, tot_trips, carried = [], 0.0, 0
+    for i, dem in enumerate(days):
+        ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
+        tot_trips += dem.total()
+        if ctx.layout().total_legs == 0:
+            iters.append(0)
+            continue
+        st, rc = ctx.solve(opts)
+        ctx.advance_interval(opts)
+        ro, rd, rw, done = ctx.residual(0)
+        iters.append(st[0]["iters"])
+        carried = int(rw.sum())
+        log(f"interval {i}: legs {ctx.layout().total_legs} iters {st[0]['iters']} gap {st[0]['gap']:.2e} "
+            f"stop {st[0]['stopped_by']} residual legs {ro.size} ({carried / FX:.0f} trips)")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
+                      "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
+                      "stop_rule": args.stop, "left_after_last_trips": carried / FX}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +247,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (MiB) once, for counter calibration")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the kernel-shape / bucket-width autotuner")
+    ap.add_argument("--mode", default="aon", choices=["aon", "plain", "batch", "day"],
+                    help="aon: the headline AON/s line; plain: batched vs per-destination launches (config 2); "
+                         "batch: 64 uneven instances together vs one after another (config 4); day: full-day QDTA")
+    ap.add_argument("--scale", type=float, default=1.0, help="day mode: network/demand scale (1 = 1.0M links)")
+    ap.add_argument("--intervals", type=int, default=96, help="day mode: number of 15-min intervals")
+    ap.add_argument("--stop", default="obj", choices=["obj", "gap"],
+                    help="day mode: stop rule, objective change (Eq. 7) or relative gap, both at 1e-4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -135,6 +263,10 @@ def main():
 
     import torch
     from paper_2104_12911_amd import qdta
+
+    if args.mode != "aon":
+        {"plain": mode_plain, "batch": mode_batch, "day": mode_day}[args.mode](args, torch, qdta)
+        return
 
     log(f"generating {args.workload}")
     w = workload(args.workload)
@@ -149,6 +281,9 @@ def main():
                              waves_per_cu=args.waves_per_cu)
     li = ctx.layout()
     Q = int(li.total_dests)
+    if not args.no_autotune and not args.delta_scale:
+        opts, best = ctx.autotune(opts, 2000.0)
+        log(f"autotune: sssp_shape={opts.sssp_shape} delta_scale={opts.delta_scale} ({best:.1f} ms)")
     log(f"layout: destinations={Q} legs={li.total_legs}; initial AON")
     t0 = time.perf_counter()
     ctx.fw_begin(opts)
@@ -198,8 +333,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {net.n} nodes, {net.m} links, {Q} destinations, {li.total_legs} legs,"
-                               f" dt {dem.dt_s:g} s", "delta_scale": args.delta_scale or 5.0,
-                   "waves_per_cu": args.waves_per_cu or 16, "line_search": "K-section K=32 x3"},
+                               f" dt {dem.dt_s:g} s", "delta_scale": opts.delta_scale or 5.0,
+                   "sssp_shape": opts.sssp_shape, "waves_per_cu": args.waves_per_cu or 16,
+                   "line_search": "K-section K=32 x3", "launch": "HIP graph per FW iteration"},
         "gteps": Q * net.m / sssp_avg_s / 1e9,
         "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

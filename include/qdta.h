@@ -248,6 +248,15 @@ int qdta_advance_interval(qdta_ctx *ctx, const qdta_opts *opts);
 int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host_orig,
                       int32_t *host_dest, int64_t *host_w_fx, int64_t *host_done_fx);
 
+/* Autotuner: times the shortest-path launch of the current demand (every
+ * instance, under the costs BPR(f) of the last solved iterate, free-flow
+ * costs otherwise) for a grid of kernel shapes and bucket widths, stopping
+ * once about budget_ms of GPU time is spent, and writes the fastest into
+ * opts->sssp_shape and opts->delta_scale (other fields unchanged).  Results
+ * never depend on these two fields, only the speed does.  *best_ms_out
+ * (host, may be NULL) receives the best trial time.  Synchronises. */
+int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best_ms_out);
+
 /* Per-phase timers: HIP events recorded on the context's stream around each
  * phase of the Frank-Wolfe iteration; durations are added at the iteration's
  * synchronisation.  Phases: 0 BPR costs, 1 shortest-path trees, 2 loading

@@ -1244,6 +1244,59 @@ int qdta_solve(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
     return fw_finish(c, o, hs);
 }
 
+int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_out) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!(budget_ms > 0.0)) return set_err(c, QDTA_EARG, "budget_ms must be > 0");
+    for (const Instance& I : c->inst)
+        if (!I.has_demand) return set_err(c, QDTA_ESTATE, "autotune needs the demand of every instance");
+    RC(ensure_demand(c, waves_per_cu(o)));
+    RC(apply_rule(c, o));
+    NetDev net = net_view(c);
+    DemDev dem = dem_view(c);
+    // trial costs: BPR of the current flows when an interval was solved, else free flow
+    if (!c->solved) HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
+    RC(clear_flags(c));
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, nullptr, 0, c->flags.p));
+    hipEvent_t e0, e1;
+    HIPCHECK(c, hipEventCreate(&e0));
+    HIPCHECK(c, hipEventCreate(&e1));
+    static const int shapes[] = {3, 4, 2, 5};
+    static const double scales[] = {5.0, 2.5, 10.0};
+    int best_shape = o->sssp_shape ? o->sssp_shape : 3;
+    double best_scale = delta_scale(o), best = 1e300, spent = 0.0;
+    int rc = QDTA_OK;
+    for (double sc : scales) {
+        for (int sh : shapes) {
+            if (spent >= budget_ms) break;
+            qdta_opts t = *o;
+            t.sssp_shape = sh;
+            t.delta_scale = sc;
+            if ((rc = next_epoch(c, c->labels, c->epoch, c->ecode.p)) < 0) break;
+            hipError_t e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess)
+                e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), c->slots, nullptr,
+                                delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), c->ecode.p, 1);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = set_err(c, QDTA_EHIP, "autotune trial: %s", hipGetErrorString(e)); break; }
+            spent += ms;
+            if (ms < best) { best = ms; best_shape = sh; best_scale = sc; }
+        }
+        if (rc < 0 || spent >= budget_ms) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc < 0) return rc;
+    o->sssp_shape = best_shape;
+    o->delta_scale = best_scale;
+    if (best_ms_out) *best_ms_out = best;
+    return QDTA_OK;
+}
+
 int qdta_profile_enable(qdta_ctx* c, int32_t on) {
     if (!c) return QDTA_EARG;
     for (int p = 0; p < kPhases; ++p) {

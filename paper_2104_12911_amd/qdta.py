@@ -28,7 +28,7 @@ EXPORTS = [
     "qdta_add_network", "qdta_set_demand", "qdta_layout", "qdta_offsets", "qdta_bpr", "qdta_trees", "qdta_aon",
     "qdta_get_legs", "qdta_ls_eval", "qdta_line_search", "qdta_fw_update", "qdta_solve", "qdta_get_flows",
     "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_fw_begin", "qdta_fw_step",
-    "qdta_profile_enable", "qdta_profile_read",
+    "qdta_profile_enable", "qdta_profile_read", "qdta_autotune",
 ]
 PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
 
@@ -106,6 +106,7 @@ def lib():
         L.qdta_fw_step.argtypes = [vp, vp, vp, C.POINTER(i32)]
         L.qdta_profile_enable.argtypes = [vp, i32]
         L.qdta_profile_read.argtypes = [vp, vp]
+        L.qdta_autotune.argtypes = [vp, vp, dbl, C.POINTER(dbl)]
         for name in EXPORTS:
             if name not in ("qdta_default_opts", "qdta_strerror", "qdta_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -257,6 +258,13 @@ class Context:
         live = C.c_int32()
         self._rc(lib().qdta_fw_step(self._h, C.byref(opts), st, C.byref(live)), allow=(OK, WABSORB))
         return [st[i].as_dict() for i in range(self.n_inst)], bool(live.value)
+
+    def autotune(self, opts, budget_ms=2000.0):
+        """Fastest kernel shape and bucket width for the current demand; returns
+        (tuned opts, best trial ms).  The given opts object is updated in place."""
+        best = C.c_double()
+        self._rc(lib().qdta_autotune(self._h, C.byref(opts), float(budget_ms), C.byref(best)))
+        return opts, best.value
 
     def profile(self, on: bool = True):
         self._rc(lib().qdta_profile_enable(self._h, 1 if on else 0))
