@@ -95,7 +95,9 @@ struct qdta_ctx {
     DBuf<int64_t> r_w;
     DBuf<unsigned long long> r_count, done_fx;
     uint32_t epoch = 0;           // epoch of the last shortest-path launch on `labels`
-    uint64_t gen = 0;             // bumped whenever device memory is (re)allocated
+    uint64_t gen = 0;             // bumped on every (re)allocation and every rebuild of the
+                                  // network or demand tables: a captured iteration is valid
+                                  // only for the generation it was captured in
     // captured FW iteration
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -298,6 +300,7 @@ int ensure_network(qdta_ctx* c) {
     }
     c->net_dirty = false;
     c->dem_dirty = true;
+    c->gen++;                          // sizes baked into a captured iteration are stale
     return QDTA_OK;
 }
 
@@ -407,6 +410,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     RC(ensure_scratch(c, c->Q, nmax, wpc));
     c->dem_dirty = false;
     c->solved = false;
+    c->gen++;                          // Q and P are baked into a captured iteration
     return QDTA_OK;
 }
 

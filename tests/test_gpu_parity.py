@@ -425,6 +425,28 @@ def test_day_small_network_chain(torch_dev, q, orc):
         assert a["done"] == b["done_fx"]
 
 
+def test_day_demand_shrinks_and_regrows(torch_dev, q, orc):
+    """Intervals whose leg and destination counts fall and then rise again
+    within the buffers of the largest one: every interval is re-captured
+    for its own sizes, so each still matches the oracle exactly."""
+    w = synth.config1()
+    rng = np.random.default_rng(17)
+    days = []
+    for frac in (0.8, 0.1, 0.45, 0.05, 0.5):
+        sel = rng.random(w.demand.P) < frac
+        days.append(synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] / 3, 900.0))
+    opts = q.default_opts(keep_history=1, tol=1e-3, max_iter=25)
+    g = _day_gpu(torch_dev, q, w.net, days, opts)
+    ref, _ = orc.qdta_day(w.net, days, tol=1e-3, max_iter=25)
+    legs = [b["legs"] for b in ref]
+    assert legs[1] < legs[0] and legs[3] < legs[4] < legs[0]
+    for a, b in zip(g, ref):
+        assert a["iters"] == b["iters"]
+        assert np.array_equal(a["f"], b["f"])
+        for x, y in zip(a["res"], b["res"]):
+            assert np.array_equal(x, y)
+
+
 # ---------------------------------------------------------------------------
 # A9 -- launch structure: graph replay, plain form, kernel shapes
 # ---------------------------------------------------------------------------
