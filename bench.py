@@ -210,29 +210,48 @@ def mode_day(args, torch, qdta):
     ctx = qdta.Context(0, stream)
     ctx.add(net)
     stop = qdta.STOP_OBJ if args.stop == "obj" else qdta.STOP_GAP
-    opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1)
+    opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1,
+                             launch_form=1 if args.profile_day else 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, tot_trips, carried = [], 0.0, 0
+    split = {"set_demand": 0.0, "solve": 0.0, "advance": 0.0, "residual_out": 0.0}
+    if args.profile_day:
+        ctx.profile(True)
     for i, dem in enumerate(days):
+        ta = time.perf_counter()
         ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
         tot_trips += dem.total()
-        if ctx.layout().total_legs == 0:
+        legs = ctx.layout().total_legs
+        tb = time.perf_counter()
+        if legs == 0:
             iters.append(0)
             continue
         st, rc = ctx.solve(opts)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
         ctx.advance_interval(opts)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
         ro, rd, rw, done = ctx.residual(0)
+        te = time.perf_counter()
+        for k, v in zip(split, (tb - ta, tc - tb, td - tc, te - td)):
+            split[k] += v
         iters.append(st[0]["iters"])
         carried = int(rw.sum())
-        log(f"interval {i}: legs {ctx.layout().total_legs} iters {st[0]['iters']} gap {st[0]['gap']:.2e} "
-            f"stop {st[0]['stopped_by']} residual legs {ro.size} ({carried / FX:.0f} trips)")
+        log(f"interval {i}: legs {legs} iters {st[0]['iters']} gap {st[0]['gap']:.2e} "
+            f"stop {st[0]['stopped_by']} residual legs {ro.size} ({carried / FX:.0f} trips); "
+            f"set {tb - ta:.2f} s solve {tc - tb:.2f} s advance {td - tc:.2f} s")
+    if args.profile_day:
+        prof = ctx.profile_read()
+        log("phases (ms, count): " + json.dumps({k: [round(v[0], 1), v[1]] for k, v in prof.items()}))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.close()
     print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
-                      "stop_rule": args.stop, "left_after_last_trips": carried / FX}), flush=True)
+                      "stop_rule": args.stop, "left_after_last_trips": carried / FX,
+                      "split_s": {k: round(v, 3) for k, v in split.items()}}), flush=True)
 
 
 def main():
@@ -253,6 +272,7 @@ def main():
                          "batch: 64 uneven instances together vs one after another (config 4); day: full-day QDTA")
     ap.add_argument("--scale", type=float, default=1.0, help="day mode: network/demand scale (1 = 1.0M links)")
     ap.add_argument("--intervals", type=int, default=96, help="day mode: number of 15-min intervals")
+    ap.add_argument("--profile-day", action="store_true", help="day mode: per-phase event timing (direct launches)")
     ap.add_argument("--stop", default="obj", choices=["obj", "gap"],
                     help="day mode: stop rule, objective change (Eq. 7) or relative gap, both at 1e-4")
     args = ap.parse_args()
