@@ -149,15 +149,21 @@ hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, cons
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
-                       int32_t* r_orig, int32_t* r_dest, int64_t* r_w, unsigned long long* r_count,
+                       int64_t* r_dense,
                        unsigned long long* done_fx, const uint32_t* ecode, int l_begin = 0, int l_end = -1);
 
 hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
-                           int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
-                           unsigned long long* r_count, unsigned long long* done_fx,
+                           int residual_mode, const double* lambda, int64_t* r_dense,
+                           unsigned long long* done_fx,
                            int trees_mode, int32_t* succ_out, int32_t n_out, const uint32_t* ecode);
+
+// residual accumulator (indexed like the labels) -> legs in (destination, origin) order
+hipError_t launch_resid_count(hipStream_t s, const NetDev& net, const DemDev& dem, const int64_t* r_dense,
+                              int64_t* cnt);
+hipError_t launch_resid_write(hipStream_t s, const NetDev& net, const DemDev& dem, int64_t* r_dense,
+                              const int64_t* off, int32_t* r_orig, int32_t* r_q, int64_t* r_w);
 
 hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                             const float* cost_local, int32_t inst, float* dist, int32_t* succ,

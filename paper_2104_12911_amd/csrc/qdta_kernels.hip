@@ -956,14 +956,14 @@ struct WalkOut {
     int32_t* stop;
     int residual_mode;
     const double* lambda;        // per instance (residual mode)
-    int32_t *r_orig, *r_dest;
-    int64_t* r_w;
-    unsigned long long *r_count, *done_fx;
+    int64_t* r_dense;            // residual accumulator, indexed like the labels
+    unsigned long long* done_fx;
 };
 
-// Residual mode emits (stop node, destination index, rint(lambda d)) for a
-// leg that stops short of q, and counts the completed weight otherwise.
-__device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q, int qi, int inst, int node0,
+// Residual mode adds rint(lambda d) of a leg that stops at s short of q to
+// the accumulator word of (tree qi, node s), whose label offset is lab0, and
+// counts the completed weight otherwise.
+__device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q, int64_t lab0, int inst, int node0,
                                            int64_t d) {
     if (!o.residual_mode) {
         if (o.stop) o.stop[l] = s - node0;
@@ -975,10 +975,7 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
         return;
     }
     if (w == 0) return;
-    const unsigned long long k = atomicAdd(o.r_count, 1ull);
-    o.r_orig[k] = s - node0;
-    o.r_dest[k] = qi;
-    o.r_w[k] = w;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&o.r_dense[lab0 + (s - node0)]), (unsigned long long)w);
 }
 
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
@@ -1022,17 +1019,17 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
         u = net.col[e];
         du = lab_val(lab, u - node0, ecode);
     }
-    finish_leg(o, l, u, q, qi, inst, node0, d);
+    finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
 }
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
-                       const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda, int32_t* r_orig,
-                       int32_t* r_dest, int64_t* r_w, unsigned long long* r_count, unsigned long long* done_fx,
+                       const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
+                       int64_t* r_dense, unsigned long long* done_fx,
                        const uint32_t* ecode, int l_begin, int l_end) {
     if (l_end < 0) l_end = dem.P;
     if (l_end <= l_begin) return hipSuccess;
-    WalkOut o{y, stop, residual_mode, lambda, r_orig, r_dest, r_w, r_count, done_fx};
+    WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
     hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, tree_cost,
                        time_cost, st, fl, o, ecode, l_begin, l_end);
     return hipGetLastError();
@@ -1133,7 +1130,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                     du = lab_val(lab, u - node0, ecode);
                 }
                 fl.int_node[l] = -1;
-                finish_leg(o, l, u, q, qi, inst, node0, d);
+                finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
             }
         }
         __syncthreads();
@@ -1143,13 +1140,88 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
 hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
-                           int residual_mode, const double* lambda, int32_t* r_orig, int32_t* r_dest, int64_t* r_w,
-                           unsigned long long* r_count, unsigned long long* done_fx, int trees_mode,
+                           int residual_mode, const double* lambda, int64_t* r_dense,
+                           unsigned long long* done_fx, int trees_mode,
                            int32_t* succ_out, int32_t n_out, const uint32_t* ecode) {
     if (dem.Q == 0) return hipSuccess;
-    WalkOut o{y, stop, residual_mode, lambda, r_orig, r_dest, r_w, r_count, done_fx};
+    WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
     hipLaunchKernelGGL(k_fallback, dim3(slots), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost, st, fl, scr,
                        o, trees_mode, succ_out, n_out, ecode);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// A8: compaction of the residual accumulator
+// ---------------------------------------------------------------------------
+// Tree t's residual legs are the non-zero words of its row (n words at
+// dest_lab[t]); rows are taken in tree order and nodes in ascending order,
+// which is (destination, origin) order.  The write pass clears what it
+// reads, so the accumulator is all zero again afterwards.
+__device__ __forceinline__ int block_excl_scan(int x, int* tot, int* s_w) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_w[wv] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int k = 0; k < kWG / 64; ++k) {
+        if (k < wv) before += s_w[k];
+        all += s_w[k];
+    }
+    __syncthreads();
+    *tot = all;
+    return before + incl - x;
+}
+
+__global__ __launch_bounds__(kWG) void k_resid_count(NetDev net, DemDev dem, const int64_t* __restrict__ r_dense,
+                                                     int64_t* cnt) {
+    __shared__ int s_w[kWG / 64];
+    const int t = blockIdx.x;
+    const int n = net.inst[dem.dest_inst[t]].n;
+    const int64_t* row = r_dense + dem.dest_lab[t];
+    int c = 0;
+    for (int v = threadIdx.x; v < n; v += kWG) c += row[v] != 0;
+    int tot = 0;
+    block_excl_scan(c, &tot, s_w);
+    if (threadIdx.x == 0) cnt[t] = tot;
+}
+
+__global__ __launch_bounds__(kWG) void k_resid_write(NetDev net, DemDev dem, int64_t* r_dense, const int64_t* off,
+                                                     int32_t* r_orig, int32_t* r_q, int64_t* r_w) {
+    __shared__ int s_w[kWG / 64];
+    const int t = blockIdx.x;
+    const int n = net.inst[dem.dest_inst[t]].n;
+    int64_t* row = r_dense + dem.dest_lab[t];
+    int64_t base = off[t];
+    for (int v0 = 0; v0 < n; v0 += kWG) {
+        const int v = v0 + threadIdx.x;
+        const int64_t x = v < n ? row[v] : 0;
+        int tot = 0;
+        const int pos = block_excl_scan(x != 0 ? 1 : 0, &tot, s_w);
+        if (x != 0) {
+            r_orig[base + pos] = v;
+            r_q[base + pos] = t;
+            r_w[base + pos] = x;
+            row[v] = 0;
+        }
+        base += tot;
+    }
+}
+
+hipError_t launch_resid_count(hipStream_t s, const NetDev& net, const DemDev& dem, const int64_t* r_dense,
+                              int64_t* cnt) {
+    if (dem.Q == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid_count, dim3(dem.Q), dim3(kWG), 0, s, net, dem, r_dense, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_write(hipStream_t s, const NetDev& net, const DemDev& dem, int64_t* r_dense,
+                              const int64_t* off, int32_t* r_orig, int32_t* r_q, int64_t* r_w) {
+    if (dem.Q == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid_write, dim3(dem.Q), dim3(kWG), 0, s, net, dem, r_dense, off, r_orig, r_q, r_w);
     return hipGetLastError();
 }
 

@@ -92,7 +92,10 @@ struct qdta_ctx {
     size_t hist_iters_cap = 0;
     // residual output
     DBuf<int32_t> r_orig, r_dest;
-    DBuf<int64_t> r_w;
+    DBuf<int64_t> r_w, r_dense, r_cnt;
+    bool r_dense_zero = false;    // the accumulator is known to be all zero
+    DBuf<InstState> st_hist;      // per-iterate instance state of a residual pass
+    DBuf<double> lam_hist;
     DBuf<unsigned long long> r_count, done_fx;
     uint32_t epoch = 0;           // epoch of the last shortest-path launch on `labels`
     uint64_t gen = 0;             // bumped on every (re)allocation and every rebuild of the
@@ -542,14 +545,14 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     if (o->launch_form == 2) {
         for (int64_t qi = 0; qi < c->Q; ++qi)
             HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
-                                    nullptr, nullptr, nullptr, nullptr, ecode, c->h_qptr[qi], c->h_qptr[qi + 1]));
+                                    nullptr, ecode, c->h_qptr[qi], c->h_qptr[qi + 1]));
     } else {
         HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, nullptr, ecode));
+                                nullptr, ecode));
     }
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
                                 (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0, ecode));
+                                nullptr, 0, nullptr, 0, ecode));
     if (marks) RC(prof_mark(c, PH_WALK, 1));
     return QDTA_OK;
 }
@@ -814,10 +817,41 @@ int qdta_set_demand(qdta_ctx* c, int32_t inst, int32_t P, const int32_t* orig, c
         d.push_back(dest[p]);
         w.push_back(trips_fx(trips[p]));
     }
-    o.insert(o.end(), I.r_orig.begin(), I.r_orig.end());
-    d.insert(d.end(), I.r_dest.begin(), I.r_dest.end());
-    w.insert(w.end(), I.r_w.begin(), I.r_w.end());
+    // the pending residual is already in (destination, origin) order with
+    // positive weights and origin != destination: sort the new legs alone,
+    // then merge the two runs (equal legs add up)
     merge_legs(o, d, w);
+    if (!I.r_orig.empty()) {
+        const size_t na = o.size(), nb = I.r_orig.size();
+        std::vector<int32_t> mo, md;
+        std::vector<int64_t> mw;
+        mo.reserve(na + nb);
+        md.reserve(na + nb);
+        mw.reserve(na + nb);
+        size_t a = 0, b = 0;
+        while (a < na || b < nb) {
+            int cmp;
+            if (a == na) cmp = 1;
+            else if (b == nb) cmp = -1;
+            else if (d[a] != I.r_dest[b]) cmp = d[a] < I.r_dest[b] ? -1 : 1;
+            else cmp = o[a] < I.r_orig[b] ? -1 : (o[a] > I.r_orig[b] ? 1 : 0);
+            if (cmp <= 0) {
+                mo.push_back(o[a]);
+                md.push_back(d[a]);
+                mw.push_back(w[a] + (cmp == 0 ? I.r_w[b] : 0));
+                ++a;
+                if (cmp == 0) ++b;
+            } else {
+                mo.push_back(I.r_orig[b]);
+                md.push_back(I.r_dest[b]);
+                mw.push_back(I.r_w[b]);
+                ++b;
+            }
+        }
+        o.swap(mo);
+        d.swap(md);
+        w.swap(mw);
+    }
     I.orig.swap(o);
     I.dest.swap(d);
     I.dfx.swap(w);
@@ -954,7 +988,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         fl.absorb_q = aq.p;
         if ((e = launch_fallback(c->stream, net, dem, lab.p, c->cost.p, c->cost.p, nullptr, nullptr, nullptr, fl,
                                  scr_view(c), (int)std::min<int64_t>(c->scr_slots, nq), 0, nullptr, nullptr, nullptr,
-                                 nullptr, nullptr, nullptr, 1, succ, I.n, ecode)))
+                                 1, succ, I.n, ecode)))
             { rc = set_err(c, QDTA_EHIP, "fallback: %s", hipGetErrorString(e)); break; }
         std::vector<int32_t> ha(nq);
         if ((e = hipMemcpyAsync(ha.data(), aq.p, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, c->stream)))
@@ -1357,80 +1391,99 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
     HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cfin.p, nullptr, nullptr, 0, c->flags.p));
     int J = 0;
     for (const Instance& I : c->inst) J = std::max(J, I.solved_iters);
-    RC(dalloc(c, c->r_orig, (size_t)std::max<int64_t>(c->P, 1)));
-    RC(dalloc(c, c->r_dest, (size_t)std::max<int64_t>(c->P, 1)));
-    RC(dalloc(c, c->r_w, (size_t)std::max<int64_t>(c->P, 1)));
-    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->done_fx.p), 0, ni));
-    std::vector<std::vector<int32_t>> ro(ni), rd(ni);
-    std::vector<std::vector<int64_t>> rw(ni);
-    std::vector<double> lam(ni);
+    // lambda_j = alpha_j prod_{k>j} (1 - alpha_k), alpha_0 = 1, per instance;
+    // instances with fewer iterations sit out.  All iterates' states go up
+    // at once, so the passes below queue without host round trips.
+    std::vector<InstState> hst((size_t)(J + 1) * ni);
+    std::vector<double> hlam((size_t)(J + 1) * ni, 0.0);
+    std::vector<char> any(J + 1, 0);
     for (int j = 0; j <= J; ++j) {
-        // lambda_j = alpha_j prod_{k>j} (1 - alpha_k), alpha_0 = 1; instances
-        // with fewer iterations sit out
-        bool any = false;
         for (int i = 0; i < ni; ++i) {
             const Instance& I = c->inst[i];
-            InstState s;
+            InstState& s = hst[(size_t)j * ni + i];
             memset(&s, 0, sizeof(s));
-            lam[i] = 0.0;
             if (I.solved_iters >= j && c->h_inst[i].nleg > 0) {
                 double l = (j == 0) ? 1.0 : I.hist_alpha[j];
                 for (int k = j + 1; k <= I.solved_iters; ++k) l = l * (1.0 - I.hist_alpha[k]);
-                lam[i] = l;
+                hlam[(size_t)j * ni + i] = l;
                 s.active = l > 0.0;
             }
-            any |= s.active != 0;
-            c->h_st[i] = s;
+            any[j] |= s.active != 0;
         }
-        if (!any) continue;
-        HIPCHECK(c, hipMemcpyAsync(c->st.p, c->h_st, sizeof(InstState) * ni, hipMemcpyHostToDevice, c->stream));
-        HIPCHECK(c, hipMemcpyAsync(c->lambda.p, lam.data(), sizeof(double) * ni, hipMemcpyHostToDevice, c->stream));
+    }
+    RC(dalloc(c, c->st_hist, hst.size()));
+    RC(dalloc(c, c->lam_hist, hlam.size()));
+    HIPCHECK(c, hipMemcpy(c->st_hist.p, hst.data(), sizeof(InstState) * hst.size(), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->lam_hist.p, hlam.data(), sizeof(double) * hlam.size(), hipMemcpyHostToDevice));
+    {
+        int64_t* before = c->r_dense.p;
+        RC(dalloc(c, c->r_dense, c->label_count));
+        if (c->r_dense.p != before) c->r_dense_zero = false;
+    }
+    if (!c->r_dense_zero) HIPCHECK(c, launch_fill_i64(c->stream, c->r_dense.p, 0, (int64_t)c->label_count));
+    c->r_dense_zero = false;
+    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->done_fx.p), 0, ni));
+    for (int j = 0; j <= J; ++j) {
+        if (!any[j]) continue;
+        const InstState* stj = c->st_hist.p + (size_t)j * ni;
+        const double* lamj = c->lam_hist.p + (size_t)j * ni;
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
         HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
         uint32_t* ecode = c->ecode.p;
         RC(next_epoch(c, c->labels, c->epoch, ecode));
-        HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, c->st.p,
+        HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, stj,
                                 delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
-        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->r_count.p), 0, 1));
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
-        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl, 1,
-                                c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p, ecode));
-        HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, c->st.p, fl,
+        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
+                                c->r_dense.p, c->done_fx.p, ecode));
+        HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, stj, fl,
                                     scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
-                                    c->lambda.p, c->r_orig.p, c->r_dest.p, c->r_w.p, c->r_count.p, c->done_fx.p, 0,
-                                    nullptr, 0, ecode));
-        unsigned long long cnt = 0;
-        HIPCHECK(c, hipMemcpyAsync(&cnt, c->r_count.p, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
-        HIPCHECK(c, hipStreamSynchronize(c->stream));
-        if (cnt > (unsigned long long)c->P) return set_err(c, QDTA_EHIP, "residual overflow");
-        std::vector<int32_t> ho(cnt), hd(cnt);
-        std::vector<int64_t> hw(cnt);
-        if (cnt) {
-            HIPCHECK(c, hipMemcpyAsync(ho.data(), c->r_orig.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
-            HIPCHECK(c, hipMemcpyAsync(hd.data(), c->r_dest.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
-            HIPCHECK(c, hipMemcpyAsync(hw.data(), c->r_w.p, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, c->stream));
-            HIPCHECK(c, hipStreamSynchronize(c->stream));
-        }
-        for (unsigned long long k = 0; k < cnt; ++k) {
-            int qi = hd[k];
-            int i = c->h_dest_inst[qi];
-            ro[i].push_back(ho[k]);
-            rd[i].push_back(c->h_dest_node[qi] - c->h_inst[i].node0);
-            rw[i].push_back(hw[k]);
-        }
+                                    lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0, ecode));
+    }
+    // compact: legs per tree, offsets, then the legs in (destination, origin) order
+    RC(dalloc(c, c->r_cnt, (size_t)std::max<int64_t>(c->Q, 1)));
+    HIPCHECK(c, launch_resid_count(c->stream, net, dem, c->r_dense.p, c->r_cnt.p));
+    std::vector<int64_t> cnt((size_t)c->Q), off((size_t)c->Q);
+    if (c->Q) HIPCHECK(c, hipMemcpyAsync(cnt.data(), c->r_cnt.p, sizeof(int64_t) * c->Q, hipMemcpyDeviceToHost,
+                                         c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    int64_t total = 0;
+    for (int64_t t = 0; t < c->Q; ++t) {
+        off[t] = total;
+        total += cnt[t];
+    }
+    RC(dalloc(c, c->r_orig, (size_t)std::max<int64_t>(total, 1)));
+    RC(dalloc(c, c->r_dest, (size_t)std::max<int64_t>(total, 1)));
+    RC(dalloc(c, c->r_w, (size_t)std::max<int64_t>(total, 1)));
+    if (c->Q) HIPCHECK(c, hipMemcpy(c->r_cnt.p, off.data(), sizeof(int64_t) * c->Q, hipMemcpyHostToDevice));
+    HIPCHECK(c, launch_resid_write(c->stream, net, dem, c->r_dense.p, c->r_cnt.p, c->r_orig.p, c->r_dest.p,
+                                   c->r_w.p));
+    std::vector<int32_t> ho((size_t)total), hq((size_t)total);
+    std::vector<int64_t> hw((size_t)total);
+    if (total) {
+        HIPCHECK(c, hipMemcpyAsync(ho.data(), c->r_orig.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(hq.data(), c->r_dest.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(hw.data(), c->r_w.p, sizeof(int64_t) * total, hipMemcpyDeviceToHost, c->stream));
     }
     std::vector<unsigned long long> done(ni);
     HIPCHECK(c, hipMemcpyAsync(done.data(), c->done_fx.p, sizeof(unsigned long long) * ni, hipMemcpyDeviceToHost,
                                c->stream));
     int h[4];
-    RC(read_flags(c, h));
+    RC(read_flags(c, h));                  // synchronises the stream
+    c->r_dense_zero = true;
+    // trees are instance-major, so each instance's legs are one run
+    int64_t k = 0;
     for (int i = 0; i < ni; ++i) {
         Instance& I = c->inst[i];
-        merge_legs(ro[i], rd[i], rw[i]);
-        I.r_orig.swap(ro[i]);
-        I.r_dest.swap(rd[i]);
-        I.r_w.swap(rw[i]);
+        const int64_t end = c->dest_off[i + 1];
+        int64_t k1 = k;
+        while (k1 < total && hq[k1] < end) ++k1;
+        I.r_orig.assign(ho.begin() + k, ho.begin() + k1);
+        I.r_dest.resize(k1 - k);
+        for (int64_t x = k; x < k1; ++x) I.r_dest[x - k] = c->h_dest_node[hq[x]] - c->h_inst[i].node0;
+        I.r_w.assign(hw.begin() + k, hw.begin() + k1);
         I.r_done = (int64_t)done[i];
+        k = k1;
     }
     c->solved = false;
     RC(flag_code(c, h));
