@@ -90,7 +90,7 @@ typedef struct {
     int32_t keep_history;  /* record (alpha_j, c_j) per iteration; needed by qdta_advance_interval */
     int32_t waves_per_cu;  /* shortest-path trees in flight per compute unit: 0 auto (16), else 1..32 */
     double delta_scale;    /* delta-stepping bucket width as a multiple of the instance's geometric-mean
-                              link cost: 0 auto (5.0); any value > 0 gives the same trees, only the speed
+                              link cost: 0 auto (10.0); any value > 0 gives the same trees, only the speed
                               changes */
     int32_t sssp_shape;    /* shortest-path kernel shape, nodes per lane per step x links per lane per
                               chunk: 0 auto, 1 (1,4), 2 (2,4), 3 (4,4), 4 (4,8), 5 (8,8), 6 (1,1) */

@@ -11,10 +11,9 @@ constexpr int kChunk = 2048;             // links per workgroup in link-parallel
 constexpr uint32_t kInfBits = 0x7f800000u;
 constexpr int kMaxK = 64;                // step sizes per line-search pass
 
-// One shortest-path label word: (0x7fffffff - epoch) << 33 | FP32 bits of
-// the distance << 1 | not-queued flag.
-typedef unsigned long long label_t;
-constexpr uint32_t kMaxEpoch = 0x7ffffffeu;
+// One shortest-path label word: (not-queued flag << 31) | FP32 bits of the
+// distance.
+typedef uint32_t label_t;
 
 // Static description of one instance inside the concatenated layout.
 struct InstDev {
@@ -69,7 +68,7 @@ struct NetDev {
 struct DemDev {
     const int32_t* dest_node;// [Q] global node of each destination
     const int32_t* dest_inst;// [Q]
-    const int64_t* dest_lab; // [Q] offset (labels) of the tree's label of node 0
+    const int64_t* dest_lab; // [Q] offset in labels of the tree's label of node 0 (a multiple of 32)
     const int32_t* qptr;     // [Q+1] legs of each destination (global leg index)
     const int32_t* leg_orig; // [P] global origin node
     const int64_t* leg_dfx;  // [P]
@@ -108,7 +107,6 @@ hipError_t launch_gap_sums(hipStream_t s, const NetDev& net, const float* cost, 
 
 hipError_t launch_gap_decide(hipStream_t s, int ninst, const long long* acc, InstState* st, int stop_rule,
                              double tol, int fixed_iters, int cap_iter);
-hipError_t launch_epoch_next(hipStream_t s, uint32_t* ecode);
 
 hipError_t launch_ls_begin(hipStream_t s, int ninst, InstState* st, double* alphas, int K, int ls_mode,
                            double dx, long long* ls_acc, int only_fallback);
@@ -141,23 +139,23 @@ hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, dou
                         double* logsum);
 hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, const uint2* radj, label_t* labels,
                         const Scratch& scr, int slots, const InstState* st, const float* delta_inst, int variant,
-                        const uint32_t* ecode, int early, int t_begin, int t_end);
+                        int early, int t_begin, int t_end);
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst, double* logsum, int variant, const uint32_t* ecode, int early);
+                       float* delta_inst, double* logsum, int variant, int early);
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int64_t* r_dense,
-                       unsigned long long* done_fx, const uint32_t* ecode, int l_begin = 0, int l_end = -1);
+                       unsigned long long* done_fx, int l_begin = 0, int l_end = -1);
 
 hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int64_t* r_dense,
                            unsigned long long* done_fx,
-                           int trees_mode, int32_t* succ_out, int32_t n_out, const uint32_t* ecode);
+                           int trees_mode, int32_t* succ_out, int32_t n_out);
 
 // residual accumulator (indexed like the labels) -> legs in (destination, origin) order
 hipError_t launch_resid_count(hipStream_t s, const NetDev& net, const DemDev& dem, const int64_t* r_dense,
@@ -167,7 +165,6 @@ hipError_t launch_resid_write(hipStream_t s, const NetDev& net, const DemDev& de
 
 hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                             const float* cost_local, int32_t inst, float* dist, int32_t* succ,
-                            int32_t* absorb_q,
-                            const uint32_t* ecode);
+                            int32_t* absorb_q);
 
 }  // namespace qdta

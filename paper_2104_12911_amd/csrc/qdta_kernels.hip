@@ -584,23 +584,25 @@ hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, doub
 // ---------------------------------------------------------------------------
 // A2: shortest-path trees, one wavefront per destination (delta-stepping)
 // ---------------------------------------------------------------------------
-// A tree's label of node v is one 64-bit word
-//     (E << 33) | (FP32 bits of D(v) << 1) | f,   E = 0x7fffffff - epoch,
-// where f = 1 when v is NOT queued.  Each shortest-path launch uses a new
-// epoch, so a word written by an earlier launch compares above every word of
-// the current one and reads as +inf, not queued: no per-launch reset.  Within
-// an epoch, unsigned order is (value, flag) order, so one atomicMin both
-// lowers the value and marks the node queued, and its return value tells
-// whether this relaxation was the one that queued it; one atomicOr(1) takes
-// a node off the queue and returns its current value.
-__device__ __forceinline__ label_t lab_word(uint32_t ecode, uint32_t vbits, uint32_t notq) {
-    return ((label_t)ecode << 33) | ((label_t)vbits << 1) | (label_t)notq;
+// A tree's label of node v is one 32-bit word, tree t's at
+// labels[dest_lab[t] + v]:
+//     (f << 31) | FP32 bits of D(v),   f = 1 when v is NOT queued.
+// D >= 0, so the value bits order like the value.  Among queued words
+// (f = 0) unsigned order is value order, so an atomicMin of a queued
+// candidate both lowers the value and marks the node queued -- provided the
+// candidate is below the current value, which the relaxation checks first
+// with a coherent read (only the tree's own wavefront writes its labels, and
+// lanes of one instruction only write queued words, which keeps that check
+// valid).  The word it replaced tells whether this relaxation queued the
+// node.  An atomicOr of the flag takes a node off the queue and returns its
+// label.  A tree starts from +inf, not queued, on every node.
+constexpr uint32_t kNotQueued = 0x80000000u;
+constexpr uint32_t kValueBits = 0x7fffffffu;
+__device__ __forceinline__ const label_t* tree_labels(const label_t* labels, const DemDev& dem, int t) {
+    return labels + dem.dest_lab[t];
 }
-__device__ __forceinline__ uint32_t word_vbits(label_t w, uint32_t ecode) {
-    return (uint32_t)(w >> 33) == ecode ? (uint32_t)(w >> 1) : kInfBits;
-}
-__device__ __forceinline__ float lab_val(const label_t* lab, int64_t i, uint32_t ecode) {
-    return __uint_as_float(word_vbits(lab[i], ecode));
+__device__ __forceinline__ float lab_val(const label_t* lab, int64_t v) {
+    return __uint_as_float(lab[v] & kValueBits);
 }
 
 __device__ __forceinline__ unsigned long long lanes_below(int lane) {
@@ -619,9 +621,13 @@ __device__ __forceinline__ float wave_min(float x) {
 //   - Up to 64 nodes are popped per step (FIFO ring); their in-links are
 //     flattened across the lanes with a prefix sum of the in-degrees, so each
 //     step relaxes 64 links whatever the degree mix.
-//   - A relaxation that queues a node (the label word's flag was 1) puts it in
-//     the near queue when its label is below the bucket bound thr, else in the
-//     far queue together with that label.  A node is in at most one queue.
+//   - A relaxation that lowers a label and finds the node's queued bit clear
+//     sets it and puts the node in the near queue when its label is below the
+//     bucket bound thr, else in the far queue together with that label.  A
+//     node is in at most one queue.  A pop clears the bit first, then reads
+//     the label, so an improvement after the read queues the node again.
+//   - A tree starts by writing +inf over its labels and clearing the wave's
+//     bitmap (128-byte aligned streaming stores).
 //   - When the near queue empties, thr moves to delta above the smallest far
 //     label (kept as a running minimum) and one pass moves the far entries
 //     below thr to the near queue.
@@ -638,10 +644,9 @@ __device__ __forceinline__ float wave_min(float x) {
 template <int U, int V>
 __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const uint2* __restrict__ radj,
                                                  label_t* labels, Scratch scr, const InstState* st,
-                                                 const float* __restrict__ delta_inst, const uint32_t* ecode_p,
-                                                 int early, int t_begin, int t_end) {
+                                                 const float* __restrict__ delta_inst, int early, int t_begin,
+                                                 int t_end) {
     constexpr int W = kWG / 64;
-    const uint32_t ecode = *ecode_p;
     constexpr int NP = 64 * U;                    // nodes per step
     __shared__ int s_pre[W][NP + 1];
     __shared__ float s_dw[W][NP];
@@ -669,8 +674,18 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
         label_t* D = labels + dem.dest_lab[t];
         const int root = dem.dest_node[t] - node0;
         const float delta = delta_inst[inst];
+        // reset the tree's labels to +inf, not queued (the region is 128-byte
+        // aligned and padded to a multiple of 32 words)
+        {
+            uint4* D4 = reinterpret_cast<uint4*>(D);
+            const uint32_t w0 = kNotQueued | kInfBits;
+            const uint4 inf4 = make_uint4(w0, w0, w0, w0);
+            const int n4 = (n + 31) / 32 * 8;
+            for (int i = lane; i < n4; i += 64) D4[i] = inf4;
+        }
+        __threadfence_block();
         if (lane == 0) {
-            D[root] = lab_word(ecode, 0u, 0u);    // value 0, queued
+            D[root] = 0u;                         // value 0, queued
             nearq[0] = root;
         }
         __threadfence_block();
@@ -693,11 +708,11 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                         int pos = head + j;
                         if (pos >= R) pos -= R;
                         const int w = nearq[pos];
-                        const label_t lw = atomicOr(&D[w], 1ull);      // dequeue, read the label
+                        const uint32_t lw = atomicOr(&D[w], kNotQueued);   // dequeue, read the label
                         const int e0 = rptr[w];
                         deg[u] = rptr[w + 1] - e0;
                         se0[j] = e0;
-                        sdw[j] = __uint_as_float((uint32_t)(lw >> 1));
+                        sdw[j] = __uint_as_float(lw & kValueBits);
                     }
                 }
                 head += k;
@@ -740,23 +755,19 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                             cd[x] = sdw[lo] + __uint_as_float(r.y);
                         }
                     }
-                    uint32_t cur[V];
+                    uint32_t cur[V];               // current value bits (coherent: see the word layout)
 #pragma unroll
-                    for (int x = 0; x < V; ++x) cur[x] = ok[x] ? word_vbits(D[vv[x]], ecode) : 0u;
+                    for (int x = 0; x < V; ++x) cur[x] = ok[x] ? (ld_coherent(&D[vv[x]]) & kValueBits) : 0u;
                     bool pn[V], pf[V];
 #pragma unroll
                     for (int x = 0; x < V; ++x) {
                         pn[x] = pf[x] = false;
                         const uint32_t cb = __float_as_uint(cd[x]);
-                        if (ok[x] && cb < cur[x]) {
-                            const label_t old = atomicMin(&D[vv[x]], lab_word(ecode, cb, 0u));
-                            // this relaxation queued v: the word it replaced was of an
-                            // earlier epoch, or not queued and not below cb
-                            const bool fresh = (uint32_t)(old >> 33) != ecode;
-                            if (fresh || ((old & 1ull) && cb <= (uint32_t)(old >> 1))) {
-                                pn[x] = cd[x] < thr;
-                                pf[x] = !pn[x];
-                            }
+                        // cb is a queued word below the value: the min lowers the value;
+                        // a replaced word that was not queued means this relaxation queued v
+                        if (ok[x] && cb < cur[x] && (atomicMin(&D[vv[x]], cb) & kNotQueued)) {
+                            pn[x] = cd[x] < thr;
+                            pf[x] = !pn[x];
                         }
                     }
                     float fm = __uint_as_float(kInfBits);
@@ -786,7 +797,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                 bool pend = false;
                 for (int l = l0 + lane; l < l1; l += 64) {
                     const int o = dem.leg_orig[l] - node0;
-                    if (!(__uint_as_float(word_vbits(ld_coherent64(&D[o]), ecode)) < thr)) pend = true;
+                    if (!(__uint_as_float(ld_coherent(&D[o]) & kValueBits) < thr)) pend = true;
                 }
                 if (__ballot(pend) == 0ull) {
                     // exact: move far entries whose current label is below thr
@@ -795,7 +806,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                         const int i = i0 + lane;
                         const bool h = i < fcnt;
                         const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
-                        const float dv = h ? __uint_as_float(word_vbits(ld_coherent64(&D[ent.x]), ecode)) : 0.0f;
+                        const float dv = h ? __uint_as_float(ld_coherent(&D[ent.x]) & kValueBits) : 0.0f;
                         const bool late = h && dv < thr;
                         const unsigned long long bl = __ballot(late);
                         if (late) {
@@ -885,15 +896,6 @@ __global__ void k_delta(NetDev net, const double* logsum, double scale, float* d
     delta_inst[inst] = (float)d;
 }
 
-// Next label epoch: the code 0x7fffffff - epoch is kept in device memory so
-// a captured iteration advances it on every replay.
-__global__ void k_epoch_next(uint32_t* ecode) { *ecode = *ecode - 1u; }
-
-hipError_t launch_epoch_next(hipStream_t s, uint32_t* ecode) {
-    hipLaunchKernelGGL(k_epoch_next, dim3(1), dim3(1), 0, s, ecode);
-    return hipGetLastError();
-}
-
 hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, double delta_scale, float* delta_inst,
                         double* logsum) {
     hipError_t e0 = launch_fill_i64(s, reinterpret_cast<int64_t*>(logsum), 0, net.ninst);
@@ -905,14 +907,14 @@ hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, dou
 
 hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, const uint2* radj, label_t* labels,
                         const Scratch& scr, int slots, const InstState* st, const float* delta_inst, int variant,
-                        const uint32_t* ecode, int early, int t_begin, int t_end) {
+                        int early, int t_begin, int t_end) {
     if (t_end <= t_begin) return hipSuccess;
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
     const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
     dim3 g(blocks), b(kWG);
 #define QDTA_SSSP(U, V) \
-    hipLaunchKernelGGL((k_sssp_ds<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, ecode, early, \
+    hipLaunchKernelGGL((k_sssp_ds<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, \
                        t_begin, t_end)
     switch (variant) {
         case 0: QDTA_SSSP(1, 4); break;
@@ -928,11 +930,11 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
 
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst, double* logsum, int variant, const uint32_t* ecode, int early) {
+                       float* delta_inst, double* logsum, int variant, int early) {
     if (dem.Q == 0) return hipSuccess;
     hipError_t e = launch_delta(s, net, cost, delta_scale, delta_inst, logsum);
     if (e != hipSuccess) return e;
-    return launch_trees(s, net, dem, radj, labels, scr, slots, st, delta_inst, variant, ecode, early, 0, dem.Q);
+    return launch_trees(s, net, dem, radj, labels, scr, slots, st, delta_inst, variant, early, 0, dem.Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -941,11 +943,11 @@ hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, cons
 // Successor of u on the tree whose labels are lab[node - node0]: the
 // lowest-uid out-link (u, w) that is tight, fl32(D(w) + c) == D(u), and
 // strict, D(w) < D(u).  -1 when FP32 absorption leaves none.
-__device__ __forceinline__ int succ_strict(const NetDev& net, const label_t* lab, uint32_t ecode, int node0, int u,
-                                          float du, const float* tree_cost) {
+__device__ __forceinline__ int succ_strict(const NetDev& net, const label_t* lab, int node0, int u, float du,
+                                          const float* tree_cost) {
     const int e1 = net.row_ptr[u + 1];
     for (int e = net.row_ptr[u]; e < e1; ++e) {
-        const float dw = lab_val(lab, net.col[e] - node0, ecode);
+        const float dw = lab_val(lab, net.col[e] - node0);
         if (dw < du && dw + tree_cost[e] == du) return e;
     }
     return -1;
@@ -981,9 +983,8 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                               const float* __restrict__ tree_cost,
                                               const float* __restrict__ time_cost, const InstState* st,
-                                              FlagsDev fl, WalkOut o, const uint32_t* ecode_p, int l_begin, int l_end) {
+                                              FlagsDev fl, WalkOut o, int l_begin, int l_end) {
     const int l = l_begin + blockIdx.x * kWG + threadIdx.x;
-    const uint32_t ecode = *ecode_p;
     if (l >= l_end) return;
     const int qi = dem.leg_q[l];
     const int inst = dem.dest_inst[qi];
@@ -991,10 +992,10 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
     const InstDev I = net.inst[inst];
     const int node0 = I.node0;
     const int q = dem.dest_node[qi];
-    const label_t* lab = labels + dem.dest_lab[qi];
+    const label_t* lab = tree_labels(labels, dem, qi);
     const int64_t d = dem.leg_dfx[l];
     int u = dem.leg_orig[l];
-    float du = lab_val(lab, u - node0, ecode);
+    float du = lab_val(lab, u - node0);
     fl.int_node[l] = -1;
     if (!(du <= 3.4028234663852886e38f)) {       // origin cannot reach q
         atomicOr(fl.err_unreach, 1);
@@ -1004,7 +1005,7 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
     float tau = 0.0f;
     for (int hops = 0; u != q; ++hops) {
         if (I.rule == RULE_CEIL && tau >= I.dt32) break;
-        const int e = succ_strict(net, lab, ecode, node0, u, du, tree_cost);
+        const int e = succ_strict(net, lab, node0, u, du, tree_cost);
         if (e < 0 || hops > I.n) {                // absorption: finish in the fallback
             fl.int_node[l] = u;
             fl.int_tau[l] = tau;
@@ -1017,7 +1018,7 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
         if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
         tau = nt;
         u = net.col[e];
-        du = lab_val(lab, u - node0, ecode);
+        du = lab_val(lab, u - node0);
     }
     finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
 }
@@ -1026,12 +1027,12 @@ hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, cons
                        const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int64_t* r_dense, unsigned long long* done_fx,
-                       const uint32_t* ecode, int l_begin, int l_end) {
+                       int l_begin, int l_end) {
     if (l_end < 0) l_end = dem.P;
     if (l_end <= l_begin) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
     hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, tree_cost,
-                       time_cost, st, fl, o, ecode, l_begin, l_end);
+                       time_cost, st, fl, o, l_begin, l_end);
     return hipGetLastError();
 }
 
@@ -1047,9 +1048,8 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                                                   const float* __restrict__ tree_cost,
                                                   const float* __restrict__ time_cost, const InstState* st,
                                                   FlagsDev fl, Scratch scr, WalkOut o, int trees_mode,
-                                                  int32_t* succ_out, int32_t n_out, const uint32_t* ecode_p) {
+                                                  int32_t* succ_out, int32_t n_out) {
     __shared__ int s_cnt[2];
-    const uint32_t ecode = *ecode_p;
     int32_t* hop = scr.farq + (int64_t)blockIdx.x * scr.nmax;
     int32_t* qbase = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
     for (int qi = blockIdx.x; qi < dem.Q; qi += gridDim.x) {
@@ -1058,7 +1058,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
         if (!inst_live(st, inst)) continue;
         const InstDev I = net.inst[inst];
         const int n = I.n, node0 = I.node0;
-        const label_t* lab = labels + dem.dest_lab[qi];
+        const label_t* lab = tree_labels(labels, dem, qi);
         const int q = dem.dest_node[qi];
         // breadth-first levels in one FIFO: level L occupies [s_cnt[0], s_cnt[1])
         for (int v = threadIdx.x; v < n; v += kWG) hop[v] = -1;
@@ -1072,11 +1072,11 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
             __syncthreads();
             for (int i = lo + threadIdx.x; i < hi; i += kWG) {
                 const int u = qbase[i];
-                const float du = lab_val(lab, u, ecode);
+                const float du = lab_val(lab, u);
                 for (int e = net.rptr[node0 + u]; e < net.rptr[node0 + u + 1]; ++e) {
                     const int v = net.rsrc[e] - node0;
                     const int link = net.rlink[e];
-                    const float dv = lab_val(lab, v, ecode);
+                    const float dv = lab_val(lab, v);
                     if (dv <= 3.4028234663852886e38f && du + tree_cost[link] == dv) {
                         if (atomicCAS(&hop[v], -1, level + 1) == -1) {
                             int pos = atomicAdd(&s_cnt[1], 1);
@@ -1091,12 +1091,12 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
         }
         // successor with the hop rule where no strict tight link exists
         auto succ_full = [&](int u, float du) -> int {
-            int e = succ_strict(net, lab, ecode, node0, u, du, tree_cost);
+            int e = succ_strict(net, lab, node0, u, du, tree_cost);
             if (e >= 0) return e;
             const int hu = ld_coherent(&hop[u - node0]);
             for (int k = net.row_ptr[u]; k < net.row_ptr[u + 1]; ++k) {
                 const int w = net.col[k];
-                const float dw = lab_val(lab, w - node0, ecode);
+                const float dw = lab_val(lab, w - node0);
                 if (dw + tree_cost[k] == du && ld_coherent(&hop[w - node0]) == hu - 1) return k;
             }
             return -1;
@@ -1105,7 +1105,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
             const int t = qi;
             for (int v = threadIdx.x; v < n; v += kWG) {
                 const int g = node0 + v;
-                const float dv = lab_val(lab, v, ecode);
+                const float dv = lab_val(lab, v);
                 if (g == q || !(dv <= 3.4028234663852886e38f)) continue;
                 if (succ_out[(int64_t)t * n_out + v] >= 0) continue;
                 const int e = succ_full(g, dv);
@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                 int u = fl.int_node[l];
                 if (u < 0) continue;
                 float tau = fl.int_tau[l];
-                float du = lab_val(lab, u - node0, ecode);
+                float du = lab_val(lab, u - node0);
                 const int64_t d = dem.leg_dfx[l];
                 for (int hops = 0; u != q && hops <= n; ++hops) {
                     if (I.rule == RULE_CEIL && tau >= I.dt32) break;
@@ -1127,7 +1127,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                     if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
                     tau = nt;
                     u = net.col[e];
-                    du = lab_val(lab, u - node0, ecode);
+                    du = lab_val(lab, u - node0);
                 }
                 fl.int_node[l] = -1;
                 finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
@@ -1142,11 +1142,11 @@ hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, 
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int64_t* r_dense,
                            unsigned long long* done_fx, int trees_mode,
-                           int32_t* succ_out, int32_t n_out, const uint32_t* ecode) {
+                           int32_t* succ_out, int32_t n_out) {
     if (dem.Q == 0) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
     hipLaunchKernelGGL(k_fallback, dim3(slots), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost, st, fl, scr,
-                       o, trees_mode, succ_out, n_out, ecode);
+                       o, trees_mode, succ_out, n_out);
     return hipGetLastError();
 }
 
@@ -1230,21 +1230,20 @@ hipError_t launch_resid_write(hipStream_t s, const NetDev& net, const DemDev& de
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_trees_out(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                                    const float* __restrict__ cost, int32_t inst, float* dist,
-                                                   int32_t* succ, int32_t* absorb_q, const uint32_t* ecode_p) {
+                                                   int32_t* succ, int32_t* absorb_q) {
     const InstDev I = net.inst[inst];
-    const uint32_t ecode = *ecode_p;
     const int n = I.n;
     const int64_t total = (int64_t)dem.Q * n;
     for (int64_t i = blockIdx.x * (int64_t)kWG + threadIdx.x; i < total; i += (int64_t)gridDim.x * kWG) {
         const int t = (int)(i / n);
         const int v = (int)(i - (int64_t)t * n);
-        const label_t* lab = labels + dem.dest_lab[t];
-        const float dv = lab_val(lab, v, ecode);
+        const label_t* lab = tree_labels(labels, dem, t);
+        const float dv = lab_val(lab, v);
         dist[i] = dv;
         const int g = I.node0 + v;
         int e = -1;
         if (g != dem.dest_node[t] && dv <= 3.4028234663852886e38f) {
-            e = succ_strict(net, lab, ecode, I.node0, g, dv, cost);   // cost: global link order
+            e = succ_strict(net, lab, I.node0, g, dv, cost);   // cost: global link order
             if (e < 0) absorb_q[t] = 1;
         }
         succ[i] = e >= 0 ? e - I.link0 : -1;
@@ -1252,11 +1251,9 @@ __global__ __launch_bounds__(kWG) void k_trees_out(NetDev net, DemDev dem, const
 }
 
 hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
-                            const float* cost, int32_t inst, float* dist, int32_t* succ, int32_t* absorb_q,
-                            const uint32_t* ecode) {
+                            const float* cost, int32_t inst, float* dist, int32_t* succ, int32_t* absorb_q) {
     if (dem.Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trees_out, dim3(2048), dim3(kWG), 0, s, net, dem, labels, cost, inst, dist, succ, absorb_q,
-                       ecode);
+    hipLaunchKernelGGL(k_trees_out, dim3(2048), dim3(kWG), 0, s, net, dem, labels, cost, inst, dist, succ, absorb_q);
     return hipGetLastError();
 }
 

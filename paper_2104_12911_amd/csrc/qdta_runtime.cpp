@@ -71,12 +71,12 @@ struct qdta_ctx {
     DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q;
     DBuf<int64_t> dest_lab, leg_dfx;
     std::vector<int32_t> h_dest_inst, h_dest_node, h_qptr;
-    DBuf<label_t> labels;
+    DBuf<label_t> labels;         // 32-bit label words, tree-major, each tree 128-byte aligned
     DBuf<int32_t> nearq, farq;
+
     DBuf<int32_t> work;
     DBuf<float> delta_inst;
     DBuf<double> logsum;
-    DBuf<uint32_t> ecode;         // [0] epoch code of `labels`, [1] of temporary label buffers
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
@@ -97,7 +97,6 @@ struct qdta_ctx {
     DBuf<InstState> st_hist;      // per-iterate instance state of a residual pass
     DBuf<double> lam_hist;
     DBuf<unsigned long long> r_count, done_fx;
-    uint32_t epoch = 0;           // epoch of the last shortest-path launch on `labels`
     uint64_t gen = 0;             // bumped on every (re)allocation and every rebuild of the
                                   // network or demand tables: a captured iteration is valid
                                   // only for the generation it was captured in
@@ -203,7 +202,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 }
 
 int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 16; }
-double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 5.0; }
+double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
 int sssp_variant(const qdta_opts* o) { return (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2; }
 
@@ -293,7 +292,6 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->alpha_arr, ni));
     RC(dalloc(c, c->lambda, ni));
     RC(dalloc(c, c->flags, 4));
-    RC(dalloc(c, c->ecode, 2));
     RC(dalloc(c, c->done_fx, ni));
     RC(dalloc(c, c->r_count, 1));
     if (c->h_st_n < ni) {
@@ -327,8 +325,10 @@ NetDev net_view(qdta_ctx* c) {
     return v;
 }
 
-// Trees are stored tree-major: destination t's labels occupy n label words at
-// dest_lab[t].  Destinations of an instance are in ascending node order.
+// Destinations of an instance are in ascending node order; tree t's labels
+// are n 32-bit words at dest_lab[t], each tree padded to 32 words (128 bytes).
+int64_t tree_words(int64_t n) { return (n + 31) / 32 * 32; }
+
 int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
     int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1), (int64_t)c->cus * wpc);
     slots = (slots + 3) / 4 * 4;                 // whole workgroups of four wavefronts
@@ -372,7 +372,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
             dest_node.push_back(d.node0 + q);
             dest_inst.push_back(i);
             dest_lab.push_back(lab);
-            lab += I.n;
+            lab += tree_words(I.n);
             while (p < I.orig.size() && I.dest[p] == q) {
                 leg_orig.push_back(d.node0 + I.orig[p]);
                 leg_dfx.push_back(I.dfx[p]);
@@ -402,11 +402,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     RC(upload(c, c->leg_dfx, leg_dfx));
     RC(upload(c, c->leg_q, leg_q));
     RC(upload(c, c->d_inst, c->h_inst));
-    {
-        label_t* before = c->labels.p;
-        RC(dalloc(c, c->labels, c->label_count));
-        if (c->labels.p != before) c->epoch = 0;      // fresh memory: reset on the next launch
-    }
+    RC(dalloc(c, c->labels, c->label_count));
     RC(dalloc(c, c->absorb_q, (size_t)c->Q));
     RC(dalloc(c, c->int_node, (size_t)c->P));
     RC(dalloc(c, c->int_tau, (size_t)c->P));
@@ -477,23 +473,6 @@ int read_flags(qdta_ctx* c, int* h) {
     return QDTA_OK;
 }
 
-// A new epoch for the next shortest-path launch on a label buffer.  The
-// epoch code (0x7fffffff - epoch) lives in device memory so a captured
-// iteration can advance it; `epoch` counts launches on the host, and after
-// kMaxEpoch of them (or on fresh memory, epoch = 0) the buffer is reset to
-// the oldest epoch (all ones).
-int next_epoch(qdta_ctx* c, DBuf<label_t>& lab, uint32_t& epoch, uint32_t* ecode_dev) {
-    if (epoch == 0 || epoch >= kMaxEpoch) {
-        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(lab.p), -1, (int64_t)lab.n));
-        HIPCHECK(c, launch_fill_u32(c->stream, ecode_dev, 0x7fffffffu - 1u, 1));
-        epoch = 1;
-        return QDTA_OK;
-    }
-    HIPCHECK(c, launch_epoch_next(c->stream, ecode_dev));
-    epoch += 1;
-    return QDTA_OK;
-}
-
 constexpr int kPhases = 7;
 enum { PH_BPR = 0, PH_SSSP = 1, PH_WALK = 2, PH_GAP = 3, PH_LS = 4, PH_UPDATE = 5, PH_GRAPH = 6 };
 
@@ -525,18 +504,16 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
     FlagsDev fl = flags_view(c);
-    uint32_t* ecode = c->ecode.p;
-    RC(next_epoch(c, c->labels, c->epoch, ecode));
     if (marks) RC(prof_mark(c, PH_SSSP, 0));
     if (o->launch_form == 2) {
         // plain form: one launch per destination tree (one workgroup each)
         HIPCHECK(c, launch_delta(c->stream, net, cost, delta_scale(o), c->delta_inst.p, c->logsum.p));
         for (int64_t t = 0; t < c->Q; ++t)
             HIPCHECK(c, launch_trees(c->stream, net, dem, c->radj.p, c->labels.p, scr_view(c), 4, st, c->delta_inst.p,
-                                     sssp_variant(o), ecode, 1, (int)t, (int)t + 1));
+                                     sssp_variant(o), 1, (int)t, (int)t + 1));
     } else {
         HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->radj.p, c->labels.p, scr_view(c), c->slots, st,
-                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
+                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
     }
     if (marks) RC(prof_mark(c, PH_SSSP, 1));
     if (marks) RC(prof_mark(c, PH_WALK, 0));
@@ -545,14 +522,14 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     if (o->launch_form == 2) {
         for (int64_t qi = 0; qi < c->Q; ++qi)
             HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
-                                    nullptr, ecode, c->h_qptr[qi], c->h_qptr[qi + 1]));
+                                    nullptr, c->h_qptr[qi], c->h_qptr[qi + 1]));
     } else {
         HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
-                                nullptr, ecode));
+                                nullptr));
     }
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
                                 (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
-                                nullptr, 0, nullptr, 0, ecode));
+                                nullptr, 0, nullptr, 0));
     if (marks) RC(prof_mark(c, PH_WALK, 1));
     return QDTA_OK;
 }
@@ -937,7 +914,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     std::vector<int64_t> dl(nq);
     for (int t = 0; t < nq; ++t) {
         dn[t] = I.node0 + hd[t];
-        dl[t] = (int64_t)t * I.n;
+        dl[t] = (int64_t)t * tree_words(I.n);
     }
     DBuf<int32_t> ddn, ddi, aq;
     DBuf<int64_t> ddl;
@@ -955,7 +932,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         if ((rc = upload(c, ddn, dn))) break;
         if ((rc = upload(c, ddi, di))) break;
         if ((rc = upload(c, ddl, dl))) break;
-        if ((rc = dalloc(c, lab, (size_t)nq * I.n))) break;
+        if ((rc = dalloc(c, lab, (size_t)nq * tree_words(I.n)))) break;
         if ((rc = dalloc(c, aq, nq))) break;
         int saved_slots = c->slots;
         if ((rc = ensure_scratch(c, nq, std::max<int64_t>(c->nmax, I.n), waves_per_cu(o)))) break;
@@ -974,21 +951,18 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
             { rc = set_err(c, QDTA_EHIP, "copy cost: %s", hipGetErrorString(e)); break; }
         if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p)))
             { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
-        uint32_t tep = 0;
-        uint32_t* ecode = c->ecode.p + 1;
-        if ((rc = next_epoch(c, lab, tep, ecode))) break;
         if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, lab.p, scr_view(c), slots, nullptr,
-                             delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 0)))
+                             delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 0)))
             { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
         if ((e = launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(aq.p), 0u, nq)))
             { rc = set_err(c, QDTA_EHIP, "fill: %s", hipGetErrorString(e)); break; }
-        if ((e = launch_trees_out(c->stream, net, dem, lab.p, c->cost.p, inst, dist, succ, aq.p, ecode)))
+        if ((e = launch_trees_out(c->stream, net, dem, lab.p, c->cost.p, inst, dist, succ, aq.p)))
             { rc = set_err(c, QDTA_EHIP, "trees_out: %s", hipGetErrorString(e)); break; }
         FlagsDev fl = flags_view(c);
         fl.absorb_q = aq.p;
         if ((e = launch_fallback(c->stream, net, dem, lab.p, c->cost.p, c->cost.p, nullptr, nullptr, nullptr, fl,
                                  scr_view(c), (int)std::min<int64_t>(c->scr_slots, nq), 0, nullptr, nullptr, nullptr,
-                                 1, succ, I.n, ecode)))
+                                 1, succ, I.n)))
             { rc = set_err(c, QDTA_EHIP, "fallback: %s", hipGetErrorString(e)); break; }
         std::vector<int32_t> ha(nq);
         if ((e = hipMemcpyAsync(ha.data(), aq.p, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, c->stream)))
@@ -1171,15 +1145,12 @@ int capture_iteration(qdta_ctx* c, const qdta_opts* o) {
     drop_graph(c);
     if (!c->cap_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipStream_t saved = c->stream;
-    uint32_t saved_epoch = c->epoch;
     c->stream = c->cap_stream;
-    c->epoch = 1;                      // inside the graph the epoch only advances
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     int rc = e == hipSuccess ? enqueue_iteration(c, o, false) : QDTA_EHIP;
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     c->stream = saved;
-    c->epoch = saved_epoch;
     if (e != hipSuccess) return set_err(c, QDTA_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     if (rc < 0) {
         if (g) (void)hipGraphDestroy(g);
@@ -1200,14 +1171,9 @@ int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
     if (graph_form(o)) {
         if (!c->graph_exec || c->graph_gen != c->gen || memcmp(&c->graph_opts, o, sizeof(qdta_opts)) != 0)
             RC(capture_iteration(c, o));
-        if (c->epoch == 0 || c->epoch + 1 >= kMaxEpoch) {
-            c->epoch = 0;                  // reset outside the graph
-            RC(next_epoch(c, c->labels, c->epoch, c->ecode.p));
-        }
         RC(prof_mark(c, PH_GRAPH, 0));
         HIPCHECK(c, hipGraphLaunch(c->graph_exec, c->stream));
         RC(prof_mark(c, PH_GRAPH, 1));
-        c->epoch += 1;
     } else {
         RC(enqueue_iteration(c, o, true));
     }
@@ -1301,7 +1267,7 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
     HIPCHECK(c, hipEventCreate(&e0));
     HIPCHECK(c, hipEventCreate(&e1));
     static const int shapes[] = {3, 4, 2, 5};
-    static const double scales[] = {5.0, 2.5, 10.0};
+    static const double scales[] = {10.0, 5.0, 20.0};
     int best_shape = o->sssp_shape ? o->sssp_shape : 3;
     double best_scale = delta_scale(o), best = 1e300, spent = 0.0;
     int rc = QDTA_OK;
@@ -1311,11 +1277,10 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
             qdta_opts t = *o;
             t.sssp_shape = sh;
             t.delta_scale = sc;
-            if ((rc = next_epoch(c, c->labels, c->epoch, c->ecode.p)) < 0) break;
             hipError_t e = hipEventRecord(e0, c->stream);
             if (e == hipSuccess)
                 e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), c->slots, nullptr,
-                                delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), c->ecode.p, 1);
+                                delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), 1);
             if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
@@ -1429,16 +1394,14 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         const double* lamj = c->lam_hist.p + (size_t)j * ni;
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
         HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
-        uint32_t* ecode = c->ecode.p;
-        RC(next_epoch(c, c->labels, c->epoch, ecode));
         HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, stj,
-                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), ecode, 1));
+                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
         HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
-                                c->r_dense.p, c->done_fx.p, ecode));
+                                c->r_dense.p, c->done_fx.p));
         HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, stj, fl,
                                     scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
-                                    lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0, ecode));
+                                    lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0));
     }
     // compact: legs per tree, offsets, then the legs in (destination, origin) order
     RC(dalloc(c, c->r_cnt, (size_t)std::max<int64_t>(c->Q, 1)));
