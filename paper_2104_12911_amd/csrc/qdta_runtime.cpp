@@ -93,7 +93,7 @@ struct qdta_ctx {
     // residual output
     DBuf<int32_t> r_orig, r_dest;
     DBuf<int64_t> r_w, r_dense, r_cnt;
-    bool r_dense_zero = false;    // the accumulator is known to be all zero
+    size_t r_dense_zero = 0;      // leading accumulator words known to be zero
     DBuf<InstState> st_hist;      // per-iterate instance state of a residual pass
     DBuf<double> lam_hist;
     DBuf<unsigned long long> r_count, done_fx;
@@ -1381,12 +1381,19 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
     HIPCHECK(c, hipMemcpy(c->st_hist.p, hst.data(), sizeof(InstState) * hst.size(), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->lam_hist.p, hlam.data(), sizeof(double) * hlam.size(), hipMemcpyHostToDevice));
     {
-        int64_t* before = c->r_dense.p;
+        // a reallocated buffer (possibly at the same address) holds anything
+        const size_t before = c->r_dense.n;
         RC(dalloc(c, c->r_dense, c->label_count));
-        if (c->r_dense.p != before) c->r_dense_zero = false;
+        if (c->r_dense.n != before) c->r_dense_zero = 0;
     }
-    if (!c->r_dense_zero) HIPCHECK(c, launch_fill_i64(c->stream, c->r_dense.p, 0, (int64_t)c->label_count));
-    c->r_dense_zero = false;
+    if (c->r_dense_zero < c->label_count) {
+        HIPCHECK(c, launch_fill_i64(c->stream, c->r_dense.p, 0, (int64_t)c->label_count));
+        c->r_dense_zero = c->label_count;
+    }
+    // the walks write only inside the current trees' rows, and the compaction
+    // clears every word it finds non-zero there; until it has, nothing is known
+    const size_t zero_after = c->r_dense_zero;
+    c->r_dense_zero = 0;
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->done_fx.p), 0, ni));
     for (int j = 0; j <= J; ++j) {
         if (!any[j]) continue;
@@ -1433,7 +1440,7 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
                                c->stream));
     int h[4];
     RC(read_flags(c, h));                  // synchronises the stream
-    c->r_dense_zero = true;
+    c->r_dense_zero = zero_after;
     // trees are instance-major, so each instance's legs are one run
     int64_t k = 0;
     for (int i = 0; i < ni; ++i) {

@@ -118,6 +118,22 @@ def test_trees_tiny_all_destinations(torch_dev, q, orc, costs):
         assert (rc == q.WABSORB) == absorbed
 
 
+@pytest.mark.parametrize("costs", ["float", "int"])
+def test_trees_high_in_degree(torch_dev, q, orc, costs):
+    """Dense tiny graphs (in-degrees up to about 15, parallel links) put most
+    in-links in the overflow run of the node records."""
+    for seed in range(4):
+        rng = np.random.default_rng(900 + seed)
+        net = synth.tiny_network(12, 90, rng, costs=costs)
+        indeg = np.bincount(net.col, minlength=net.n)
+        assert indeg.max() > 8
+        D, S, rc = _trees(torch_dev, q, net, net.fftt, list(range(net.n)), ds=0.5)
+        for t in range(net.n):
+            Do, So, _ = orc.tree(net, net.fftt, t)
+            assert np.array_equal(D[t].view(np.uint32), Do.view(np.uint32)), (costs, seed, t)
+            assert np.array_equal(S[t], So), (costs, seed, t)
+
+
 @pytest.mark.parametrize("ds", [0.05, 1.0, 3.0, 40.0, 1e30])
 def test_trees_grid_every_bucket_width(torch_dev, q, orc, ds):
     """Any bucket width gives the same least fixed point: tiny buckets (near
