@@ -95,6 +95,10 @@ struct qdta_ctx {
     DBuf<int64_t> r_w, r_dense, r_cnt;
     size_t r_dense_zero = 0;      // leading accumulator words known to be zero
     DBuf<InstState> st_hist;      // per-iterate instance state of a residual pass
+    // labels of the solve's iterates, kept while device memory allows, so the
+    // residual pass walks them instead of growing the trees again
+    DBuf<label_t> lab_hist;
+    std::vector<char> lab_hist_ok;  // iterate j's labels are at lab_hist + j * label_count
     DBuf<double> lam_hist;
     DBuf<unsigned long long> r_count, done_fx;
     uint64_t gen = 0;             // bumped on every (re)allocation and every rebuild of the
@@ -409,6 +413,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     RC(ensure_scratch(c, c->Q, nmax, wpc));
     c->dem_dirty = false;
     c->solved = false;
+    c->lab_hist_ok.clear();
     c->gen++;                          // Q and P are baked into a captured iteration
     return QDTA_OK;
 }
@@ -618,6 +623,53 @@ int line_search_core(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const in
 int flag_code(qdta_ctx* c, const int* h) {
     if (h[0]) return set_err(c, QDTA_EOVF, "non-finite link cost or exact-sum overflow");
     if (h[1]) return set_err(c, QDTA_EUNREACH, "a leg's destination is unreachable from its origin");
+    return QDTA_OK;
+}
+
+// Slots of label history for this solve: as many iterates as fit in the free
+// device memory less a reserve for the residual pass (its accumulator and
+// outputs) and 16 GiB of headroom; at most max_iter + 1 and 64.
+int plan_label_history(qdta_ctx* c, const qdta_opts* o) {
+    c->lab_hist_ok.clear();
+    const size_t per = c->label_count;
+    if (per == 0) return QDTA_OK;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return QDTA_OK;
+    }
+    size_t avail = free_b + c->lab_hist.n * sizeof(label_t);
+    size_t reserve = (size_t)16 << 30;
+    if (c->r_dense.n < c->label_count) reserve += (c->label_count - c->r_dense.n) * sizeof(int64_t);
+    reserve += (size_t)c->P * 16;
+    if (avail <= reserve) return QDTA_OK;
+    size_t slots = (avail - reserve) / (per * sizeof(label_t));
+    const size_t want = o->fixed_iters > 0 ? (size_t)o->fixed_iters + 1 : (size_t)std::max(o->max_iter, 0) + 1;
+    slots = std::min<size_t>(std::min<size_t>(slots, want), 64);
+    if (slots == 0) return QDTA_OK;
+    if (c->lab_hist.n < slots * per) {
+        if (c->lab_hist.p) {
+            hipFree(c->lab_hist.p);
+            auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->lab_hist.p);
+            if (it != c->allocs.end()) c->allocs.erase(it);
+            c->lab_hist.p = nullptr;
+            c->lab_hist.n = 0;
+        }
+        if (dalloc(c, c->lab_hist, slots * per) != QDTA_OK) {   // not fatal: recompute instead
+            c->err.clear();
+            return QDTA_OK;
+        }
+    }
+    c->lab_hist_ok.assign(slots, 0);
+    return QDTA_OK;
+}
+
+// After iterate j's shortest paths: keep its labels if a slot is free.
+int stash_labels(qdta_ctx* c, int j) {
+    if (j < 0 || (size_t)j >= c->lab_hist_ok.size()) return QDTA_OK;
+    HIPCHECK(c, hipMemcpyAsync(c->lab_hist.p + (size_t)j * c->label_count, c->labels.p,
+                               sizeof(label_t) * c->label_count, hipMemcpyDeviceToDevice, c->stream));
+    c->lab_hist_ok[j] = 1;
     return QDTA_OK;
 }
 
@@ -1066,9 +1118,13 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     RC(prof_mark(c, PH_BPR, 0));
     HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, c->flags.p));
     RC(prof_mark(c, PH_BPR, 1));
+    c->lab_hist_ok.clear();
+    if (o->keep_history) RC(plan_label_history(c, o));
     RC(aon_core(c, o, c->cost.p, c->f.p, nullptr, c->st.p));
-    if (o->keep_history)
+    if (o->keep_history) {
         HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p, c->cost.p, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
+        RC(stash_labels(c, 0));
+    }
     c->fw_j = 0;
     c->fw_live = true;
     c->solved = false;
@@ -1181,6 +1237,7 @@ int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
         RC(ensure_history(c, (size_t)j + 1));
         HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p + (size_t)j * c->M, c->cost.p, sizeof(float) * c->M,
                                    hipMemcpyDeviceToDevice, c->stream));
+        RC(stash_labels(c, j));
     }
     HIPCHECK(c, hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     RC(pull_state(c));
@@ -1400,13 +1457,18 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         const InstState* stj = c->st_hist.p + (size_t)j * ni;
         const double* lamj = c->lam_hist.p + (size_t)j * ni;
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
-        HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
-        HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, stj,
-                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
+        label_t* lab = c->labels.p;
+        if ((size_t)j < c->lab_hist_ok.size() && c->lab_hist_ok[j]) {
+            lab = c->lab_hist.p + (size_t)j * c->label_count;    // the solve's own trees of iterate j
+        } else {
+            HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
+            HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, stj,
+                                    delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
+        }
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
-        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
+        HIPCHECK(c, launch_walk(c->stream, net, dem, lab, cj, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
                                 c->r_dense.p, c->done_fx.p));
-        HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cj, c->cfin.p, nullptr, nullptr, stj, fl,
+        HIPCHECK(c, launch_fallback(c->stream, net, dem, lab, cj, c->cfin.p, nullptr, nullptr, stj, fl,
                                     scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
                                     lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0));
     }
