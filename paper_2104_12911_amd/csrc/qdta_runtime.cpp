@@ -498,6 +498,8 @@ void prof_collect(qdta_ctx* c) {
         if (hipEventElapsedTime(&ms, c->prof_ev[p][0], c->prof_ev[p][1]) == hipSuccess) {
             c->prof_ms[p] += ms;
             c->prof_n[p] += 1;
+        } else {
+            (void)hipGetLastError();           // a timer is optional: leave no sticky error
         }
         c->prof_open[p] = 0;
     }
@@ -1197,16 +1199,18 @@ void drop_graph(qdta_ctx* c) {
 
 // Capture one iteration on a side stream; the graph is then launched on the
 // context's stream (which may be the null stream, which cannot capture).
-int capture_iteration(qdta_ctx* c, const qdta_opts* o) {
+int capture_once(qdta_ctx* c, const qdta_opts* o) {
     drop_graph(c);
     if (!c->cap_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipStream_t saved = c->stream;
     c->stream = c->cap_stream;
+    for (int p = 0; p < kPhases; ++p) c->prof_open[p] = 0;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     int rc = e == hipSuccess ? enqueue_iteration(c, o, false) : QDTA_EHIP;
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     c->stream = saved;
+    for (int p = 0; p < kPhases; ++p) c->prof_open[p] = 0;
     if (e != hipSuccess) return set_err(c, QDTA_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     if (rc < 0) {
         if (g) (void)hipGraphDestroy(g);
@@ -1219,6 +1223,10 @@ int capture_iteration(qdta_ctx* c, const qdta_opts* o) {
     c->graph_opts = *o;
     return QDTA_OK;
 }
+
+// Phase events stay out of the graph (event nodes cannot be timed), so a
+// profiled replay reports only the whole iteration.
+int capture_iteration(qdta_ctx* c, const qdta_opts* o) { return capture_once(c, o); }
 
 // One Frank-Wolfe iteration j, then one host synchronisation.
 int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
