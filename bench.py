@@ -368,7 +368,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {net.n} nodes, {net.m} links, {Q} destinations, {li.total_legs} legs,"
                                f" dt {dem.dt_s:g} s", "delta_scale": opts.delta_scale or 10.0,
-                   "sssp_shape": opts.sssp_shape, "waves_per_cu": args.waves_per_cu or 16,
+                   "sssp_shape": opts.sssp_shape, "waves_per_cu": args.waves_per_cu or 32,
                    "line_search": "K-section K=32 x3", "launch": "HIP graph per FW iteration"},
         "gteps": Q * net.m / sssp_avg_s / 1e9,
         "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},

@@ -651,6 +651,9 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
     __shared__ int s_pre[W][NP + 1];
     __shared__ float s_dw[W][NP];
     __shared__ int s_e0[W][NP];
+    // near queue as 64 rings, one per node-id range (lane r keeps range r's
+    // head and count): take offsets / heads for pops, tails / push counts
+    __shared__ int s_tpre[W][64], s_rh[W][64], s_tail[W][64], s_push[W][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int64_t slot = (int64_t)blockIdx.x * W + wv;
@@ -660,6 +663,10 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
     int* pre = s_pre[wv];
     float* sdw = s_dw[wv];
     int* se0 = s_e0[wv];
+    int* tpre = s_tpre[wv];
+    int* rhd = s_rh[wv];
+    int* rtail = s_tail[wv];
+    int* rpush = s_push[wv];
 
     for (;;) {
         int t = 0;
@@ -684,30 +691,78 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
             for (int i = lane; i < n4; i += 64) D4[i] = inf4;
         }
         __threadfence_block();
+        // ranges of 2^rsh node ids (at most 64); ring r holds at most the
+        // range's nodes (each node is queued once): capacity size + 1, so the
+        // rings take n + 64 entries
+        int rsh = 0;
+        while (((n - 1) >> rsh) >= 64) ++rsh;
+        const int rs = 1 << rsh;
+        const int nranges = ((n - 1) >> rsh) + 1;
+        const bool rvalid = lane < nranges;
+        const int rcap = rvalid ? min(rs, n - lane * rs) + 1 : 1;
         if (lane == 0) {
             D[root] = 0u;                         // value 0, queued
-            nearq[0] = root;
+            nearq[(root >> rsh) * (rs + 1)] = root;
         }
         __threadfence_block();
+        int rh = 0, rc = (lane == (root >> rsh)) ? 1 : 0;
+        // ring slot of range r at position pos (r < nranges)
+        auto ring_at = [&](int r, int pos) -> int32_t* {
+            const int cap = min(rs, n - r * rs) + 1;
+            if (pos >= cap) pos -= cap;
+            return nearq + (int64_t)r * (rs + 1) + pos;
+        };
+        // before a phase that pushes to near: tails after the pops, counters at 0
+        auto open_push = [&]() {
+            int tl = rh + rc;
+            if (tl >= rcap) tl -= rcap;
+            rtail[lane] = tl;
+            rpush[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+        };
+        auto push_near = [&](int v) {
+            const int r = v >> rsh;
+            *ring_at(r, rtail[r] + atomicAdd(&rpush[r], 1)) = v;
+        };
+        // after it: the ring counts take in what was pushed
+        auto close_push = [&]() {
+            __builtin_amdgcn_wave_barrier();
+            if (rvalid) rc += rpush[lane];
+        };
         const int l0 = early ? dem.qptr[t] : 0, l1 = early ? dem.qptr[t + 1] : 0;
-        const int R = n + 1;                      // near ring capacity: at most n nodes are queued
-        int head = 0, ncnt = 1;                   // near ring: ncnt entries from head, modulo R
+        int ncnt = 1;                             // queued in near (sum of the ring counts)
         int fcnt = 0;
         float thr = delta;
         float fmin = __uint_as_float(kInfBits);   // smallest label pushed to far
         for (;;) {
             while (ncnt > 0) {
                 const int k = ncnt < NP ? ncnt : NP;
-                // pop: slot j = u * 64 + lane
+                // pop from the lowest non-empty ranges first: nodes close in id
+                // (and, in Hilbert order, in space) are handled together, so
+                // their label lines are reused before they leave the cache
+                int incl = rc;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int x = __shfl_up(incl, o);
+                    if (lane >= o) incl += x;
+                }
+                const int excl = incl - rc;
+                const int take = max(0, min(rc, NP - excl));
+                tpre[lane] = min(excl, NP);
+                rhd[lane] = rh;
+                __builtin_amdgcn_wave_barrier();
+                // pop: slot j = u * 64 + lane, from the largest range r with tpre[r] <= j
                 int deg[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = u * 64 + lane;
                     deg[u] = 0;
                     if (j < k) {
-                        int pos = head + j;
-                        if (pos >= R) pos -= R;
-                        const int w = nearq[pos];
+                        int lo = 0, hi = 64;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (tpre[mid] <= j) lo = mid; else hi = mid;
+                        }
+                        const int w = *ring_at(lo, rhd[lo] + (j - tpre[lo]));
                         const uint32_t lw = atomicOr(&D[w], kNotQueued);   // dequeue, read the label
                         const int e0 = rptr[w];
                         deg[u] = rptr[w + 1] - e0;
@@ -715,9 +770,11 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                         sdw[j] = __uint_as_float(lw & kValueBits);
                     }
                 }
-                head += k;
-                if (head >= R) head -= R;
+                rh += take;
+                if (rh >= rcap) rh -= rcap;
+                rc -= take;
                 ncnt -= k;
+                open_push();
                 // exclusive prefix of in-degrees in slot order
                 int base = 0;
 #pragma unroll
@@ -774,11 +831,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
 #pragma unroll
                     for (int x = 0; x < V; ++x) {
                         const unsigned long long bn = __ballot(pn[x]), bf = __ballot(pf[x]);
-                        if (pn[x]) {
-                            int pos = head + ncnt + __popcll(bn & below);
-                            if (pos >= R) pos -= R;
-                            nearq[pos] = vv[x];
-                        }
+                        if (pn[x]) push_near(vv[x]);
                         if (pf[x]) {
                             farq[fcnt + __popcll(bf & below)] = make_uint2((uint32_t)vv[x], __float_as_uint(cd[x]));
                             fm = fminf(fm, cd[x]);
@@ -788,6 +841,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                     }
                     fmin = fminf(fmin, wave_min(fm));
                 }
+                close_push();
                 __threadfence_block();
             }
             // Bucket [.., thr) is drained.  Far entries carry the label they had
@@ -802,6 +856,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                 if (__ballot(pend) == 0ull) {
                     // exact: move far entries whose current label is below thr
                     int moved = 0;
+                    open_push();
                     for (int i0 = 0; i0 < fcnt; i0 += 64) {
                         const int i = i0 + lane;
                         const bool h = i < fcnt;
@@ -809,11 +864,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                         const float dv = h ? __uint_as_float(ld_coherent(&D[ent.x]) & kValueBits) : 0.0f;
                         const bool late = h && dv < thr;
                         const unsigned long long bl = __ballot(late);
-                        if (late) {
-                            int pos = head + ncnt + __popcll(bl & below);
-                            if (pos >= R) pos -= R;
-                            nearq[pos] = (int)ent.x;
-                        }
+                        if (late) push_near((int)ent.x);
                         // keep the rest, in order
                         const unsigned long long bk = __ballot(h && !late);
                         if (h && !late) farq[i0 - moved + __popcll(bk & below)] = ent;
@@ -821,6 +872,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                         moved += __popcll(bl);
                     }
                     fcnt -= moved;
+                    close_push();
                     __threadfence_block();
                     if (moved == 0) break;            // every node below thr is settled
                     if (fcnt > 0) {
@@ -840,6 +892,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
             if (!(thr > fmin)) thr = __uint_as_float(__float_as_uint(fmin) + 1u);
             int keep = 0;
             float kmin = __uint_as_float(kInfBits);
+            open_push();
             for (int i0 = 0; i0 < fcnt; i0 += 64) {
                 const int i = i0 + lane;
                 const bool h = i < fcnt;
@@ -848,11 +901,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
                 const bool ton = h && dv < thr;
                 const bool tok = h && !ton;
                 const unsigned long long bn = __ballot(ton), bk = __ballot(tok);
-                if (ton) {
-                    int pos = head + ncnt + __popcll(bn & below);
-                    if (pos >= R) pos -= R;
-                    nearq[pos] = (int)ent.x;
-                }
+                if (ton) push_near((int)ent.x);
                 if (tok) farq[keep + __popcll(bk & below)] = ent;
                 ncnt += __popcll(bn);
                 keep += __popcll(bk);
@@ -860,6 +909,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
             }
             fcnt = keep;
             fmin = wave_min(kmin);
+            close_push();
             __threadfence_block();
         }
     }

@@ -205,7 +205,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     return true;
 }
 
-int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 16; }
+int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 32; }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
 int sssp_variant(const qdta_opts* o) { return (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2; }
@@ -337,7 +337,7 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
     int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1), (int64_t)c->cus * wpc);
     slots = (slots + 3) / 4 * 4;                 // whole workgroups of four wavefronts
     c->slots = slots;
-    nmax = std::max<int64_t>(nmax, 1) + 1;       // the near ring holds up to n nodes in n + 1 slots
+    nmax = std::max<int64_t>(nmax, 1) + 65;      // near rings: n queued nodes in n + (up to 64) slots
     if (slots > c->scr_slots || nmax > c->scr_nmax) {
         int64_t ns = std::max<int64_t>(slots, c->scr_slots), nm = std::max<int64_t>(nmax, c->scr_nmax);
         RC(dalloc(c, c->nearq, (size_t)ns * nm));
