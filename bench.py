@@ -211,7 +211,8 @@ def mode_day(args, torch, qdta):
     ctx.add(net)
     stop = qdta.STOP_OBJ if args.stop == "obj" else qdta.STOP_GAP
     opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1,
-                             launch_form=1 if args.profile_day else 0)
+                             launch_form=1 if args.profile_day else 0, tree_waves=args.tree_waves,
+                             waves_per_cu=args.waves_per_cu)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, tot_trips, carried = [], 0.0, 0
@@ -250,7 +251,7 @@ def mode_day(args, torch, qdta):
     ctx.close()
     print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
-                      "stop_rule": args.stop, "left_after_last_trips": carried / FX,
+                      "stop_rule": args.stop, "tree_waves": opts.tree_waves or 4, "left_after_last_trips": carried / FX,
                       "split_s": {k: round(v, 3) for k, v in split.items()}}), flush=True)
 
 
@@ -261,7 +262,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
     ap.add_argument("--delta-scale", type=float, default=0.0, help="bucket width / mean link cost (0: library default)")
-    ap.add_argument("--waves-per-cu", type=int, default=0, help="trees in flight per CU (0: library default)")
+    ap.add_argument("--waves-per-cu", type=int, default=0, help="wavefronts in flight per CU (0: library default)")
+    ap.add_argument("--tree-waves", type=int, default=0, help="wavefronts per tree, 1 or 4 (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -298,12 +300,13 @@ def main():
     ctx.add(net)
     ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
     opts = qdta.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=1 << 30, delta_scale=args.delta_scale,
-                             waves_per_cu=args.waves_per_cu)
+                             waves_per_cu=args.waves_per_cu, tree_waves=args.tree_waves)
     li = ctx.layout()
     Q = int(li.total_dests)
     if not args.no_autotune and not args.delta_scale:
         opts, best = ctx.autotune(opts, 2000.0)
-        log(f"autotune: sssp_shape={opts.sssp_shape} delta_scale={opts.delta_scale} ({best:.1f} ms)")
+        log(f"autotune: sssp_shape={opts.sssp_shape} delta_scale={opts.delta_scale} tree_waves={opts.tree_waves} "
+            f"({best:.1f} ms)")
     log(f"layout: destinations={Q} legs={li.total_legs}; initial AON")
     t0 = time.perf_counter()
     ctx.fw_begin(opts)
@@ -340,7 +343,8 @@ def main():
         # inputs; only the launch path differs)
         kernel_timing = "HIP events around direct launches of the same number of steps, after the timed graph replays"
         od = qdta.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=1 << 30, delta_scale=opts.delta_scale,
-                               sssp_shape=opts.sssp_shape, waves_per_cu=args.waves_per_cu, launch_form=1)
+                               sssp_shape=opts.sssp_shape, waves_per_cu=opts.waves_per_cu,
+                               tree_waves=opts.tree_waves, launch_form=1)
         ctx.profile(True)
         for _ in range(args.steps):
             ctx.fw_step(od)
@@ -368,12 +372,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {net.n} nodes, {net.m} links, {Q} destinations, {li.total_legs} legs,"
                                f" dt {dem.dt_s:g} s", "delta_scale": opts.delta_scale or 10.0,
-                   "sssp_shape": opts.sssp_shape, "waves_per_cu": args.waves_per_cu or 32,
+                   "sssp_shape": opts.sssp_shape, "waves_per_cu": opts.waves_per_cu or 32,
+                   "tree_waves": opts.tree_waves or 4,
                    "line_search": "K-section K=32 x3", "launch": "HIP graph per FW iteration"},
         "gteps": Q * net.m / sssp_avg_s / 1e9,
         "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_sssp",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sssp_wg" if (opts.tree_waves or 4) == 4 else "k_sssp_ds",
                      "kernel_ms": sssp_avg_s * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_timing": kernel_timing},
         "gap_last": gaps[-1] if gaps else None,

@@ -98,7 +98,9 @@ typedef struct {
                               one pass, one FW iteration replayed as a captured HIP graph when possible
                               (K-section or MSA); 1 batched with direct launches; 2 plain: one launch per
                               destination tree and per step size (same results, for comparison) */
-    int32_t reserved[2];
+    int32_t tree_waves;    /* wavefronts that grow one shortest-path tree: 0 auto (4), 4 (a whole
+                              workgroup per tree, a quarter as many trees in flight), or 1 */
+    int32_t reserved;
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */
@@ -250,11 +252,12 @@ int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host
 
 /* Autotuner: times the shortest-path launch of the current demand (every
  * instance, under the costs BPR(f) of the last solved iterate, free-flow
- * costs otherwise) for a grid of kernel shapes and bucket widths, stopping
- * once about budget_ms of GPU time is spent, and writes the fastest into
- * opts->sssp_shape and opts->delta_scale (other fields unchanged).  Results
- * never depend on these two fields, only the speed does.  *best_ms_out
- * (host, may be NULL) receives the best trial time.  Synchronises. */
+ * costs otherwise) for a grid of kernel shapes, bucket widths and
+ * wavefronts per tree, stopping once about budget_ms of GPU time is spent,
+ * and writes the fastest into opts->sssp_shape, opts->delta_scale and
+ * opts->tree_waves (other fields unchanged).  Results never depend on these
+ * fields, only the speed does.  *best_ms_out (host, may be NULL) receives
+ * the best trial time.  Synchronises. */
 int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best_ms_out);
 
 /* Per-phase timers: HIP events recorded on the context's stream around each

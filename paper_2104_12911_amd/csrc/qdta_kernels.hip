@@ -915,6 +915,329 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
     }
 }
 
+// Workgroup-per-tree form of the same delta-stepping: the four wavefronts of
+// a workgroup grow one tree together, popping up to 256 U nodes per step
+// from the lowest node-id ranges, so a quarter as many trees are in flight
+// for the same number of wavefronts and each keeps four times as many of its
+// label lines in the L2.  Queue state (range heads and counts, near / far
+// counts) is in LDS; a step is: wavefront 0 takes the pops from the lowest
+// ranges; every thread pops; a workgroup prefix sum of the in-degrees;
+// every thread relaxes V in-links per chunk; the counts are folded in.
+template <int U, int V>
+__global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const uint2* __restrict__ radj,
+                                                 label_t* labels, Scratch scr, const InstState* st,
+                                                 const float* __restrict__ delta_inst, int early, int t_begin,
+                                                 int t_end) {
+    constexpr int NT = kWG;
+    constexpr int NW = NT / 64;
+    constexpr int NP = NT * U;                    // nodes per step
+    __shared__ int s_pre[NP + 1];
+    __shared__ float s_dw[NP];
+    __shared__ int s_e0[NP];
+    __shared__ int s_rh[64], s_rc[64], s_rhp[64], s_tail[64], s_push[64], s_tpre[64];
+    __shared__ int s_wsum[NW];
+    __shared__ int s_t, s_nn, s_fn;
+    __shared__ uint32_t s_fm;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int32_t* nearq = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
+    uint2* farq = reinterpret_cast<uint2*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
+    for (;;) {
+        if (tid == 0) s_t = t_begin + atomicAdd(scr.work, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();
+        if (t >= t_end) break;
+        const int inst = dem.dest_inst[t];
+        if (!inst_live(st, inst)) continue;
+        const InstDev I = net.inst[inst];
+        const int n = I.n, node0 = I.node0;
+        const int* __restrict__ rptr = net.rptr + node0;
+        label_t* D = labels + dem.dest_lab[t];
+        const int root = dem.dest_node[t] - node0;
+        const float delta = delta_inst[inst];
+        {
+            uint4* D4 = reinterpret_cast<uint4*>(D);
+            const uint32_t w0 = kNotQueued | kInfBits;
+            const uint4 inf4 = make_uint4(w0, w0, w0, w0);
+            const int n4 = (n + 31) / 32 * 8;
+            for (int i = tid; i < n4; i += NT) D4[i] = inf4;
+        }
+        int rsh = 0;
+        while (((n - 1) >> rsh) >= 64) ++rsh;
+        const int rs = 1 << rsh;
+        const int nranges = ((n - 1) >> rsh) + 1;
+        if (tid < 64) {
+            s_rh[tid] = 0;
+            s_rc[tid] = (tid == (root >> rsh)) ? 1 : 0;
+            s_push[tid] = 0;
+        }
+        if (tid == 0) {
+            s_nn = 0;
+            s_fn = 0;
+            s_fm = kInfBits;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) {
+            D[root] = 0u;                         // value 0, queued
+            nearq[(root >> rsh) * (rs + 1)] = root;
+        }
+        __threadfence_block();
+        __syncthreads();
+        auto ring_at = [&](int r, int pos) -> int32_t* {
+            const int cap = min(rs, n - r * rs) + 1;
+            if (pos >= cap) pos -= cap;
+            return nearq + (int64_t)r * (rs + 1) + pos;
+        };
+        auto push_near = [&](int v) {
+            const int r = v >> rsh;
+            *ring_at(r, s_tail[r] + atomicAdd(&s_push[r], 1)) = v;
+            atomicAdd(&s_nn, 1);
+        };
+        // wavefront 0: tails of the rings for the pushes to come
+        auto open_push = [&]() {
+            if (wv == 0) {
+                const int cap = lane < nranges ? min(rs, n - lane * rs) + 1 : 1;
+                int tl = s_rh[lane] + s_rc[lane];
+                if (tl >= cap) tl -= cap;
+                s_tail[lane] = tl;
+                s_push[lane] = 0;
+            }
+        };
+        // after a pushing phase (all threads past a barrier): counts folded in
+        int ncnt = 1, fcnt = 0;
+        float thr = delta, fmin = __uint_as_float(kInfBits);
+        auto fold = [&]() -> int {
+            __threadfence_block();
+            __syncthreads();
+            const int nn = s_nn, fn = s_fn;
+            const float fm = __uint_as_float(s_fm);
+            __syncthreads();
+            if (wv == 0) {
+                if (lane < nranges) s_rc[lane] += s_push[lane];
+                s_push[lane] = 0;
+            }
+            if (tid == 0) {
+                s_nn = 0;
+                s_fn = 0;
+                s_fm = kInfBits;
+            }
+            ncnt += nn;
+            fcnt += fn;
+            fmin = fminf(fmin, fm);
+            return nn;
+        };
+        int lcur = early ? dem.qptr[t] : 0;
+        const int lend = early ? dem.qptr[t + 1] : 0;
+        for (;;) {
+            while (ncnt > 0) {
+                const int k = ncnt < NP ? ncnt : NP;
+                if (wv == 0) {
+                    const int rc = s_rc[lane], rh = s_rh[lane];
+                    int incl = rc;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int x = __shfl_up(incl, o);
+                        if (lane >= o) incl += x;
+                    }
+                    const int excl = incl - rc;
+                    const int take = max(0, min(rc, NP - excl));
+                    const int cap = lane < nranges ? min(rs, n - lane * rs) + 1 : 1;
+                    s_tpre[lane] = min(excl, NP);
+                    s_rhp[lane] = rh;
+                    int nh = rh + take;
+                    if (nh >= cap) nh -= cap;
+                    s_rh[lane] = nh;
+                    s_rc[lane] = rc - take;
+                    int tl = nh + rc - take;
+                    if (tl >= cap) tl -= cap;
+                    s_tail[lane] = tl;
+                    s_push[lane] = 0;
+                }
+                __syncthreads();
+                int deg[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = u * NT + tid;
+                    deg[u] = 0;
+                    if (j < k) {
+                        int lo = 0, hi = 64;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_tpre[mid] <= j) lo = mid; else hi = mid;
+                        }
+                        const int w = *ring_at(lo, s_rhp[lo] + (j - s_tpre[lo]));
+                        const uint32_t lw = atomicOr(&D[w], kNotQueued);   // dequeue, read the label
+                        const int e0 = rptr[w];
+                        deg[u] = rptr[w + 1] - e0;
+                        s_e0[j] = e0;
+                        s_dw[j] = __uint_as_float(lw & kValueBits);
+                    }
+                }
+                // exclusive prefix of the in-degrees in slot order (workgroup-wide)
+                int base = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    int incl = deg[u];
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int x = __shfl_up(incl, o);
+                        if (lane >= o) incl += x;
+                    }
+                    if (lane == 63) s_wsum[wv] = incl;
+                    __syncthreads();
+                    int before = 0, all = 0;
+                    for (int q = 0; q < NW; ++q) {
+                        if (q < wv) before += s_wsum[q];
+                        all += s_wsum[q];
+                    }
+                    s_pre[u * NT + tid] = base + before + incl - deg[u];
+                    base += all;
+                    __syncthreads();
+                }
+                if (tid == 0) s_pre[NP] = base;
+                if (k < NP && tid == 0) s_pre[k] = base;
+                __syncthreads();
+                const int total = base;
+                ncnt -= k;
+                for (int g0 = 0; g0 < total; g0 += NT * V) {
+                    int vv[V];
+                    float cd[V];
+                    bool ok[V];
+#pragma unroll
+                    for (int x = 0; x < V; ++x) {
+                        const int g = g0 + x * NT + tid;
+                        ok[x] = g < total;
+                        vv[x] = 0;
+                        cd[x] = 0.0f;
+                        if (ok[x]) {
+                            int lo = 0, hi = k;   // owner slot: pre[lo] <= g < pre[lo + 1]
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (s_pre[mid] <= g) lo = mid; else hi = mid;
+                            }
+                            const int e = s_e0[lo] + (g - s_pre[lo]);
+                            const uint2 r = radj[e];
+                            vv[x] = (int)r.x - node0;
+                            cd[x] = s_dw[lo] + __uint_as_float(r.y);
+                        }
+                    }
+                    uint32_t cur[V];
+#pragma unroll
+                    for (int x = 0; x < V; ++x) cur[x] = ok[x] ? (ld_coherent(&D[vv[x]]) & kValueBits) : 0u;
+#pragma unroll
+                    for (int x = 0; x < V; ++x) {
+                        const uint32_t cb = __float_as_uint(cd[x]);
+                        if (ok[x] && cb < cur[x] && (atomicMin(&D[vv[x]], cb) & kNotQueued)) {
+                            if (cd[x] < thr) {
+                                push_near(vv[x]);
+                            } else {
+                                farq[fcnt + atomicAdd(&s_fn, 1)] = make_uint2((uint32_t)vv[x], cb);
+                                atomicMin(&s_fm, cb);
+                            }
+                        }
+                    }
+                }
+                fold();
+            }
+            if (early) {
+                bool pend = false;
+                while (lcur < lend) {
+                    const int l = lcur + tid;
+                    bool p = false;
+                    if (l < lend) {
+                        const int o = dem.leg_orig[l] - node0;
+                        p = !(__uint_as_float(ld_coherent(&D[o]) & kValueBits) < thr);
+                    }
+                    if (__syncthreads_or(p)) { pend = true; break; }
+                    lcur += NT;
+                }
+                if (!pend) {
+                    // exact: queue the far nodes whose current label is below thr
+                    int moved = 0, keep = 0;
+                    float km = __uint_as_float(kInfBits);
+                    open_push();
+                    __syncthreads();
+                    for (int i0 = 0; i0 < fcnt; i0 += NT) {
+                        const int i = i0 + tid;
+                        const bool h = i < fcnt;
+                        const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                        const bool late = h && __uint_as_float(ld_coherent(&D[ent.x]) & kValueBits) < thr;
+                        __syncthreads();                  // the chunk is read before it is overwritten
+                        if (late) {
+                            push_near((int)ent.x);
+                        } else if (h) {
+                            farq[keep + atomicAdd(&s_fn, 1)] = ent;
+                            atomicMin(&s_fm, ent.y);
+                        }
+                        __threadfence_block();
+                        __syncthreads();
+                        const int nn = s_nn, fn = s_fn;
+                        const float fm = __uint_as_float(s_fm);
+                        __syncthreads();
+                        if (tid == 0) {
+                            s_nn = 0;
+                            s_fn = 0;
+                            s_fm = kInfBits;
+                        }
+                        ncnt += nn;
+                        moved += nn;
+                        keep += fn;
+                        km = fminf(km, fm);
+                    }
+                    if (wv == 0) {
+                        if (lane < nranges) s_rc[lane] += s_push[lane];
+                        s_push[lane] = 0;
+                    }
+                    __syncthreads();
+                    fcnt = keep;
+                    fmin = km;
+                    if (moved == 0) break;                // every label below thr is final
+                    continue;
+                }
+            }
+            if (fcnt == 0) break;
+            thr = fmaxf(thr, fmin) + delta;
+            if (!(thr > fmin)) thr = __uint_as_float(__float_as_uint(fmin) + 1u);
+            int keep = 0;
+            float km = __uint_as_float(kInfBits);
+            open_push();
+            __syncthreads();
+            for (int i0 = 0; i0 < fcnt; i0 += NT) {
+                const int i = i0 + tid;
+                const bool h = i < fcnt;
+                const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                __syncthreads();
+                if (h && __uint_as_float(ent.y) < thr) {
+                    push_near((int)ent.x);
+                } else if (h) {
+                    farq[keep + atomicAdd(&s_fn, 1)] = ent;
+                    atomicMin(&s_fm, ent.y);
+                }
+                __threadfence_block();
+                __syncthreads();
+                const int nn = s_nn, fn = s_fn;
+                const float fm = __uint_as_float(s_fm);
+                __syncthreads();
+                if (tid == 0) {
+                    s_nn = 0;
+                    s_fn = 0;
+                    s_fm = kInfBits;
+                }
+                ncnt += nn;
+                keep += fn;
+                km = fminf(km, fm);
+            }
+            if (wv == 0) {
+                if (lane < nranges) s_rc[lane] += s_push[lane];
+                s_push[lane] = 0;
+            }
+            __syncthreads();
+            fcnt = keep;
+            fmin = km;
+        }
+        __syncthreads();
+    }
+}
+
 // Bucket width per instance: delta = scale * (geometric mean link cost of the
 // instance).  The geometric mean follows the typical link; the arithmetic
 // mean is dominated by the few links that congestion makes very slow.
@@ -963,6 +1286,22 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
     if (e != hipSuccess) return e;
     const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
     dim3 g(blocks), b(kWG);
+    if (variant >= 8) {
+        // one workgroup per tree (scratch slot = workgroup)
+#define QDTA_SSSP_WG(U, V) \
+    hipLaunchKernelGGL((k_sssp_wg<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, t_begin, \
+                       t_end)
+        switch (variant - 8) {
+            case 0: QDTA_SSSP_WG(1, 2); break;
+            case 1: QDTA_SSSP_WG(1, 4); break;
+            case 2: QDTA_SSSP_WG(2, 4); break;
+            case 3: QDTA_SSSP_WG(4, 4); break;
+            case 4: QDTA_SSSP_WG(2, 2); break;
+            default: QDTA_SSSP_WG(4, 2); break;
+        }
+#undef QDTA_SSSP_WG
+        return hipGetLastError();
+    }
 #define QDTA_SSSP(U, V) \
     hipLaunchKernelGGL((k_sssp_ds<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, \
                        t_begin, t_end)

@@ -198,6 +198,10 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     if (o->waves_per_cu < 0 || o->waves_per_cu > 32) { set_err(c, QDTA_EARG, "waves_per_cu must be in 0..32"); return false; }
     if (o->sssp_shape < 0 || o->sssp_shape > 6) { set_err(c, QDTA_EARG, "sssp_shape must be in 0..6"); return false; }
     if (o->launch_form < 0 || o->launch_form > 2) { set_err(c, QDTA_EARG, "launch_form must be 0, 1 or 2"); return false; }
+    if (o->tree_waves != 0 && o->tree_waves != 1 && o->tree_waves != 4) {
+        set_err(c, QDTA_EARG, "tree_waves must be 0, 1 or 4");
+        return false;
+    }
     if (!(o->delta_scale >= 0.0) || !std::isfinite(o->delta_scale)) {
         set_err(c, QDTA_EARG, "delta_scale must be finite and >= 0");
         return false;
@@ -208,7 +212,12 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 32; }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
-int sssp_variant(const qdta_opts* o) { return (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2; }
+// Kernel variants 0-5: one wavefront per tree; 8-13: one workgroup per tree
+// (the default).
+int sssp_variant(const qdta_opts* o) {
+    const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2;
+    return o->tree_waves == 1 ? v : v + 8;
+}
 
 // ---------------------------------------------------------------------------
 // network layout: instances concatenated, reverse CSR, link chunks
@@ -1333,34 +1342,35 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
     HIPCHECK(c, hipEventCreate(&e1));
     static const int shapes[] = {3, 4, 2, 5};
     static const double scales[] = {10.0, 5.0, 20.0};
-    int best_shape = o->sssp_shape ? o->sssp_shape : 3;
+    static const int tws[] = {4, 1};
+    int best_shape = o->sssp_shape ? o->sssp_shape : 3, best_tw = o->tree_waves ? o->tree_waves : 4;
     double best_scale = delta_scale(o), best = 1e300, spent = 0.0;
     int rc = QDTA_OK;
-    for (double sc : scales) {
-        for (int sh : shapes) {
-            if (spent >= budget_ms) break;
-            qdta_opts t = *o;
-            t.sssp_shape = sh;
-            t.delta_scale = sc;
-            hipError_t e = hipEventRecord(e0, c->stream);
-            if (e == hipSuccess)
-                e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), c->slots, nullptr,
-                                delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), 1);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { rc = set_err(c, QDTA_EHIP, "autotune trial: %s", hipGetErrorString(e)); break; }
-            spent += ms;
-            if (ms < best) { best = ms; best_shape = sh; best_scale = sc; }
-        }
-        if (rc < 0 || spent >= budget_ms) break;
+    for (int k = 0; k < 24 && rc == QDTA_OK && spent < budget_ms; ++k) {
+        const int tw = tws[k / 12], sc_i = (k % 12) / 4, sh = shapes[k % 4];
+        const double sc = scales[sc_i];
+        qdta_opts t = *o;
+        t.sssp_shape = sh;
+        t.delta_scale = sc;
+        t.tree_waves = tw;
+        hipError_t e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess)
+            e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), c->slots, nullptr,
+                            delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), 1);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { rc = set_err(c, QDTA_EHIP, "autotune trial: %s", hipGetErrorString(e)); break; }
+        spent += ms;
+        if (ms < best) { best = ms; best_shape = sh; best_scale = sc; best_tw = tw; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc < 0) return rc;
     o->sssp_shape = best_shape;
     o->delta_scale = best_scale;
+    o->tree_waves = best_tw;
     if (best_ms_out) *best_ms_out = best;
     return QDTA_OK;
 }

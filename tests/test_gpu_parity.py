@@ -91,13 +91,13 @@ def test_bpr_worked_example(torch_dev, q, orc):
 # ---------------------------------------------------------------------------
 # A2 -- trees
 # ---------------------------------------------------------------------------
-def _trees(torch, q, net, cost, dests, ds=0.0):
+def _trees(torch, q, net, cost, dests, ds=0.0, waves=1):
     with q.Context() as ctx:
         ctx.add(net)
         nq = len(dests)
         dist = torch.empty(nq * net.n, dtype=torch.float32, device="cuda")
         succ = torch.empty(nq * net.n, dtype=torch.int32, device="cuda")
-        rc = ctx.trees(q.default_opts(delta_scale=ds), 0, dev(torch, cost.astype(np.float32)),
+        rc = ctx.trees(q.default_opts(delta_scale=ds, tree_waves=waves), 0, dev(torch, cost.astype(np.float32)),
                        dev(torch, np.asarray(dests, np.int32)), dist, succ)
         return host(dist).reshape(nq, net.n), host(succ).reshape(nq, net.n), rc
 
@@ -118,8 +118,9 @@ def test_trees_tiny_all_destinations(torch_dev, q, orc, costs):
         assert (rc == q.WABSORB) == absorbed
 
 
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("costs", ["float", "int"])
-def test_trees_high_in_degree(torch_dev, q, orc, costs):
+def test_trees_high_in_degree(torch_dev, q, orc, costs, waves):
     """Dense tiny graphs (in-degrees up to about 15, parallel links) put most
     in-links in the overflow run of the node records."""
     for seed in range(4):
@@ -127,22 +128,24 @@ def test_trees_high_in_degree(torch_dev, q, orc, costs):
         net = synth.tiny_network(12, 90, rng, costs=costs)
         indeg = np.bincount(net.col, minlength=net.n)
         assert indeg.max() > 8
-        D, S, rc = _trees(torch_dev, q, net, net.fftt, list(range(net.n)), ds=0.5)
+        D, S, rc = _trees(torch_dev, q, net, net.fftt, list(range(net.n)), ds=0.5, waves=waves)
         for t in range(net.n):
             Do, So, _ = orc.tree(net, net.fftt, t)
             assert np.array_equal(D[t].view(np.uint32), Do.view(np.uint32)), (costs, seed, t)
             assert np.array_equal(S[t], So), (costs, seed, t)
 
 
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("ds", [0.05, 1.0, 3.0, 40.0, 1e30])
-def test_trees_grid_every_bucket_width(torch_dev, q, orc, ds):
+def test_trees_grid_every_bucket_width(torch_dev, q, orc, ds, waves):
     """Any bucket width gives the same least fixed point: tiny buckets (near
-    Dijkstra), the default, and one bucket (Bellman-Ford)."""
+    Dijkstra), the default, and one bucket (Bellman-Ford); one wavefront or
+    one workgroup per tree."""
     w = synth.config1()
     rng = np.random.default_rng(7)
     cost = (w.net.fftt * rng.uniform(1, 4, w.net.m)).astype(np.float32)
     dests = list(range(0, w.net.n, 7))          # 58 trees
-    D, S, _ = _trees(torch_dev, q, w.net, cost, dests, ds=ds)
+    D, S, _ = _trees(torch_dev, q, w.net, cost, dests, ds=ds, waves=waves)
     for k, t in enumerate(dests):
         Do, So, _ = orc.tree(w.net, cost, t)
         assert np.array_equal(D[k].view(np.uint32), Do.view(np.uint32))
@@ -263,6 +266,10 @@ def test_bad_inputs_rejected(torch_dev, q):
         with pytest.raises(q.QdtaError) as ei:
             ctx.solve(q.default_opts(beta=0))
         assert ei.value.code == q.EARG
+        for tw in (2, 3, 8, -1):
+            with pytest.raises(q.QdtaError) as ei:
+                ctx.solve(q.default_opts(tree_waves=tw))
+            assert ei.value.code == q.EARG
 
 
 # ---------------------------------------------------------------------------
@@ -441,6 +448,25 @@ def test_day_small_network_chain(torch_dev, q, orc):
         assert a["done"] == b["done_fx"]
 
 
+def test_day_chain_workgroup_trees(torch_dev, q, orc):
+    """The interval chain with one workgroup per tree (early exit, residual
+    walks on stored labels) equals the oracle."""
+    w = synth.config1()
+    rng = np.random.default_rng(23)
+    days = []
+    for frac in (0.6, 0.3, 0.5):
+        sel = rng.random(w.demand.P) < frac
+        days.append(synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] / 2, 600.0))
+    opts = q.default_opts(keep_history=1, tol=1e-3, max_iter=20, tree_waves=4)
+    g = _day_gpu(torch_dev, q, w.net, days, opts)
+    ref, _ = orc.qdta_day(w.net, days, tol=1e-3, max_iter=20)
+    for a, b in zip(g, ref):
+        assert a["iters"] == b["iters"]
+        assert np.array_equal(a["f"], b["f"])
+        for x, y in zip(a["res"], b["res"]):
+            assert np.array_equal(x, y)
+
+
 def test_day_demand_shrinks_and_regrows(torch_dev, q, orc):
     """Intervals whose leg and destination counts fall and then rise again
     within the buffers of the largest one: every interval is re-captured
@@ -509,8 +535,29 @@ def test_plain_form_matches_batched(torch_dev, q, orc):
         assert np.array_equal(f_p, ref.f)
 
 
+def test_autotune_picks_valid_options_and_results_do_not_move(torch_dev, q, orc):
+    """The autotuner only chooses kernel shape, bucket width and wavefronts
+    per tree; a solve with its choice equals the oracle bit for bit."""
+    w = synth.config2()
+    sel = np.isin(w.demand.dest, w.extra["zones"][:40])
+    dem = synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel], 900.0)
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
+        opts, best = ctx.autotune(q.default_opts(fixed_iters=3), 300.0)
+        assert 1 <= opts.sssp_shape <= 6 and opts.delta_scale > 0 and opts.tree_waves in (1, 4)
+        assert best > 0
+        st, rc = ctx.solve(opts)
+        f = torch_dev.empty(w.net.m, dtype=torch_dev.int64, device="cuda")
+        ctx.get_flows(f)
+        o, d, wfx = ctx.legs()
+    ref = orc.fw_solve(w.net, o, d, wfx, fixed_iters=3, dt_s=900.0, keep_history=False)
+    assert np.array_equal(host(f), ref.f)
+
+
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6])
-def test_sssp_shapes_identical(torch_dev, q, orc, shape):
+def test_sssp_shapes_identical(torch_dev, q, orc, shape, waves):
     w = synth.config2()
     rng = np.random.default_rng(40 + shape)
     f = rng.integers(0, 600 * FX, w.net.m).astype(np.int64)
@@ -522,7 +569,7 @@ def test_sssp_shapes_identical(torch_dev, q, orc, shape):
         ctx.add(w.net)
         ctx.set_demand(0, w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel], 900.0)
         yy = torch_dev.empty(w.net.m, dtype=torch_dev.int64, device="cuda")
-        ctx.aon(q.default_opts(sssp_shape=shape), dev(torch_dev, cost), yy)
+        ctx.aon(q.default_opts(sssp_shape=shape, tree_waves=waves), dev(torch_dev, cost), yy)
         assert np.array_equal(host(yy), y)
     yo, so, _ = orc.aon(w.net, cost, o, d, wfx, 900.0, 1)
     assert np.array_equal(y, yo)
