@@ -88,7 +88,8 @@ typedef struct {
     int32_t max_iter;      /* FW iteration cap */
     int32_t fixed_iters;   /* > 0: exactly this many updates, stop rule ignored */
     int32_t keep_history;  /* record (alpha_j, c_j) per iteration; needed by qdta_advance_interval */
-    int32_t waves_per_cu;  /* shortest-path trees in flight per compute unit: 0 auto (32), else 1..32 */
+    int32_t waves_per_cu;  /* shortest-path wavefronts in flight per compute unit (a tree takes
+                              tree_waves of them): 0 auto (32), else 1..32 */
     double delta_scale;    /* delta-stepping bucket width as a multiple of the instance's geometric-mean
                               link cost: 0 auto (10.0); any value > 0 gives the same trees, only the speed
                               changes */
@@ -242,7 +243,12 @@ int qdta_get_costs(qdta_ctx *ctx, const qdta_opts *opts, float *cost);
  * paths (weights lambda_j = alpha_j prod_{k>j}(1 - alpha_k), alpha_0 = 1) are
  * re-truncated under the final costs BPR(f); a leg stopping at s != q leaves
  * rint(lambda_j d) as demand (s, q), merged into the next qdta_set_demand.
- * Needs opts->keep_history during qdta_solve.  Synchronises. */
+ * Needs opts->keep_history during qdta_solve.  With keep_history, the solve
+ * keeps each iterate's shortest-path labels in device memory while it lasts
+ * (sized at qdta_fw_begin from the free memory, leaving 16 GiB free, held
+ * until the context is destroyed); this pass walks those and grows trees
+ * again only for the iterates that did not fit.  Residual legs are kept in
+ * (destination, origin) order.  Synchronises. */
 int qdta_advance_interval(qdta_ctx *ctx, const qdta_opts *opts);
 
 /* The pending residual demand of instance inst (host outputs).  Call with

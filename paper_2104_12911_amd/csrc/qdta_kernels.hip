@@ -2,16 +2,17 @@
 //
 // One Frank-Wolfe iteration of the link-flow form (Alg. 6, section 5.1):
 //   k_bpr        link costs by the BPR curve (Eq. 1)
-//   k_sssp_ds    destination-rooted FP32 shortest-path trees, one wavefront
-//                per tree, delta-stepping (Get_shortest_path of Alg. 3 / Alg. 7)
+//   k_sssp_wg    destination-rooted FP32 shortest-path trees, delta-stepping
+//   k_sssp_ds    (Get_shortest_path of Alg. 3 / Alg. 7), one workgroup or one
+//                wavefront per tree
 //   k_walk       route truncation (Eq. 2) and loading along the successor
 //                links (Eq. 5, Alg. 3), int64 fixed-point atomics
 //   k_gap_sums   exact sums for the relative gap / stop test
 //   k_ls_*       line search on the Beckmann objective (Eq. 6, Eq. 8-10,
 //                Alg. 8-9), K step sizes per pass over the links
 //   k_fw_update  f <- f + rint(alpha (y - f))
-// plus the tie-rule fallback under FP32 absorption and the residual-demand
-// walk of Alg. 4.
+// plus the tie-rule fallback under FP32 absorption, the residual-demand
+// walk of Alg. 4 and the compaction of its accumulator.
 //
 // Numeric contract: FP64 per-link arithmetic with no fused multiply-add (the
 // library is compiled with -ffp-contract=off), power by repeated
@@ -42,9 +43,6 @@ __device__ __forceinline__ uint32_t ld_coherent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int32_t ld_coherent(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_coherent64(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -84,7 +84,7 @@ struct qdta_ctx {
     DBuf<uint2> radj;             // reverse adjacency records (source node, cost)
     DBuf<InstState> st;
     DBuf<long long> acc, ls_acc;
-    DBuf<double> alphas, alpha_arr, lambda;
+    DBuf<double> alphas, alpha_arr;
     DBuf<int> flags;              // [0] overflow, [1] unreach, [2] absorb count
     DBuf<int32_t> absorb_q, int_node;
     DBuf<float> int_tau;
@@ -100,7 +100,7 @@ struct qdta_ctx {
     DBuf<label_t> lab_hist;
     std::vector<char> lab_hist_ok;  // iterate j's labels are at lab_hist + j * label_count
     DBuf<double> lam_hist;
-    DBuf<unsigned long long> r_count, done_fx;
+    DBuf<unsigned long long> done_fx;
     uint64_t gen = 0;             // bumped on every (re)allocation and every rebuild of the
                                   // network or demand tables: a captured iteration is valid
                                   // only for the generation it was captured in
@@ -303,10 +303,8 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->ls_acc, (size_t)ni * kMaxK * 6));
     RC(dalloc(c, c->alphas, (size_t)ni * kMaxK));
     RC(dalloc(c, c->alpha_arr, ni));
-    RC(dalloc(c, c->lambda, ni));
     RC(dalloc(c, c->flags, 4));
     RC(dalloc(c, c->done_fx, ni));
-    RC(dalloc(c, c->r_count, 1));
     if (c->h_st_n < ni) {
         if (c->h_st) hipHostFree(c->h_st);
         HIPCHECK(c, hipHostMalloc((void**)&c->h_st, sizeof(InstState) * ni, hipHostMallocDefault));
