@@ -383,6 +383,21 @@ def test_fw_objective_stop_rule(torch_dev, q, orc):
     assert st[0]["stopped_by"] == 2
 
 
+def test_config3_peak_full_size(torch_dev, q, orc):
+    """The benchmark workload at full size (550k nodes, 1.0M links, 5,000
+    trees, 261k legs, dt = 900 s) in the configuration bench.py times (one
+    FW iteration replayed as a HIP graph, default kernel and bucket width):
+    the initial AON and two FW iterations equal the oracle bit for bit."""
+    w = synth.config3()
+    opts = q.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=2)
+    st, f, off, (o, d, wfx), rc = _solve(torch_dev, q, [(w.net, w.demand)], opts)
+    ref = orc.fw_solve(w.net, o, d, wfx, alpha_b=w.alpha, beta=w.beta, dt_s=w.demand.dt_s, fixed_iters=2,
+                       keep_history=False)
+    assert np.array_equal(f, ref.f)
+    assert st[0]["gap"] == ref.gap
+    assert st[0]["iters"] == ref.iters
+
+
 def test_fw_batched_instances_match_single(torch_dev, q, orc):
     """Several uneven grids in one context (one launch sequence per FW
     iteration) give, per instance, exactly the single-instance oracle result."""
