@@ -101,7 +101,9 @@ typedef struct {
                               destination tree and per step size (same results, for comparison) */
     int32_t tree_waves;    /* wavefronts that grow one shortest-path tree: 0 auto (4), 4 (a whole
                               workgroup per tree, a quarter as many trees in flight), or 1 */
-    int32_t reserved;
+    int32_t history_mib;   /* with keep_history: device memory for the iterates' labels, in MiB:
+                              0 auto (the free memory less 16 GiB), < 0 none (the residual step
+                              grows every tree again); never changes results */
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */

@@ -637,11 +637,12 @@ int flag_code(qdta_ctx* c, const int* h) {
 
 // Slots of label history for this solve: as many iterates as fit in the free
 // device memory less a reserve for the residual pass (its accumulator and
-// outputs) and 16 GiB of headroom; at most max_iter + 1 and 64.
+// outputs) and 16 GiB of headroom, or in opts->history_mib; at most
+// max_iter + 1 and 64.
 int plan_label_history(qdta_ctx* c, const qdta_opts* o) {
     c->lab_hist_ok.clear();
     const size_t per = c->label_count;
-    if (per == 0) return QDTA_OK;
+    if (per == 0 || o->history_mib < 0) return QDTA_OK;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         (void)hipGetLastError();
@@ -652,7 +653,9 @@ int plan_label_history(qdta_ctx* c, const qdta_opts* o) {
     if (c->r_dense.n < c->label_count) reserve += (c->label_count - c->r_dense.n) * sizeof(int64_t);
     reserve += (size_t)c->P * 16;
     if (avail <= reserve) return QDTA_OK;
-    size_t slots = (avail - reserve) / (per * sizeof(label_t));
+    size_t budget = avail - reserve;
+    if (o->history_mib > 0) budget = std::min(budget, (size_t)o->history_mib << 20);
+    size_t slots = budget / (per * sizeof(label_t));
     const size_t want = o->fixed_iters > 0 ? (size_t)o->fixed_iters + 1 : (size_t)std::max(o->max_iter, 0) + 1;
     slots = std::min<size_t>(std::min<size_t>(slots, want), 64);
     if (slots == 0) return QDTA_OK;

@@ -39,7 +39,7 @@ class Opts(C.Structure):
                 ("T2", C.c_double), ("dx", C.c_double), ("stop_rule", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("sssp_shape", C.c_int32),
-                ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("reserved", C.c_int32)]
+                ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("history_mib", C.c_int32)]
 
 
 class Stats(C.Structure):

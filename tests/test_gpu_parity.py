@@ -482,6 +482,28 @@ def test_day_chain_workgroup_trees(torch_dev, q, orc):
             assert np.array_equal(x, y)
 
 
+def test_day_peak_scaled_network(torch_dev, q, orc):
+    """Six morning-peak intervals of the 1/20-scale day (27,500 nodes, 250
+    zones, up to 14 iterates and 28k residual legs per interval), chained
+    from a cold start under the objective rule of Eq. 7: flows, iteration
+    counts and residual legs equal the oracle with the label history on
+    (every iterate stored), capped at 100 MiB (three stored, the rest grown
+    again) and off."""
+    w = synth.config3_day(0.05)
+    days = w.demand[28:34]
+    ref, _ = orc.qdta_day(w.net, days, stop_rule=orc.STOP_OBJ, tol=1e-4, max_iter=100)
+    assert max(r["iters"] for r in ref) >= 10
+    for hist in (0, 100, -1):
+        opts = q.default_opts(stop_rule=q.STOP_OBJ, tol=1e-4, max_iter=100, keep_history=1, history_mib=hist)
+        g = _day_gpu(torch_dev, q, w.net, days, opts)
+        for a, b in zip(g, ref):
+            assert a["iters"] == b["iters"], hist
+            assert np.array_equal(a["f"], b["f"]), hist
+            for x, y in zip(a["res"], b["res"]):
+                assert np.array_equal(x, y), hist
+            assert a["done"] == b["done_fx"], hist
+
+
 def test_day_demand_shrinks_and_regrows(torch_dev, q, orc):
     """Intervals whose leg and destination counts fall and then rise again
     within the buffers of the largest one: every interval is re-captured
