@@ -81,8 +81,9 @@ struct DemDev {
 struct Scratch {
     int32_t* nearq;          // [slots][nmax] near queue (ring of n + 1)
     int32_t* farq;           // [slots][nmax] far queue of (node, label) pairs (2 ints each)
-    int64_t nmax;            // >= largest n + 1
+    int64_t nmax;            // >= largest n + 65
     int32_t* work;           // tree work counter
+    int32_t nslots;          // slots allocated (a launch is clamped to them)
 };
 
 struct FlagsDev {

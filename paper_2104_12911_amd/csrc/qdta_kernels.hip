@@ -1282,10 +1282,12 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
     if (t_end <= t_begin) return hipSuccess;
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
-    const int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
-    dim3 g(blocks), b(kWG);
+    int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
     if (variant >= 8) {
         // one workgroup per tree (scratch slot = workgroup)
+        blocks = min(blocks, scr.nslots);
+        if (blocks <= 0) return hipErrorInvalidValue;
+        dim3 g(blocks), b(kWG);
 #define QDTA_SSSP_WG(U, V) \
     hipLaunchKernelGGL((k_sssp_wg<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, t_begin, \
                        t_end)
@@ -1300,6 +1302,10 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
 #undef QDTA_SSSP_WG
         return hipGetLastError();
     }
+    // one wavefront per tree (scratch slot = wavefront)
+    blocks = min(blocks, scr.nslots / (kWG / 64));
+    if (blocks <= 0) return hipErrorInvalidValue;
+    dim3 g(blocks), b(kWG);
 #define QDTA_SSSP(U, V) \
     hipLaunchKernelGGL((k_sssp_ds<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, \
                        t_begin, t_end)

@@ -210,6 +210,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 }
 
 int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 32; }
+int tree_waves(const qdta_opts* o) { return o->tree_waves == 1 ? 1 : 4; }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
 // Kernel variants 0-5: one wavefront per tree; 8-13: one workgroup per tree
@@ -340,13 +341,17 @@ NetDev net_view(qdta_ctx* c) {
 // are n 32-bit words at dest_lab[t], each tree padded to 32 words (128 bytes).
 int64_t tree_words(int64_t n) { return (n + 31) / 32 * 32; }
 
-int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
+// c->slots: wavefronts of a shortest-path launch (whole workgroups of four).
+// Scratch: one slot per tree in flight, i.e. per wavefront (tree_waves 1) or
+// per workgroup (tree_waves 4); launches never use more slots than exist.
+int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
     int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1), (int64_t)c->cus * wpc);
-    slots = (slots + 3) / 4 * 4;                 // whole workgroups of four wavefronts
+    slots = (slots + 3) / 4 * 4;
     c->slots = slots;
+    const int need = tw == 1 ? slots : slots / 4;
     nmax = std::max<int64_t>(nmax, 1) + 65;      // near rings: n queued nodes in n + (up to 64) slots
-    if (slots > c->scr_slots || nmax > c->scr_nmax) {
-        int64_t ns = std::max<int64_t>(slots, c->scr_slots), nm = std::max<int64_t>(nmax, c->scr_nmax);
+    if (need > c->scr_slots || nmax > c->scr_nmax) {
+        int64_t ns = std::max<int64_t>(need, c->scr_slots), nm = std::max<int64_t>(nmax, c->scr_nmax);
         RC(dalloc(c, c->nearq, (size_t)ns * nm));
         RC(dalloc(c, c->farq, (size_t)ns * nm * 2));
         c->scr_slots = (int)ns;
@@ -358,9 +363,10 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc) {
     return QDTA_OK;
 }
 
-int ensure_demand(qdta_ctx* c, int wpc) {
+// wpc = 0: the demand tables only (no shortest-path scratch).
+int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     RC(ensure_network(c));
-    if (!c->dem_dirty) return ensure_scratch(c, c->Q, c->nmax, wpc);
+    if (!c->dem_dirty) return wpc > 0 ? ensure_scratch(c, c->Q, c->nmax, wpc, tw) : QDTA_OK;
     int ni = (int)c->inst.size();
     std::vector<int32_t> qptr{0}, leg_orig, leg_q, dest_node, dest_inst;
     std::vector<int64_t> leg_dfx, dest_lab;
@@ -417,7 +423,7 @@ int ensure_demand(qdta_ctx* c, int wpc) {
     RC(dalloc(c, c->absorb_q, (size_t)c->Q));
     RC(dalloc(c, c->int_node, (size_t)c->P));
     RC(dalloc(c, c->int_tau, (size_t)c->P));
-    RC(ensure_scratch(c, c->Q, nmax, wpc));
+    if (wpc > 0) RC(ensure_scratch(c, c->Q, nmax, wpc, tw));
     c->dem_dirty = false;
     c->solved = false;
     c->lab_hist_ok.clear();
@@ -460,6 +466,7 @@ Scratch scr_view(qdta_ctx* c) {
     s.farq = c->farq.p;
     s.nmax = c->scr_nmax;
     s.work = c->work.p;
+    s.nslots = c->scr_slots;
     return s;
 }
 
@@ -910,7 +917,7 @@ int qdta_set_demand(qdta_ctx* c, int32_t inst, int32_t P, const int32_t* orig, c
 int qdta_layout(qdta_ctx* c, qdta_layout_info* info) {
     if (!c || !info) return QDTA_EARG;
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, 16));
+    if (c->dem_dirty) RC(ensure_demand(c, 0));
     info->n_instances = (int32_t)c->inst.size();
     info->total_nodes = c->N;
     info->total_links = c->M;
@@ -922,7 +929,7 @@ int qdta_layout(qdta_ctx* c, qdta_layout_info* info) {
 int qdta_offsets(qdta_ctx* c, int64_t* node_off, int64_t* link_off, int64_t* leg_off, int64_t* dest_off) {
     if (!c) return QDTA_EARG;
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, 16));
+    if (c->dem_dirty) RC(ensure_demand(c, 0));
     size_t k = c->inst.size() + 1;
     if (node_off) std::copy(c->node_off.begin(), c->node_off.begin() + k, node_off);
     if (link_off) std::copy(c->link_off.begin(), c->link_off.begin() + k, link_off);
@@ -950,7 +957,7 @@ int qdta_bpr(qdta_ctx* c, const qdta_opts* o, const int64_t* f, float* cost) {
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!f || !cost) return set_err(c, QDTA_EARG, "null array");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o)));   // kappa of each instance
+    if (c->dem_dirty) RC(ensure_demand(c, 0));   // kappa of each instance
     RC(clear_flags(c));
     HIPCHECK(c, launch_bpr(c->stream, net_view(c), f, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
     int h[4];
@@ -999,7 +1006,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         if ((rc = dalloc(c, lab, (size_t)nq * tree_words(I.n)))) break;
         if ((rc = dalloc(c, aq, nq))) break;
         int saved_slots = c->slots;
-        if ((rc = ensure_scratch(c, nq, std::max<int64_t>(c->nmax, I.n), waves_per_cu(o)))) break;
+        if ((rc = ensure_scratch(c, nq, std::max<int64_t>(c->nmax, I.n), waves_per_cu(o), tree_waves(o)))) break;
         int slots = c->slots;
         c->slots = saved_slots;
         DemDev dem;
@@ -1045,7 +1052,7 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!cost || !y) return set_err(c, QDTA_EARG, "null array");
-    RC(ensure_demand(c, waves_per_cu(o)));
+    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
@@ -1068,7 +1075,7 @@ int qdta_ls_eval(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (K < 1 || K > kMaxK || !f || !y || !alphas || !sums) return set_err(c, QDTA_EARG, "bad arguments");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o)));
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     int ni = (int)c->inst.size();
     RC(clear_flags(c));
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->ls_acc.p), 0, (int64_t)ni * K * 6));
@@ -1087,7 +1094,7 @@ int qdta_line_search(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const in
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!f || !y || !alpha_out || j < 1) return set_err(c, QDTA_EARG, "bad arguments");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o)));
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     int ni = (int)c->inst.size();
     RC(init_state(c, true, j));
     RC(clear_flags(c));
@@ -1115,7 +1122,7 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     if (!opts_ok(c, o)) return QDTA_EARG;
     for (const Instance& I : c->inst)
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solving");
-    RC(ensure_demand(c, waves_per_cu(o)));
+    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
     NetDev net = net_view(c);
     RC(init_state(c, false, 0));
@@ -1330,7 +1337,7 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
     if (!(budget_ms > 0.0)) return set_err(c, QDTA_EARG, "budget_ms must be > 0");
     for (const Instance& I : c->inst)
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "autotune needs the demand of every instance");
-    RC(ensure_demand(c, waves_per_cu(o)));
+    RC(ensure_demand(c, waves_per_cu(o), 1));            // slots for either kernel form
     RC(apply_rule(c, o));
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
