@@ -212,7 +212,7 @@ def mode_day(args, torch, qdta):
     stop = qdta.STOP_OBJ if args.stop == "obj" else qdta.STOP_GAP
     opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1,
                              launch_form=1 if args.profile_day else 0, tree_waves=args.tree_waves,
-                             waves_per_cu=args.waves_per_cu)
+                             waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, tot_trips, carried = [], 0.0, 0
@@ -251,7 +251,8 @@ def mode_day(args, torch, qdta):
     ctx.close()
     print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
-                      "stop_rule": args.stop, "tree_waves": opts.tree_waves or 4, "left_after_last_trips": carried / FX,
+                      "stop_rule": args.stop, "tree_waves": opts.tree_waves or 4,
+                      "delta_scale": opts.delta_scale or 10.0, "left_after_last_trips": carried / FX,
                       "split_s": {k: round(v, 3) for k, v in split.items()}}), flush=True)
 
 
