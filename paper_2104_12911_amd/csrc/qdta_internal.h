@@ -58,6 +58,7 @@ struct NetDev {
     const int32_t* rsrc;     // [M]   tail (global node) of each in-link
     const int32_t* rlink;    // [M]   global link id of each in-link
     const int32_t* revpos;   // [M]   position of link a in the reverse arrays
+    uint2* fadj;             // [M]   forward records (head, cost bits): the costs the trees are grown with
     const InstDev* inst;     // [ninst]
     const int32_t* blk_inst; // [nblk] instance of each link chunk
     const int32_t* blk_start;// [nblk] first global link of each chunk
@@ -145,8 +146,9 @@ hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, cons
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
                        float* delta_inst, double* logsum, int variant, int early);
 
+// time_cost NULL: the trees' own costs (held in the forward records)
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
-                       const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
+                       const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int64_t* r_dense,
                        unsigned long long* done_fx, int l_begin = 0, int l_end = -1);

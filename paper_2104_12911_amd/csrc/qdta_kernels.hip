@@ -168,7 +168,10 @@ __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restri
         float c32 = (float)c;
         if (!(c32 <= 3.4028234663852886e38f)) bad = 1;
         cost[a] = c32;
-        if (radj) radj[net.revpos[a]].y = __float_as_uint(c32);
+        if (radj) {
+            radj[net.revpos[a]].y = __float_as_uint(c32);
+            net.fadj[a].y = __float_as_uint(c32);
+        }
     }
     if (bad) atomicOr(err, 1);
 }
@@ -540,12 +543,15 @@ hipError_t launch_fw_update(hipStream_t s, const NetDev& net, int64_t* f, const 
     return hipGetLastError();
 }
 
-// Costs into the reverse adjacency records (source node, cost) read by the
-// shortest-path kernel: one 8-byte record per in-link.
+// Costs into the link records: the reverse records (source node, cost) read
+// by the shortest-path kernels, one 8-byte record per in-link, and the
+// forward records (head node, cost) read by the walks.
 __global__ __launch_bounds__(kWG) void k_scatter_rcost(NetDev net, const float* __restrict__ cost,
                                                        uint2* __restrict__ radj) {
-    for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG)
+    for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG) {
         radj[net.revpos[a]].y = __float_as_uint(cost[a]);
+        net.fadj[a].y = __float_as_uint(cost[a]);
+    }
 }
 
 hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, uint2* radj) {
@@ -1346,6 +1352,25 @@ __device__ __forceinline__ int succ_strict(const NetDev& net, const label_t* lab
     return -1;
 }
 
+// The same successor, reading (head, cost) from the forward link records,
+// whose costs are the ones the trees were grown with: one line per link
+// instead of the head and cost arrays.  Also returns the head and the cost.
+__device__ __forceinline__ int succ_rec(const NetDev& net, const label_t* lab, int node0, int u, float du, int& head,
+                                       float& cost) {
+    const int e1 = net.row_ptr[u + 1];
+    for (int e = net.row_ptr[u]; e < e1; ++e) {
+        const uint2 r = net.fadj[e];
+        const float dw = lab_val(lab, (int)r.x - node0);
+        const float c = __uint_as_float(r.y);
+        if (dw < du && dw + c == du) {
+            head = (int)r.x;
+            cost = c;
+            return e;
+        }
+    }
+    return -1;
+}
+
 struct WalkOut {
     int64_t* y;
     int32_t* stop;
@@ -1373,8 +1398,9 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
     atomicAdd(reinterpret_cast<unsigned long long*>(&o.r_dense[lab0 + (s - node0)]), (unsigned long long)w);
 }
 
+// time_cost: the costs that clock the truncation (Eq. 2); NULL = the trees'
+// own costs (the forward records), as in the AON of an iteration.
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
-                                              const float* __restrict__ tree_cost,
                                               const float* __restrict__ time_cost, const InstState* st,
                                               FlagsDev fl, WalkOut o, int l_begin, int l_end) {
     const int l = l_begin + blockIdx.x * kWG + threadIdx.x;
@@ -1398,7 +1424,9 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
     float tau = 0.0f;
     for (int hops = 0; u != q; ++hops) {
         if (I.rule == RULE_CEIL && tau >= I.dt32) break;
-        const int e = succ_strict(net, lab, node0, u, du, tree_cost);
+        int head = 0;
+        float ce = 0.0f;
+        const int e = succ_rec(net, lab, node0, u, du, head, ce);
         if (e < 0 || hops > I.n) {                // absorption: finish in the fallback
             fl.int_node[l] = u;
             fl.int_tau[l] = tau;
@@ -1406,25 +1434,25 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
             atomicAdd(fl.absorb_count, 1);
             return;
         }
-        const float nt = tau + time_cost[e];
+        const float nt = tau + (time_cost ? time_cost[e] : ce);
         if (I.rule == RULE_FLOOR && nt > I.dt32) break;
         if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
         tau = nt;
-        u = net.col[e];
+        u = head;
         du = lab_val(lab, u - node0);
     }
     finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
 }
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
-                       const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
+                       const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int64_t* r_dense, unsigned long long* done_fx,
                        int l_begin, int l_end) {
     if (l_end < 0) l_end = dem.P;
     if (l_end <= l_begin) return hipSuccess;
     WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
-    hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, tree_cost,
+    hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels,
                        time_cost, st, fl, o, l_begin, l_end);
     return hipGetLastError();
 }

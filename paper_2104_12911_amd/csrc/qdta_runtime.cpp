@@ -82,6 +82,7 @@ struct qdta_ctx {
     DBuf<int64_t> f, y;
     DBuf<float> cost, cfin;
     DBuf<uint2> radj;             // reverse adjacency records (source node, cost)
+    DBuf<uint2> fadj;             // forward link records (head node, cost)
     DBuf<InstState> st;
     DBuf<long long> acc, ls_acc;
     DBuf<double> alphas, alpha_arr;
@@ -294,9 +295,13 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->y, c->M));
     RC(dalloc(c, c->cost, c->M));
     {
-        std::vector<uint2> ra(c->M);
-        for (int64_t k = 0; k < c->M; ++k) ra[k] = make_uint2((uint32_t)rsrc[k], 0u);
+        std::vector<uint2> ra(c->M), fa(c->M);
+        for (int64_t k = 0; k < c->M; ++k) {
+            ra[k] = make_uint2((uint32_t)rsrc[k], 0u);
+            fa[k] = make_uint2((uint32_t)col[k], 0u);
+        }
         RC(upload(c, c->radj, ra));
+        RC(upload(c, c->fadj, fa));
     }
     RC(dalloc(c, c->cfin, c->M));
     RC(dalloc(c, c->st, ni));
@@ -327,6 +332,7 @@ NetDev net_view(qdta_ctx* c) {
     v.rsrc = c->rsrc.p;
     v.rlink = c->rlink.p;
     v.revpos = c->revpos.p;
+    v.fadj = c->fadj.p;
     v.inst = c->d_inst.p;
     v.blk_inst = c->blk_inst.p;
     v.blk_start = c->blk_start.p;
@@ -542,10 +548,10 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
     if (o->launch_form == 2) {
         for (int64_t qi = 0; qi < c->Q; ++qi)
-            HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
+            HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, nullptr, y, stop, st, fl, 0, nullptr, nullptr,
                                     nullptr, c->h_qptr[qi], c->h_qptr[qi + 1]));
     } else {
-        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, 0, nullptr, nullptr,
+        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, nullptr, y, stop, st, fl, 0, nullptr, nullptr,
                                 nullptr));
     }
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
@@ -1484,15 +1490,16 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         const double* lamj = c->lam_hist.p + (size_t)j * ni;
         const float* cj = c->hist_cost.p + (size_t)j * c->M;
         label_t* lab = c->labels.p;
+        // the trees' costs c_j into the link records (the walk's tight test reads them)
+        HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
         if ((size_t)j < c->lab_hist_ok.size() && c->lab_hist_ok[j]) {
             lab = c->lab_hist.p + (size_t)j * c->label_count;    // the solve's own trees of iterate j
         } else {
-            HIPCHECK(c, launch_scatter_rcost(c->stream, net, cj, c->radj.p));
             HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, stj,
                                     delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
         }
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
-        HIPCHECK(c, launch_walk(c->stream, net, dem, lab, cj, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
+        HIPCHECK(c, launch_walk(c->stream, net, dem, lab, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
                                 c->r_dense.p, c->done_fx.p));
         HIPCHECK(c, launch_fallback(c->stream, net, dem, lab, cj, c->cfin.p, nullptr, nullptr, stj, fl,
                                     scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
