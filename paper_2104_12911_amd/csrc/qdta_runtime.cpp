@@ -148,7 +148,7 @@ template <class T>
 int dalloc(qdta_ctx* c, DBuf<T>& b, size_t n) {
     if (b.p && b.n >= n && n > 0) return QDTA_OK;
     if (b.p) {
-        hipFree(b.p);
+        (void)hipFree(b.p);
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)b.p);
         if (it != c->allocs.end()) c->allocs.erase(it);
         b.p = nullptr;
@@ -158,7 +158,7 @@ int dalloc(qdta_ctx* c, DBuf<T>& b, size_t n) {
     hipError_t e = hipMalloc((void**)&b.p, bytes);
     if (e != hipSuccess) {
         b.p = nullptr;
-        hipGetLastError();
+        (void)hipGetLastError();
         return set_err(c, QDTA_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
     b.n = std::max<size_t>(n, 1);
@@ -312,7 +312,7 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->flags, 4));
     RC(dalloc(c, c->done_fx, ni));
     if (c->h_st_n < ni) {
-        if (c->h_st) hipHostFree(c->h_st);
+        if (c->h_st) (void)hipHostFree(c->h_st);
         HIPCHECK(c, hipHostMalloc((void**)&c->h_st, sizeof(InstState) * ni, hipHostMallocDefault));
         c->h_st_n = ni;
     }
@@ -674,7 +674,7 @@ int plan_label_history(qdta_ctx* c, const qdta_opts* o) {
     if (slots == 0) return QDTA_OK;
     if (c->lab_hist.n < slots * per) {
         if (c->lab_hist.p) {
-            hipFree(c->lab_hist.p);
+            (void)hipFree(c->lab_hist.p);
             auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->lab_hist.p);
             if (it != c->allocs.end()) c->allocs.erase(it);
             c->lab_hist.p = nullptr;
@@ -708,7 +708,7 @@ int ensure_history(qdta_ctx* c, size_t iters) {
                                    hipMemcpyDeviceToDevice, c->stream));
     if (c->hist_cost.p) {
         HIPCHECK(c, hipStreamSynchronize(c->stream));
-        hipFree(c->hist_cost.p);
+        (void)hipFree(c->hist_cost.p);
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->hist_cost.p);
         if (it != c->allocs.end()) c->allocs.erase(it);
     }
@@ -804,13 +804,13 @@ int qdta_create(qdta_ctx** out, int device, void* stream) {
 
 int qdta_destroy(qdta_ctx* c) {
     if (!c) return QDTA_EARG;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
-    for (void* p : c->allocs) hipFree(p);
-    if (c->h_st) hipHostFree(c->h_st);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->h_st) (void)hipHostFree(c->h_st);
     for (int p = 0; p < 8; ++p)
         for (int e = 0; e < 2; ++e)
-            if (c->prof_ev[p][e]) hipEventDestroy(c->prof_ev[p][e]);
+            if (c->prof_ev[p][e]) (void)hipEventDestroy(c->prof_ev[p][e]);
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -999,7 +999,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     auto cleanup = [&]() {
         for (void* p : {(void*)ddn.p, (void*)ddi.p, (void*)aq.p, (void*)ddl.p, (void*)lab.p}) {
             if (!p) continue;
-            hipFree(p);
+            (void)hipFree(p);
             auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
             if (it != c->allocs.end()) c->allocs.erase(it);
         }

@@ -398,6 +398,22 @@ def test_config3_peak_full_size(torch_dev, q, orc):
     assert st[0]["iters"] == ref.iters
 
 
+def test_config4_full_batch_sampled(torch_dev, q, orc):
+    """All 64 uneven networks at full size in one context (4.7M links,
+    33,840 trees; one launch sequence per FW iteration, replayed as a HIP
+    graph): three sampled instances, the largest among them, equal the
+    single-instance oracle bit for bit after two iterations."""
+    insts = synth.config4()
+    opts = q.default_opts(fixed_iters=2)
+    st, f, off, (o, d, wfx), rc = _solve(torch_dev, q, [(x.net, x.demand) for x in insts], opts)
+    big = int(np.argmax([x.net.m for x in insts]))
+    for i in (big, 7, 40):
+        x = insts[i]
+        a, b = off["leg"][i], off["leg"][i + 1]
+        ref = orc.fw_solve(x.net, o[a:b], d[a:b], wfx[a:b], fixed_iters=2, keep_history=False)
+        _cmp_fw(st[i], None, f[off["link"][i]:off["link"][i + 1]], ref)
+
+
 def test_fw_batched_instances_match_single(torch_dev, q, orc):
     """Several uneven grids in one context (one launch sequence per FW
     iteration) give, per instance, exactly the single-instance oracle result."""
