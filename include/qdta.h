@@ -258,6 +258,17 @@ int qdta_advance_interval(qdta_ctx *ctx, const qdta_opts *opts);
 int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host_orig,
                       int32_t *host_dest, int64_t *host_w_fx, int64_t *host_done_fx);
 
+/* Resume (Alg. 1): the whole state carried from interval i to i+1 is the
+ * residual demand d^r(i+1), so a day stopped after qdta_advance_interval and
+ * qdta_get_residual continues, bit for bit, in another context on the same
+ * network: qdta_set_residual replaces instance inst's pending residual with
+ * count legs (host inputs, copied) in the order qdta_get_residual returns
+ * them, strictly increasing by (destination, origin), origin != destination,
+ * w_fx > 0; the next qdta_set_demand merges them as it merges its own.
+ * count = 0 clears it.  Errors: QDTA_EARG (ids out of range, order, weights). */
+int qdta_set_residual(qdta_ctx *ctx, int32_t inst, int64_t count, const int32_t *host_orig,
+                      const int32_t *host_dest, const int64_t *host_w_fx);
+
 /* Autotuner: times the shortest-path launch of the current demand (every
  * instance, under the costs BPR(f) of the last solved iterate, free-flow
  * costs otherwise) for a grid of kernel shapes, bucket widths and

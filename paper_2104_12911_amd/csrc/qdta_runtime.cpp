@@ -1568,4 +1568,25 @@ int qdta_get_residual(qdta_ctx* c, int32_t inst, int64_t* count, int32_t* ho, in
     return QDTA_OK;
 }
 
+int qdta_set_residual(qdta_ctx* c, int32_t inst, int64_t count, const int32_t* ho, const int32_t* hd,
+                      const int64_t* hw) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
+    if (count < 0 || (count > 0 && (!ho || !hd || !hw))) return set_err(c, QDTA_EARG, "bad residual legs");
+    Instance& I = c->inst[inst];
+    for (int64_t p = 0; p < count; ++p) {
+        if (ho[p] < 0 || ho[p] >= I.n || hd[p] < 0 || hd[p] >= I.n || ho[p] == hd[p])
+            return set_err(c, QDTA_EARG, "residual leg %lld: bad nodes", (long long)p);
+        if (hw[p] <= 0) return set_err(c, QDTA_EARG, "residual leg %lld: weight <= 0", (long long)p);
+        if (p > 0 && !(hd[p - 1] < hd[p] || (hd[p - 1] == hd[p] && ho[p - 1] < ho[p])))
+            return set_err(c, QDTA_EARG, "residual leg %lld: not in (destination, origin) order", (long long)p);
+    }
+    I.r_orig.assign(ho, ho + count);
+    I.r_dest.assign(hd, hd + count);
+    I.r_w.assign(hw, hw + count);
+    I.r_done = 0;
+    return QDTA_OK;
+}
+
 }  // extern "C"

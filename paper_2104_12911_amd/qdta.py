@@ -27,7 +27,7 @@ EXPORTS = [
     "qdta_default_opts", "qdta_strerror", "qdta_last_error", "qdta_create", "qdta_destroy", "qdta_set_stream",
     "qdta_add_network", "qdta_set_demand", "qdta_layout", "qdta_offsets", "qdta_bpr", "qdta_trees", "qdta_aon",
     "qdta_get_legs", "qdta_ls_eval", "qdta_line_search", "qdta_fw_update", "qdta_solve", "qdta_get_flows",
-    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_fw_begin", "qdta_fw_step",
+    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_set_residual", "qdta_fw_begin", "qdta_fw_step",
     "qdta_profile_enable", "qdta_profile_read", "qdta_autotune",
 ]
 PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
@@ -102,6 +102,7 @@ def lib():
         L.qdta_get_costs.argtypes = [vp, vp, vp]
         L.qdta_advance_interval.argtypes = [vp, vp]
         L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64)]
+        L.qdta_set_residual.argtypes = [vp, i32, i64, vp, vp, vp]
         L.qdta_fw_begin.argtypes = [vp, vp]
         L.qdta_fw_step.argtypes = [vp, vp, vp, C.POINTER(i32)]
         L.qdta_profile_enable.argtypes = [vp, i32]
@@ -290,6 +291,12 @@ class Context:
         o, d, w = np.zeros(k, np.int32), np.zeros(k, np.int32), np.zeros(k, np.int64)
         self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), _ptr(o), _ptr(d), _ptr(w), C.byref(done)))
         return o, d, w, done.value
+
+    def set_residual(self, inst, orig, dest, w_fx):
+        o, d, w = _np(orig, np.int32), _np(dest, np.int32), _np(w_fx, np.int64)
+        if not (len(o) == len(d) == len(w)):
+            raise ValueError("residual arrays differ in length")
+        self._rc(lib().qdta_set_residual(self._h, int(inst), len(o), _ptr(o), _ptr(d), _ptr(w)))
 
 
 def kappa(dt_s: float) -> float:

@@ -520,6 +520,70 @@ def test_day_peak_scaled_network(torch_dev, q, orc):
             assert a["done"] == b["done_fx"], hist
 
 
+def test_day_resume_from_saved_residual(torch_dev, q, orc):
+    """Checkpoint and resume: a day stopped after interval 2 (its residual
+    legs read back to the host, the context destroyed) and continued in a
+    fresh context from qdta_set_residual gives the flows and residual legs
+    of the uninterrupted run bit for bit."""
+    w = synth.config1()
+    rng = np.random.default_rng(31)
+    days = []
+    for frac in (0.7, 0.4, 0.6, 0.3, 0.5):
+        sel = rng.random(w.demand.P) < frac
+        days.append(synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] / 2, 450.0))
+    opts = q.default_opts(keep_history=1, tol=1e-3, max_iter=25)
+    whole = _day_gpu(torch_dev, q, w.net, days, opts)
+    head = _day_gpu(torch_dev, q, w.net, days[:3], opts)
+    saved = head[-1]["res"]
+    assert len(saved[0]) > 0
+    tail = []
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_residual(0, *saved)
+        o, d, wt, _ = ctx.residual(0)
+        assert all(np.array_equal(x, y) for x, y in zip((o, d, wt), saved))
+        for dem in days[3:]:
+            ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
+            st, rc = ctx.solve(opts)
+            f = torch_dev.empty(w.net.m, dtype=torch_dev.int64, device="cuda")
+            ctx.get_flows(f)
+            ctx.advance_interval(opts)
+            ro, rd, rw, done = ctx.residual(0)
+            tail.append({"f": host(f), "res": (ro, rd, rw), "iters": st[0]["iters"]})
+    for a_, b_ in zip(head + tail, whole):
+        assert a_["iters"] == b_["iters"]
+        assert np.array_equal(a_["f"], b_["f"])
+        for x, y in zip(a_["res"], b_["res"]):
+            assert np.array_equal(x, y)
+    ref, _ = orc.qdta_day(w.net, days, tol=1e-3, max_iter=25)
+    for a_, b_ in zip(whole, ref):
+        assert np.array_equal(a_["f"], b_["f"])
+
+
+def test_set_residual_rejects_bad_legs(torch_dev, q):
+    w = synth.config1()
+    n = w.net.n
+    bad = [([1, 2], [5, 5], [3, 0]),            # weight 0
+           ([2, 1], [5, 5], [3, 3]),            # origins out of order
+           ([1, 1], [5, 5], [3, 3]),            # repeated leg
+           ([1, 2], [7, 5], [3, 3]),            # destinations out of order
+           ([5], [5], [3]),                     # origin == destination
+           ([n], [0], [3]),                     # node out of range
+           ([0], [-1], [3])]
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        for o, d, wt in bad:
+            with pytest.raises(q.QdtaError) as e:
+                ctx.set_residual(0, np.array(o), np.array(d), np.array(wt))
+            assert e.value.code == q.EARG
+        with pytest.raises(q.QdtaError):
+            ctx.set_residual(1, np.array([1]), np.array([2]), np.array([3]))
+        ctx.set_residual(0, np.array([1, 3, 0]), np.array([2, 2, 4]), np.array([5, 6, 7]))
+        assert ctx.residual(0)[0].tolist() == [1, 3, 0]
+        ctx.set_residual(0, np.zeros(0), np.zeros(0), np.zeros(0))
+        assert ctx.residual(0)[0].size == 0
+
+
 def test_day_demand_shrinks_and_regrows(torch_dev, q, orc):
     """Intervals whose leg and destination counts fall and then rise again
     within the buffers of the largest one: every interval is re-captured
