@@ -418,6 +418,74 @@ int orc_aon(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, co
     return absorb ? ORC_WARN_ABSORB : ORC_OK;
 }
 
+/* Truncated paths (the link incidence of Eq. 5 under one set of trees): for
+ * every leg, the links the walk of orc_aon loads, in walk order.  ptr
+ * (int64[P+1]) always receives the offsets; links (int32[ptr[P]]) is filled
+ * when not NULL.  Legs that orc_aon skips (d <= 0 or origin == destination)
+ * have empty paths.  Single-threaded. */
+typedef struct { int32_t *links; int64_t at; } pathctx;
+
+static void put_link(void *ctx, int32_t e) {
+    pathctx *pc = (pathctx *)ctx;
+    if (pc->links) pc->links[pc->at] = e;
+    pc->at++;
+}
+
+int orc_paths(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
+              int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx, double dt_s,
+              int32_t rule, int64_t *ptr, int32_t *links) {
+    if (orc_check_csr(n, m, row_ptr, col)) return ORC_ECSR;
+    for (int32_t p = 0; p < P; ++p)
+        if (orig[p] < 0 || orig[p] >= n || dest[p] < 0 || dest[p] >= n) return ORC_EARG;
+    graph_t g;
+    if (graph_build(&g, n, m, row_ptr, col)) return ORC_EARG;
+    int eff = effective_rule(dt_s, rule);
+    float dt32 = (float)dt_s;
+    float *D = (float *)malloc(sizeof(float) * (size_t)n);
+    int32_t *succ = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *qu = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *len = (int64_t *)calloc((size_t)(P > 0 ? P : 1), sizeof(int64_t));
+    heap_t h = {0};
+    int32_t *qptr;
+    int32_t *idx = legs_by_dest(n, P, dest, &qptr);
+    int rc = ORC_OK;
+    /* pass 1: lengths */
+    for (int32_t q = 0; q < n && rc >= 0; ++q) {
+        if (qptr[q] == qptr[q + 1]) continue;
+        dijkstra_to(&g, cost, q, D, &h);
+        if (successors(&g, cost, q, D, succ, hop, qu)) rc = ORC_WARN_ABSORB;
+        for (int32_t i = qptr[q]; i < qptr[q + 1]; ++i) {
+            int32_t p = idx[i];
+            if (d_fx[p] <= 0 || orig[p] == q) continue;
+            if (!isfinite(D[orig[p]])) { rc = ORC_EUNREACH; break; }
+            pathctx pc = {NULL, 0};
+            walk_leg(col, succ, cost, orig[p], q, dt32, eff, put_link, &pc);
+            len[p] = pc.at;
+        }
+    }
+    ptr[0] = 0;
+    for (int32_t p = 0; p < P; ++p) ptr[p + 1] = ptr[p] + len[p];
+    /* pass 2: the links, written at each leg's offset */
+    if (links && rc >= 0) {
+        for (int32_t q = 0; q < n; ++q) {
+            if (qptr[q] == qptr[q + 1]) continue;
+            dijkstra_to(&g, cost, q, D, &h);
+            successors(&g, cost, q, D, succ, hop, qu);
+            for (int32_t i = qptr[q]; i < qptr[q + 1]; ++i) {
+                int32_t p = idx[i];
+                if (d_fx[p] <= 0 || orig[p] == q) continue;
+                pathctx pc = {links + ptr[p], 0};
+                walk_leg(col, succ, cost, orig[p], q, dt32, eff, put_link, &pc);
+            }
+        }
+    }
+    free(idx); free(qptr); free(len);
+    free(D); free(succ); free(hop); free(qu); free(h.a);
+    graph_free(&g);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Line search (Eq. 6, Eq. 8-10, Alg. 8-9)                                   */
 /* ------------------------------------------------------------------------ */
