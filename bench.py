@@ -57,9 +57,22 @@ def sssp_bytes_per_tree(n, m):
     return 8.0 * n + 8.0 * m
 
 
-def traffic_entry(kernel_src_hash):
+# kernel instantiation per (sssp_shape, tree_waves): nodes per thread and
+# in-links per thread of each relaxation chunk
+WG_SHAPES = {1: (1, 2), 2: (1, 4), 3: (2, 4), 4: (4, 4), 5: (2, 2), 6: (4, 2)}
+DS_SHAPES = {1: (1, 4), 2: (2, 4), 3: (4, 4), 4: (4, 8), 5: (8, 8), 6: (1, 1)}
+
+
+def sssp_kernel_name(shape, tree_waves):
+    shape = shape if shape in WG_SHAPES else 3
+    if (tree_waves or 4) == 1:
+        return "k_sssp_ds<%d, %d>" % DS_SHAPES[shape]
+    return "k_sssp_wg<%d, %d>" % WG_SHAPES[shape]
+
+
+def traffic_entry(kernel_src_hash, kernel):
     """HBM bytes per SSSP launch from the rocprofv3 PMC runs, if they were
-    taken on the current kernel source."""
+    taken on the current kernel source and the same instantiation."""
     path = os.path.join(ROOT, "profiles", "sssp_traffic.json")
     if not os.path.exists(path):
         return None
@@ -68,7 +81,7 @@ def traffic_entry(kernel_src_hash):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256") != kernel_src_hash:
+    if t.get("kernel_sha256") != kernel_src_hash or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
 
@@ -357,7 +370,8 @@ def main():
     bytes_launch = Q * sssp_bytes_per_tree(net.n, net.m) + 8.0 * net.m + 4.0 * net.n
     achieved = bytes_launch / sssp_avg_s / 1e9
     src = open(os.path.join(ROOT, "paper_2104_12911_amd", "csrc", "qdta_kernels.hip"), "rb").read()
-    traffic = traffic_entry(hashlib.sha256(src).hexdigest())
+    kname = sssp_kernel_name(opts.sssp_shape, opts.tree_waves)
+    traffic = traffic_entry(hashlib.sha256(src).hexdigest(), kname)
     result = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -380,7 +394,7 @@ def main():
         "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sssp_wg" if (opts.tree_waves or 4) == 4 else "k_sssp_ds",
+                     "kernel": kname,
                      "kernel_ms": sssp_avg_s * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_timing": kernel_timing},
         "gap_last": gaps[-1] if gaps else None,

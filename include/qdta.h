@@ -94,7 +94,9 @@ typedef struct {
                               link cost: 0 auto (10.0); any value > 0 gives the same trees, only the speed
                               changes */
     int32_t sssp_shape;    /* shortest-path kernel shape, nodes per lane per step x links per lane per
-                              chunk: 0 auto, 1 (1,4), 2 (2,4), 3 (4,4), 4 (4,8), 5 (8,8), 6 (1,1) */
+                              chunk, 0 auto (3); four wavefronts per tree: 1 (1,2), 2 (1,4), 3 (2,4),
+                              4 (4,4), 5 (2,2), 6 (4,2); one: 1 (1,4), 2 (2,4), 3 (4,4), 4 (4,8),
+                              5 (8,8), 6 (1,1) */
     int32_t launch_form;   /* 0 batched: every tree of every instance in one launch, all K step sizes in
                               one pass, one FW iteration replayed as a captured HIP graph when possible
                               (K-section or MSA); 1 batched with direct launches; 2 plain: one launch per
@@ -269,14 +271,51 @@ int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host
 int qdta_set_residual(qdta_ctx *ctx, int32_t inst, int64_t count, const int32_t *host_orig,
                       const int32_t *host_dest, const int64_t *host_w_fx);
 
+/* ---- Derivatives for OD calibration (not in the paper) -------------------
+ * The frozen-path model of a solved interval: its J applied Frank-Wolfe
+ * updates are replayed with every iterate's trees and truncation frozen,
+ * as a function of the demand d (veh per leg) and the capacities C:
+ *     f = L_0 d;  for j = 1..J:  y_j = L_j d,  alpha_j = line search of
+ *     (f, y_j) under C (Eq. 6, opts->ls_mode),  f += rint(alpha_j (y_j - f)),
+ * where L_j loads each leg along its truncated path under iterate j's trees
+ * (Eq. 2, Eq. 5).  At the solve's own demand and capacities it reproduces the
+ * solve's flows bit for bit.  The reverse pass treats alpha_j as the root of
+ * C'(alpha) = 0 (implicit-function theorem; a step at 0 or 1, or an MSA step,
+ * has zero derivative) and the rounding as the identity.  One instance only.
+ *
+ * qdta_adjoint_record: after qdta_solve with opts->keep_history, walks every
+ * leg under every iterate's trees (stored labels, else grown again from the
+ * recorded costs) and keeps the paths in device memory (about 4 bytes per
+ * loaded link per iterate).  Errors: QDTA_ESTATE (no solved interval, no
+ * history, more than one instance, FP32 absorption on a path).
+ * Synchronises. */
+int qdta_adjoint_record(qdta_ctx *ctx, const qdta_opts *opts);
+
+/* Forward pass of the model.  d: double[total_legs] (device), veh per leg in
+ * the context's leg order (qdta_get_legs); cap: float[total_links] (device)
+ * or NULL for the network's capacities; f_out: double[total_links] (device),
+ * veh.  Keeps the iterates for qdta_model_backward.  Errors: QDTA_ESTATE (no
+ * record for the current solve), QDTA_EOVF (non-finite demand or costs).
+ * Synchronises. */
+int qdta_model_forward(qdta_ctx *ctx, const qdta_opts *opts, const double *d, const float *cap,
+                       double *f_out);
+
+/* Reverse pass of the last qdta_model_forward: given fbar = dL/df (double
+ * [total_links], device), writes dbar = dL/dd (double[total_legs]) and
+ * capbar = dL/dC (double[total_links]), device outputs.  Enqueued on the
+ * stream, no synchronisation. */
+int qdta_model_backward(qdta_ctx *ctx, const double *fbar, double *dbar, double *capbar);
+
 /* Autotuner: times the shortest-path launch of the current demand (every
  * instance, under the costs BPR(f) of the last solved iterate, free-flow
  * costs otherwise) for a grid of kernel shapes, bucket widths and
  * wavefronts per tree, stopping once about budget_ms of GPU time is spent,
  * and writes the fastest into opts->sssp_shape, opts->delta_scale and
- * opts->tree_waves (other fields unchanged).  Results never depend on these
- * fields, only the speed does.  *best_ms_out (host, may be NULL) receives
- * the best trial time.  Synchronises. */
+ * opts->tree_waves (other fields unchanged).  The configuration passed in
+ * (zero fields read as the defaults) is timed first, after one untimed
+ * launch, and is kept unless another is at least 2% faster.  Results never
+ * depend on these fields, only the speed does.  *best_ms_out (host, may be
+ * NULL) receives the time of the configuration chosen.  Synchronises. */
 int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best_ms_out);
 
 /* Per-phase timers: HIP events recorded on the context's stream around each

@@ -170,4 +170,16 @@ hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem,
                             const float* cost_local, int32_t inst, float* dist, int32_t* succ,
                             int32_t* absorb_q);
 
+// frozen-path model and its reverse pass (OD calibration)
+hipError_t launch_path_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
+                            const int64_t* ptr, int32_t* links, int64_t* len, int* bad);
+hipError_t launch_path_load(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* d,
+                            int64_t* y, int* err);
+hipError_t launch_path_gather(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* g,
+                              double* dbar, int accumulate);
+hipError_t launch_adj_step(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
+                           const double* alpha, int is_root, double ab, int beta, double* fbar, double* ybar,
+                           double* capbar, double* part /*[2 x 1024]*/, double* sbuf);
+hipError_t launch_fx_to_veh(hipStream_t s, int64_t M, const int64_t* f, double* out);
+
 }  // namespace qdta

@@ -12,7 +12,9 @@
 //                Alg. 8-9), K step sizes per pass over the links
 //   k_fw_update  f <- f + rint(alpha (y - f))
 // plus the tie-rule fallback under FP32 absorption, the residual-demand
-// walk of Alg. 4 and the compaction of its accumulator.
+// walk of Alg. 4 and the compaction of its accumulator, and the frozen-path
+// model of an interval's iterations with its reverse pass (k_path_*,
+// k_adj_*: derivatives for OD calibration, not part of the paper).
 //
 // Numeric contract: FP64 per-link arithmetic with no fused multiply-add (the
 // library is compiled with -ffp-contract=off), power by repeated
@@ -1675,6 +1677,233 @@ hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem,
                             const float* cost, int32_t inst, float* dist, int32_t* succ, int32_t* absorb_q) {
     if (dem.Q == 0) return hipSuccess;
     hipLaunchKernelGGL(k_trees_out, dim3(2048), dim3(kWG), 0, s, net, dem, labels, cost, inst, dist, succ, absorb_q);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Frozen-path model and its reverse pass (OD calibration)
+// ---------------------------------------------------------------------------
+// The truncated path of every leg under one iterate's trees: the links the
+// walk of that iterate loads (same successor rule, same clock), in walk
+// order.  ptr == NULL counts them into len[l]; otherwise they are written at
+// links[ptr[l]], never past ptr[l + 1].  bad: 1 an origin cannot reach its
+// destination, 2 FP32 absorption (the tie fallback's paths are not
+// recorded), 4 a path longer than counted.
+__global__ __launch_bounds__(kWG) void k_path_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
+                                                   const int64_t* __restrict__ ptr, int32_t* __restrict__ links,
+                                                   int64_t* __restrict__ len, int* bad) {
+    const int l = blockIdx.x * kWG + threadIdx.x;
+    if (l >= dem.P) return;
+    const int qi = dem.leg_q[l];
+    const InstDev I = net.inst[dem.dest_inst[qi]];
+    const int node0 = I.node0;
+    const int q = dem.dest_node[qi];
+    const label_t* lab = tree_labels(labels, dem, qi);
+    int u = dem.leg_orig[l];
+    float du = lab_val(lab, u - node0);
+    const int64_t at = ptr ? ptr[l] : 0, end = ptr ? ptr[l + 1] : 0;
+    int64_t k = 0;
+    if (!(du <= 3.4028234663852886e38f)) {
+        atomicOr(bad, 1);
+        if (len) len[l] = 0;
+        return;
+    }
+    float tau = 0.0f;
+    for (int hops = 0; u != q; ++hops) {
+        if (I.rule == RULE_CEIL && tau >= I.dt32) break;
+        int head = 0;
+        float ce = 0.0f;
+        const int e = succ_rec(net, lab, node0, u, du, head, ce);
+        if (e < 0 || hops > I.n) {
+            atomicOr(bad, 2);
+            break;
+        }
+        const float nt = tau + ce;
+        if (I.rule == RULE_FLOOR && nt > I.dt32) break;
+        if (ptr) {
+            if (at + k >= end) {
+                atomicOr(bad, 4);
+                break;
+            }
+            links[at + k] = e;
+        }
+        ++k;
+        tau = nt;
+        u = head;
+        du = lab_val(lab, u - node0);
+    }
+    if (len) len[l] = k;
+}
+
+hipError_t launch_path_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
+                            const int64_t* ptr, int32_t* links, int64_t* len, int* bad) {
+    if (dem.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_path_walk, dim3((dem.P + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, ptr, links,
+                       len, bad);
+    return hipGetLastError();
+}
+
+// y += rint(d 2^20) along every leg's path: the loading of Eq. 5 for a
+// real-valued demand, exact in int64 whatever the order of the atomics.
+__global__ __launch_bounds__(kWG) void k_path_load(int P, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ links, const double* __restrict__ d,
+                                                   int64_t* y, int* err) {
+    const int l = blockIdx.x * kWG + threadIdx.x;
+    if (l >= P) return;
+    const double x = d[l] * 1048576.0;
+    if (!(x > -9.0e18 && x < 9.0e18)) {
+        atomicOr(err, 1);
+        return;
+    }
+    const int64_t w = (int64_t)__builtin_rint(x);
+    if (w == 0) return;
+    for (int64_t k = ptr[l]; k < ptr[l + 1]; ++k)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&y[links[k]]), (unsigned long long)w);
+}
+
+hipError_t launch_path_load(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* d,
+                            int64_t* y, int* err) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_path_load, dim3((P + kWG - 1) / kWG), dim3(kWG), 0, s, P, ptr, links, d, y, err);
+    return hipGetLastError();
+}
+
+// dbar[l] (+)= the sum of g over leg l's path, in walk order: the transpose
+// of the loading.
+__global__ __launch_bounds__(kWG) void k_path_gather(int P, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ links,
+                                                     const double* __restrict__ g, double* dbar, int accumulate) {
+    const int l = blockIdx.x * kWG + threadIdx.x;
+    if (l >= P) return;
+    double acc = 0.0;
+    for (int64_t k = ptr[l]; k < ptr[l + 1]; ++k) acc += g[links[k]];
+    dbar[l] = accumulate ? dbar[l] + acc : acc;
+}
+
+hipError_t launch_path_gather(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* g,
+                              double* dbar, int accumulate) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_path_gather, dim3((P + kWG - 1) / kWG), dim3(kWG), 0, s, P, ptr, links, g, dbar,
+                       accumulate);
+    return hipGetLastError();
+}
+
+// BPR cost, dc/dv and dc/dC at v (veh) in FP64, products left to right.
+__device__ __forceinline__ void bpr_terms(double v, float c0f, float capf, double ab, int beta, double kappa,
+                                          double& cost, double& dcdv, double& dcdcap) {
+    const double c0 = (double)c0f, cap = (double)capf;
+    const double r = (v * kappa) / cap;
+    double p1 = 1.0;
+    for (int k = 1; k < beta; ++k) p1 = p1 * r;
+    const double p = p1 * r;
+    cost = c0 * (1.0 + ab * p);
+    dcdv = c0 * ab * (double)beta * p1 * kappa / cap;
+    dcdcap = -c0 * ab * (double)beta * p / cap;
+}
+
+// Reverse step of one FW update f' = f + alpha (y - f), where alpha is the
+// root of F(a) = sum_a t_a c_a(f_a + a t_a) (t = y - f): per-workgroup
+// partial sums of abar = fbar . t and dF/dalpha = sum t^2 c'(v).
+__global__ __launch_bounds__(kWG) void k_adj_sums(NetDev net, const int64_t* __restrict__ f,
+                                                  const int64_t* __restrict__ y, const double* __restrict__ alpha,
+                                                  const double* __restrict__ fbar, double ab, int beta,
+                                                  double* part) {
+    __shared__ double s0[kWG], s1[kWG];
+    const double al = *alpha, kappa = net.inst[0].kappa;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG) {
+        const double F = (double)f[a] * kFxInv, t = (double)y[a] * kFxInv - F;
+        double cost, dcdv, dcdcap;
+        bpr_terms(F + al * t, net.c0[a], net.cap[a], ab, beta, kappa, cost, dcdv, dcdcap);
+        a0 += fbar[a] * t;
+        a1 += t * t * dcdv;
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int k = kWG / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            s0[threadIdx.x] += s0[threadIdx.x + k];
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// s = -abar / (dF/dalpha) for a step size strictly inside (0, 1) that is a
+// root (not the fixed MSA sequence); 0 otherwise.  One workgroup, partials
+// summed in a fixed order.
+__global__ __launch_bounds__(kWG) void k_adj_scale(const double* __restrict__ part, int nb,
+                                                   const double* __restrict__ alpha, int is_root, double* s_out) {
+    __shared__ double s0[kWG], s1[kWG];
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kWG) {
+        a0 += part[2 * b];
+        a1 += part[2 * b + 1];
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int k = kWG / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            s0[threadIdx.x] += s0[threadIdx.x + k];
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double al = *alpha;
+        *s_out = (is_root && al > 0.0 && al < 1.0 && s1[0] != 0.0) ? -s0[0] / s1[0] : 0.0;
+    }
+}
+
+// Per link: ybar, and fbar and capbar carried back through the update and
+// through alpha's dependence on (f, y, C) (implicit-function theorem).
+__global__ __launch_bounds__(kWG) void k_adj_links(NetDev net, const int64_t* __restrict__ f,
+                                                   const int64_t* __restrict__ y, const double* __restrict__ alpha,
+                                                   const double* __restrict__ sp, double ab, int beta, double* fbar,
+                                                   double* __restrict__ ybar, double* capbar) {
+    const double al = *alpha, s = *sp, kappa = net.inst[0].kappa;
+    for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG) {
+        const double F = (double)f[a] * kFxInv, t = (double)y[a] * kFxInv - F;
+        double cost, dcdv, dcdcap;
+        bpr_terms(F + al * t, net.c0[a], net.cap[a], ab, beta, kappa, cost, dcdv, dcdcap);
+        const double g = fbar[a];
+        ybar[a] = al * g + s * (cost + al * t * dcdv);
+        fbar[a] = (1.0 - al) * g + s * (-cost + (1.0 - al) * t * dcdv);
+        capbar[a] = capbar[a] + s * t * dcdcap;
+    }
+}
+
+static int adj_blocks(int64_t M) {
+    const int64_t b = (M + kWG - 1) / kWG;
+    return b < 1 ? 1 : (b > 1024 ? 1024 : (int)b);
+}
+
+hipError_t launch_adj_step(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
+                           const double* alpha, int is_root, double ab, int beta, double* fbar, double* ybar,
+                           double* capbar, double* part /*[2 x 1024]*/, double* sbuf) {
+    if (net.M == 0) return hipSuccess;
+    const int nb = adj_blocks(net.M);
+    hipLaunchKernelGGL(k_adj_sums, dim3(nb), dim3(kWG), 0, s, net, f, y, alpha, fbar, ab, beta, part);
+    hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(kWG), 0, s, part, nb, alpha, is_root, sbuf);
+    hipLaunchKernelGGL(k_adj_links, dim3(nb), dim3(kWG), 0, s, net, f, y, alpha, sbuf, ab, beta, fbar, ybar, capbar);
+    return hipGetLastError();
+}
+
+// flows in veh from fixed point
+__global__ void k_fx_to_veh(int64_t M, const int64_t* __restrict__ f, double* out) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < M; a += (int64_t)gridDim.x * blockDim.x)
+        out[a] = (double)f[a] * kFxInv;
+}
+
+hipError_t launch_fx_to_veh(hipStream_t s, int64_t M, const int64_t* f, double* out) {
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fx_to_veh, dim3(adj_blocks(M)), dim3(kWG), 0, s, M, f, out);
     return hipGetLastError();
 }
 

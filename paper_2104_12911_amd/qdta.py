@@ -27,7 +27,8 @@ EXPORTS = [
     "qdta_default_opts", "qdta_strerror", "qdta_last_error", "qdta_create", "qdta_destroy", "qdta_set_stream",
     "qdta_add_network", "qdta_set_demand", "qdta_layout", "qdta_offsets", "qdta_bpr", "qdta_trees", "qdta_aon",
     "qdta_get_legs", "qdta_ls_eval", "qdta_line_search", "qdta_fw_update", "qdta_solve", "qdta_get_flows",
-    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_set_residual", "qdta_fw_begin", "qdta_fw_step",
+    "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_set_residual", "qdta_adjoint_record",
+    "qdta_model_forward", "qdta_model_backward", "qdta_fw_begin", "qdta_fw_step",
     "qdta_profile_enable", "qdta_profile_read", "qdta_autotune",
 ]
 PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
@@ -103,6 +104,9 @@ def lib():
         L.qdta_advance_interval.argtypes = [vp, vp]
         L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64)]
         L.qdta_set_residual.argtypes = [vp, i32, i64, vp, vp, vp]
+        L.qdta_adjoint_record.argtypes = [vp, vp]
+        L.qdta_model_forward.argtypes = [vp, vp, vp, vp, vp]
+        L.qdta_model_backward.argtypes = [vp, vp, vp, vp]
         L.qdta_fw_begin.argtypes = [vp, vp]
         L.qdta_fw_step.argtypes = [vp, vp, vp, C.POINTER(i32)]
         L.qdta_profile_enable.argtypes = [vp, i32]
@@ -142,7 +146,7 @@ def _check_tensor(t, dtype, numel, name):
     import torch
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a device tensor")
-    if t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+    if t.dtype != getattr(torch, dtype) or not t.is_contiguous() or t.numel() < numel:
         raise ValueError(f"{name}: need contiguous {dtype} with >= {numel} elements")
 
 
@@ -292,6 +296,24 @@ class Context:
         self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), _ptr(o), _ptr(d), _ptr(w), C.byref(done)))
         return o, d, w, done.value
 
+    def adjoint_record(self, opts):
+        return self._rc(lib().qdta_adjoint_record(self._h, C.byref(opts)))
+
+    def model_forward(self, opts, d, cap, f_out):
+        li = self.layout()
+        _check_tensor(d, "float64", li.total_legs, "d")
+        if cap is not None:
+            _check_tensor(cap, "float32", li.total_links, "cap")
+        _check_tensor(f_out, "float64", li.total_links, "f_out")
+        return self._rc(lib().qdta_model_forward(self._h, C.byref(opts), _ptr(d), _ptr(cap), _ptr(f_out)))
+
+    def model_backward(self, fbar, dbar, capbar):
+        li = self.layout()
+        _check_tensor(fbar, "float64", li.total_links, "fbar")
+        _check_tensor(dbar, "float64", li.total_legs, "dbar")
+        _check_tensor(capbar, "float64", li.total_links, "capbar")
+        return self._rc(lib().qdta_model_backward(self._h, _ptr(fbar), _ptr(dbar), _ptr(capbar)))
+
     def set_residual(self, inst, orig, dest, w_fx):
         o, d, w = _np(orig, np.int32), _np(dest, np.int32), _np(w_fx, np.int64)
         if not (len(o) == len(d) == len(w)):
@@ -301,3 +323,45 @@ class Context:
 
 def kappa(dt_s: float) -> float:
     return 3600.0 / dt_s if math.isfinite(dt_s) else 1.0
+
+
+def _frozen_path_flows_class():
+    import torch
+
+    class FrozenPathFlows(torch.autograd.Function):
+        """f = M(d, C): the link flows (veh) of a solved interval's Frank-Wolfe
+        updates replayed on their frozen paths (qdta_model_forward), with the
+        reverse pass of qdta_model_backward.  Needs Context.adjoint_record
+        after the solve; the backward belongs to the most recent forward of
+        that context."""
+
+        @staticmethod
+        def forward(ctx, qctx, opts, d, cap):
+            li = qctx.layout()
+            f = torch.empty(li.total_links, dtype=torch.float64, device=d.device)
+            qctx.model_forward(opts, d.detach().contiguous(), None if cap is None else cap.detach().contiguous(), f)
+            ctx.qctx = qctx
+            ctx.cap_dtype = None if cap is None else cap.dtype
+            return f
+
+        @staticmethod
+        def backward(ctx, fbar):
+            qctx = ctx.qctx
+            li = qctx.layout()
+            dbar = torch.empty(li.total_legs, dtype=torch.float64, device=fbar.device)
+            capbar = torch.empty(li.total_links, dtype=torch.float64, device=fbar.device)
+            qctx.model_backward(fbar.to(torch.float64).contiguous(), dbar, capbar)
+            return None, None, dbar, (None if ctx.cap_dtype is None else capbar.to(ctx.cap_dtype))
+
+    return FrozenPathFlows
+
+
+_FPF = None
+
+
+def frozen_path_flows(qctx, opts, d, cap=None):
+    """Differentiable link flows of the frozen-path model (see FrozenPathFlows)."""
+    global _FPF
+    if _FPF is None:
+        _FPF = _frozen_path_flows_class()
+    return _FPF.apply(qctx, opts, d, cap)

@@ -690,3 +690,162 @@ def test_sssp_shapes_identical(torch_dev, q, orc, shape, waves):
         assert np.array_equal(host(yy), y)
     yo, so, _ = orc.aon(w.net, cost, o, d, wfx, 900.0, 1)
     assert np.array_equal(y, yo)
+
+
+# ---------------------------------------------------------------------------
+# Derivatives of the frozen-path model (OD calibration)
+# ---------------------------------------------------------------------------
+def _adj_case(name):
+    if name == "grid":
+        w = synth.config1()
+        return w.net, w.demand, 5
+    if name == "grid_trunc":
+        w = synth.config1()
+        rng = np.random.default_rng(5)
+        sel = rng.random(w.demand.P) < 0.35
+        dem = synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] * 0.5, 1800.0)
+        return w.net, dem, 4
+    # 1/20-scale metro network, a morning interval with doubled trips and a
+    # 30-minute horizon (congested, truncated, step sizes inside (0, 1))
+    w = synth.config3_day(0.05)
+    x = w.demand[34]
+    return w.net, synth.demand.Demand(x.orig, x.dest, x.trips * 2.0, 1800.0), 3
+
+
+def _adj_setup(q, orc, net, dem, iters):
+    from oracle import adjoint as adj
+    ctx = q.Context()
+    ctx.add(net)
+    ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
+    opts = q.default_opts(fixed_iters=iters, keep_history=1)
+    ctx.solve(opts)
+    ctx.adjoint_record(opts)
+    o, d, wfx = ctx.legs()
+    res = orc.fw_solve(net, o, d, wfx, dt_s=dem.dt_s, fixed_iters=iters, keep_history=True)
+    pl = adj.frozen_paths(net, o, d, wfx, res.hist_cost, dem.dt_s)
+    return ctx, opts, (o, d, wfx), res, pl
+
+
+def _perturbed(net, wfx, seed):
+    rng = np.random.default_rng(seed)
+    d2 = (wfx / FX) * (1.0 + 0.3 * rng.uniform(-1.0, 1.0, wfx.shape[0]))
+    cap2 = (net.cap.astype(np.float64) * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, net.m))).astype(np.float32)
+    return d2, cap2
+
+
+@pytest.mark.parametrize("case", ["grid", "grid_trunc", "metro_scaled"])
+def test_model_forward_bit_exact(torch_dev, q, orc, case):
+    """The frozen-path replay at the solve's own demand gives the solve's
+    flows; at another demand and other capacities it equals the oracle's
+    contract replay bit for bit."""
+    from oracle import adjoint as adj
+    torch = torch_dev
+    net, dem, iters = _adj_case(case)
+    ctx, opts, (o, d, wfx), res, pl = _adj_setup(q, orc, net, dem, iters)
+    try:
+        f_solve = torch.empty(net.m, dtype=torch.int64, device="cuda")
+        ctx.get_flows(f_solve)
+        fo = torch.empty(net.m, dtype=torch.float64, device="cuda")
+        ctx.model_forward(opts, dev(torch, wfx / FX), None, fo)
+        assert np.array_equal(host(fo), host(f_solve) / FX)
+        assert np.array_equal(host(fo), res.f / FX)
+        d2, cap2 = _perturbed(net, wfx, 3)
+        ctx.model_forward(opts, dev(torch, d2), dev(torch, cap2), fo)
+        f2, st2 = adj.forward_contract(pl, net.m, d2, net.fftt, cap2, 0.15, 4, dem.dt_s)
+        assert np.array_equal(host(fo) * FX, f2.astype(np.float64))
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("case", ["grid", "grid_trunc", "metro_scaled"])
+def test_model_backward_matches_oracle(torch_dev, q, orc, case):
+    """Reverse pass at a perturbed demand and capacities: dL/dd per leg and
+    dL/dC per link against the oracle's FP64 reverse pass on the same
+    (bit-identical) iterates.  Only the order of the FP64 reductions over the
+    links differs: agreement to 1e-9 of the largest component."""
+    from oracle import adjoint as adj
+    torch = torch_dev
+    net, dem, iters = _adj_case(case)
+    ctx, opts, (o, d, wfx), res, pl = _adj_setup(q, orc, net, dem, iters)
+    try:
+        d2, cap2 = _perturbed(net, wfx, 4)
+        fo = torch.empty(net.m, dtype=torch.float64, device="cuda")
+        ctx.model_forward(opts, dev(torch, d2), dev(torch, cap2), fo)
+        f2, st2 = adj.forward_contract(pl, net.m, d2, net.fftt, cap2, 0.15, 4, dem.dt_s)
+        assert sum(0.0 < s[2] < 1.0 for s in st2[1:]) >= 1
+        rng = np.random.default_rng(8)
+        fbar = np.where(rng.random(net.m) < 0.2, rng.standard_normal(net.m), 0.0)
+        dbar = torch.empty(len(o), dtype=torch.float64, device="cuda")
+        capbar = torch.empty(net.m, dtype=torch.float64, device="cuda")
+        ctx.model_backward(dev(torch, fbar), dbar, capbar)
+        rd, rc = adj.backward(st2, fbar, pl, net.fftt, cap2, 0.15, 4, dem.dt_s)
+        gd, gc = host(dbar), host(capbar)
+        assert np.max(np.abs(gd - rd)) <= 1e-9 * np.max(np.abs(rd))
+        assert np.max(np.abs(gc - rc)) <= 1e-9 * np.max(np.abs(rc))
+        assert np.max(np.abs(rc)) > 0
+    finally:
+        ctx.close()
+
+
+def test_model_autograd_function(torch_dev, q, orc):
+    """torch.autograd through the frozen-path model: the squared count error
+    on 10% of the links, gradients in the demand (float64) and the
+    capacities (float32) against the oracle's reverse pass."""
+    from oracle import adjoint as adj
+    torch = torch_dev
+    net, dem, iters = _adj_case("grid_trunc")
+    ctx, opts, (o, d, wfx), res, pl = _adj_setup(q, orc, net, dem, iters)
+    try:
+        d2, cap2 = _perturbed(net, wfx, 6)
+        rng = np.random.default_rng(9)
+        obs = rng.random(net.m) < 0.1
+        target = res.f / FX * (1.0 + 0.1 * rng.standard_normal(net.m))
+        dt = dev(torch, d2).requires_grad_(True)
+        ct = dev(torch, cap2).requires_grad_(True)
+        f = q.frozen_path_flows(ctx, opts, dt, ct)
+        m_obs = dev(torch, obs)
+        loss = (((f - dev(torch, target)) ** 2) * m_obs).sum()
+        loss.backward()
+        f2, st2 = adj.forward_contract(pl, net.m, d2, net.fftt, cap2, 0.15, 4, dem.dt_s)
+        fbar = np.where(obs, 2.0 * (f2 / FX - target), 0.0)
+        rd, rc = adj.backward(st2, fbar, pl, net.fftt, cap2, 0.15, 4, dem.dt_s)
+        assert np.max(np.abs(host(dt.grad) - rd)) <= 1e-9 * np.max(np.abs(rd))
+        assert ct.grad.dtype == torch.float32
+        assert np.allclose(host(ct.grad), rc.astype(np.float32), rtol=1e-6, atol=1e-6 * np.max(np.abs(rc)))
+    finally:
+        ctx.close()
+
+
+def test_model_needs_record_for_the_current_solve(torch_dev, q):
+    torch = torch_dev
+    w = synth.config1()
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_demand(0, w.demand.orig, w.demand.dest, w.demand.trips, w.demand.dt_s)
+        opts = q.default_opts(fixed_iters=2, keep_history=1)
+        P = ctx.layout().total_legs
+        d = torch.ones(P, dtype=torch.float64, device="cuda")
+        f = torch.empty(w.net.m, dtype=torch.float64, device="cuda")
+        ctx.solve(opts)
+        with pytest.raises(q.QdtaError) as e:
+            ctx.model_forward(opts, d, None, f)
+        assert e.value.code == q.ESTATE
+        with pytest.raises(q.QdtaError) as e:
+            ctx.adjoint_record(q.default_opts(fixed_iters=2))
+        assert e.value.code == q.ESTATE
+        ctx.adjoint_record(opts)
+        ctx.model_forward(opts, d, None, f)
+        ctx.solve(opts)                             # a new solve invalidates the record
+        with pytest.raises(q.QdtaError) as e:
+            ctx.model_forward(opts, d, None, f)
+        assert e.value.code == q.ESTATE
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.add(w.net)
+        for i in range(2):
+            ctx.set_demand(i, w.demand.orig, w.demand.dest, w.demand.trips, w.demand.dt_s)
+        opts = q.default_opts(fixed_iters=1, keep_history=1)
+        ctx.solve(opts)
+        with pytest.raises(q.QdtaError) as e:
+            ctx.adjoint_record(opts)
+        assert e.value.code == q.ESTATE
