@@ -269,6 +269,116 @@ def mode_day(args, torch, qdta):
                       "split_s": {k: round(v, 3) for k, v in split.items()}}), flush=True)
 
 
+def mode_calib(args, torch, qdta):
+    """OD calibration against link counts at the config-3 peak interval (the
+    derivative pattern; not in the paper).  The interval is solved (FW to
+    relative gap 1e-4, at most --calib-iters updates) and its iterations are
+    frozen (qdta_adjoint_record).  Synthetic counts: the solved flows on 2% of
+    the links with 10% Gaussian noise.  The demand starts from a lognormal
+    perturbation of the truth; Adam runs --calib-steps steps on the squared
+    count error, each one frozen-path forward replay and one reverse pass
+    (the adjoint kernels) through torch.autograd.  Central differences
+    (h = 2^-10 veh, about 1e-3 and a whole number of fixed-point units) on a
+    few legs check the gradient at full size.  --calib-dt replaces the
+    interval's 900 s horizon (0 keeps it; inf gives the static assignment of
+    the same demand, whose step sizes stay inside (0, 1))."""
+    import synth
+    w = synth.config3()
+    net, dem = w.net, w.demand
+    stream = torch.cuda.current_stream()
+    ctx = qdta.Context(0, stream)
+    ctx.add(net)
+    dt_s = args.calib_dt if args.calib_dt else dem.dt_s
+    ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dt_s)
+    opts = qdta.default_opts(alpha=w.alpha, beta=w.beta, tol=1e-4, max_iter=args.calib_iters, keep_history=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rc = ctx.solve(opts)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    log(f"solve (dt {dt_s:g} s): {st[0]['iters']} updates, gap {st[0]['gap']:.3e}, stopped_by "
+        f"{st[0]['stopped_by']}, {t_solve:.2f} s")
+    t0 = time.perf_counter()
+    ctx.adjoint_record(opts)
+    t_rec = time.perf_counter() - t0
+    log(f"paths recorded for {st[0]['iters'] + 1} iterates in {t_rec:.2f} s")
+    o, d, wfx = ctx.legs()
+    m, P = net.m, len(o)
+    d_true = torch.tensor(wfx / FX, dtype=torch.float64, device="cuda")
+    f_true = torch.empty(m, dtype=torch.float64, device="cuda")
+    ctx.model_forward(opts, d_true, None, f_true)
+    rng = np.random.default_rng(2104129115)
+    obs = torch.tensor(np.sort(rng.choice(m, int(0.02 * m), replace=False)), device="cuda")
+    counts = f_true[obs] * torch.tensor(1.0 + 0.1 * rng.standard_normal(obs.numel()), device="cuda")
+    d_start = d_true * torch.tensor(np.exp(0.5 * rng.standard_normal(P)), device="cuda")
+    dp = d_start.clone().requires_grad_(True)
+    cap = torch.tensor(net.cap, device="cuda").requires_grad_(True)
+    optim = torch.optim.Adam([dp], lr=args.calib_lr)
+
+    def loss_of(f):
+        return ((f[obs] - counts) ** 2).sum()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    losses, fwd_ms, bwd_ms = [], 0.0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.calib_steps):
+        optim.zero_grad()
+        ev[0].record()
+        f = qdta.frozen_path_flows(ctx, opts, dp, cap)
+        loss = loss_of(f)
+        ev[1].record()
+        loss.backward()
+        ev[2].record()
+        optim.step()
+        with torch.no_grad():
+            dp.clamp_(min=0.0)
+        ev[2].synchronize()
+        fwd_ms += ev[0].elapsed_time(ev[1])
+        bwd_ms += ev[1].elapsed_time(ev[2])
+        losses.append(float(loss))
+        if k % 20 == 0 or k == args.calib_steps - 1:
+            log(f"adam step {k}: loss {losses[-1]:.6e}")
+    torch.cuda.synchronize()
+    t_adam = time.perf_counter() - t0
+    n = max(args.calib_steps, 1)
+    gcap = float(cap.grad.abs().max()) if cap.grad is not None else 0.0
+    # central differences of the full-size model at the final demand
+    dfin = dp.detach().clone()
+    fo = torch.empty(m, dtype=torch.float64, device="cuda")
+
+    def loss_at(dv):
+        ctx.model_forward(opts, dv, None, fo)
+        return float(loss_of(fo))
+
+    g = torch.empty(P, dtype=torch.float64, device="cuda")
+    capbar = torch.empty(m, dtype=torch.float64, device="cuda")
+    ctx.model_forward(opts, dfin, None, fo)
+    fbar = torch.zeros(m, dtype=torch.float64, device="cuda")
+    fbar[obs] = 2.0 * (fo[obs] - counts)
+    ctx.model_backward(fbar, g, capbar)
+    gh = g.cpu().numpy()
+    fd_err = []
+    for l in np.argsort(-np.abs(gh))[:4]:
+        h = 2.0 ** -10
+        e = torch.zeros(P, dtype=torch.float64, device="cuda")
+        e[int(l)] = h
+        fd = (loss_at(dfin + e) - loss_at(dfin - e)) / (2 * h)
+        fd_err.append(abs(fd - gh[l]) / max(abs(gh[l]), 1e-300))
+        log(f"leg {int(l)}: adjoint {gh[l]:.6e}, central difference {fd:.6e}")
+    dt_h = d_true.cpu().numpy()
+    out = {"mode": "calib", "workload": f"config3 peak interval: {net.n} nodes, {m} links, {P} legs, dt {dt_s:g} s",
+           "observed_links": int(obs.numel()), "fw_updates": st[0]["iters"], "solve_s": t_solve, "record_s": t_rec,
+           "adam_steps": args.calib_steps, "lr": args.calib_lr, "step_ms": t_adam / n * 1e3,
+           "forward_ms": fwd_ms / n, "backward_ms": bwd_ms / n, "loss_first": losses[0] if losses else None,
+           "loss_last": losses[-1] if losses else None,
+           "demand_rmse_start": float(np.sqrt(np.mean((d_start.cpu().numpy() - dt_h) ** 2))),
+           "demand_rmse_end": float(np.sqrt(np.mean((dfin.cpu().numpy() - dt_h) ** 2))),
+           "cap_grad_max_abs": gcap, "fd_rel_err_max": max(fd_err) if fd_err else None}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,9 +393,15 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (MiB) once, for counter calibration")
     ap.add_argument("--no-autotune", action="store_true", help="skip the kernel-shape / bucket-width autotuner")
-    ap.add_argument("--mode", default="aon", choices=["aon", "plain", "batch", "day"],
+    ap.add_argument("--mode", default="aon", choices=["aon", "plain", "batch", "day", "calib"],
                     help="aon: the headline AON/s line; plain: batched vs per-destination launches (config 2); "
-                         "batch: 64 uneven instances together vs one after another (config 4); day: full-day QDTA")
+                         "batch: 64 uneven instances together vs one after another (config 4); day: full-day QDTA; "
+                         "calib: OD calibration against link counts (Adam through the adjoint)")
+    ap.add_argument("--calib-steps", type=int, default=200, help="calib mode: Adam steps")
+    ap.add_argument("--calib-iters", type=int, default=40, help="calib mode: cap on the solve's FW updates")
+    ap.add_argument("--calib-lr", type=float, default=0.02, help="calib mode: Adam learning rate (veh per leg)")
+    ap.add_argument("--calib-dt", type=float, default=0.0,
+                    help="calib mode: horizon in s (0: the interval's 900 s; inf: static assignment)")
     ap.add_argument("--scale", type=float, default=1.0, help="day mode: network/demand scale (1 = 1.0M links)")
     ap.add_argument("--intervals", type=int, default=96, help="day mode: number of 15-min intervals")
     ap.add_argument("--profile-day", action="store_true", help="day mode: per-phase event timing (direct launches)")
@@ -301,7 +417,7 @@ def main():
     from paper_2104_12911_amd import qdta
 
     if args.mode != "aon":
-        {"plain": mode_plain, "batch": mode_batch, "day": mode_day}[args.mode](args, torch, qdta)
+        {"plain": mode_plain, "batch": mode_batch, "day": mode_day, "calib": mode_calib}[args.mode](args, torch, qdta)
         return
 
     log(f"generating {args.workload}")
