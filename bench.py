@@ -223,12 +223,13 @@ def mode_day(args, torch, qdta):
     ctx = qdta.Context(0, stream)
     ctx.add(net)
     stop = qdta.STOP_OBJ if args.stop == "obj" else qdta.STOP_GAP
+    ls_mode = {"ksection": qdta.LS_KSECTION, "qn": qdta.LS_QN, "msa": qdta.LS_MSA}[args.ls]
     opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1,
                              launch_form=1 if args.profile_day else 0, tree_waves=args.tree_waves,
-                             waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale)
+                             waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale, ls_mode=ls_mode)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, tot_trips, carried = [], 0.0, 0
+    iters, seg_s, tot_trips, carried = [], [], 0.0, 0
     split = {"set_demand": 0.0, "solve": 0.0, "advance": 0.0, "residual_out": 0.0}
     if args.profile_day:
         ctx.profile(True)
@@ -240,6 +241,7 @@ def mode_day(args, torch, qdta):
         tb = time.perf_counter()
         if legs == 0:
             iters.append(0)
+            seg_s.append(0.0)
             continue
         st, rc = ctx.solve(opts)
         torch.cuda.synchronize()
@@ -252,6 +254,7 @@ def mode_day(args, torch, qdta):
         for k, v in zip(split, (tb - ta, tc - tb, td - tc, te - td)):
             split[k] += v
         iters.append(st[0]["iters"])
+        seg_s.append(te - ta)
         carried = int(rw.sum())
         log(f"interval {i}: legs {legs} iters {st[0]['iters']} gap {st[0]['gap']:.2e} "
             f"stop {st[0]['stopped_by']} residual legs {ro.size} ({carried / FX:.0f} trips); "
@@ -264,9 +267,10 @@ def mode_day(args, torch, qdta):
     ctx.close()
     print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
-                      "stop_rule": args.stop, "tree_waves": opts.tree_waves or 4,
+                      "stop_rule": args.stop, "line_search": args.ls, "tree_waves": opts.tree_waves or 4,
                       "delta_scale": opts.delta_scale or 10.0, "left_after_last_trips": carried / FX,
-                      "split_s": {k: round(v, 3) for k, v in split.items()}}), flush=True)
+                      "split_s": {k: round(v, 3) for k, v in split.items()},
+                      "iters_per_interval": iters, "seconds_per_interval": [round(x, 3) for x in seg_s]}), flush=True)
 
 
 def mode_calib(args, torch, qdta):
@@ -407,6 +411,8 @@ def main():
     ap.add_argument("--profile-day", action="store_true", help="day mode: per-phase event timing (direct launches)")
     ap.add_argument("--stop", default="obj", choices=["obj", "gap"],
                     help="day mode: stop rule, objective change (Eq. 7) or relative gap, both at 1e-4")
+    ap.add_argument("--ls", default="ksection", choices=["ksection", "qn", "msa"],
+                    help="day mode: step rule (K-section line search, quasi-Newton of Alg. 8, or MSA)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
