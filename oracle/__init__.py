@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(_HERE, "libqdta_oracle.so")
 RULE_NONE, RULE_CEIL, RULE_FLOOR = 0, 1, 2
 LS_KSECTION, LS_QN, LS_MSA = 0, 1, 2
 STOP_GAP, STOP_OBJ = 0, 1
+OBJ_UE, OBJ_SO = 0, 1
 WARN_ABSORB = 1
 FX = 1 << 20
 SUM_Q = 1 << 16
@@ -38,7 +39,8 @@ def build(force: bool = True) -> str:
 
 class _LsOpts(C.Structure):
     _fields_ = [("ls_mode", C.c_int32), ("K", C.c_int32), ("passes", C.c_int32),
-                ("max_ls", C.c_int32), ("T1", C.c_double), ("T2", C.c_double), ("dx", C.c_double)]
+                ("max_ls", C.c_int32), ("T1", C.c_double), ("T2", C.c_double), ("dx", C.c_double),
+                ("objective", C.c_int32)]
 
 
 class _LsInfo(C.Structure):
@@ -111,13 +113,16 @@ def kappa(dt_s: float) -> float:
     return 3600.0 / dt_s if math.isfinite(dt_s) else 1.0
 
 
-def bpr(f_fx, c0, cap, alpha, beta, dt_s):
+def bpr(f_fx, c0, cap, alpha, beta, dt_s, marginal=False):
+    """BPR costs (Eq. 1), or with `marginal` the system optimum's marginal
+    costs c + F dc/dF."""
     f_fx, c0, cap = _i64(f_fx), _f32(c0), _f32(cap)
     out = np.empty(c0.shape[0], dtype=np.float32)
     L = lib()
-    L.orc_bpr.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
-                          C.c_double, C.c_void_p]
-    rc = L.orc_bpr(c0.shape[0], _p(f_fx), _p(c0), _p(cap), alpha, beta, kappa(dt_s), _p(out))
+    L.orc_bpr_obj.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                              C.c_double, C.c_int32, C.c_void_p]
+    rc = L.orc_bpr_obj(c0.shape[0], _p(f_fx), _p(c0), _p(cap), alpha, beta, kappa(dt_s), int(bool(marginal)),
+                       _p(out))
     return out, rc
 
 
@@ -159,21 +164,21 @@ def aon(net, cost, orig, dest, d_fx, dt_s, rule=RULE_CEIL, nthreads=0):
     return y, stop, rc
 
 
-def ls_eval(f, y, c0, cap, alpha_b, beta, dt_s, alphas):
+def ls_eval(f, y, c0, cap, alpha_b, beta, dt_s, alphas, objective=0):
     f, y, c0, cap, alphas = _i64(f), _i64(y), _f32(c0), _f32(cap), _f64(alphas)
     K = alphas.shape[0]
     Cs = np.zeros(2 * K, dtype=np.int64)
     Ds = np.zeros(2 * K, dtype=np.int64)
     L = lib()
     L.orc_ls_eval.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
-                              C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+                              C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
     rc = L.orc_ls_eval(f.shape[0], _p(f), _p(y), _p(c0), _p(cap), alpha_b, beta, kappa(dt_s), K,
-                       _p(alphas), _p(Cs), _p(Ds))
+                       _p(alphas), _p(Cs), _p(Ds), objective)
     return [i128(Cs[2 * k:2 * k + 2]) for k in range(K)], [i128(Ds[2 * k:2 * k + 2]) for k in range(K)], rc
 
 
-def ls_options(ls_mode=LS_KSECTION, K=32, passes=3, max_ls=20, T1=1e-4, T2=1e-4, dx=1e-4):
-    return _LsOpts(ls_mode, K, passes, max_ls, T1, T2, dx)
+def ls_options(ls_mode=LS_KSECTION, K=32, passes=3, max_ls=20, T1=1e-4, T2=1e-4, dx=1e-4, objective=OBJ_UE):
+    return _LsOpts(ls_mode, K, passes, max_ls, T1, T2, dx, objective)
 
 
 def line_search(f, y, c0, cap, alpha_b, beta, dt_s, j, **kw):

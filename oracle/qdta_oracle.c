@@ -55,6 +55,9 @@ typedef __int128 i128;
 #define ORC_EOVF (-5)
 #define ORC_WARN_ABSORB 1
 
+#define OBJ_UE 0   /* user equilibrium: Beckmann objective (Eq. 6), BPR costs route */
+#define OBJ_SO 1   /* system optimum: total travel time, marginal costs route */
+
 #define RULE_NONE 0
 #define RULE_CEIL 1
 #define RULE_FLOOR 2
@@ -107,25 +110,34 @@ double orc_i128_to_double(const int64_t *limbs) { return (double)get128(limbs); 
 double orc_kappa(double dt_s) { return isfinite(dt_s) ? 3600.0 / dt_s : 1.0; }
 
 /* c_a = c0_a * (1 + alpha * (kappa F_a / C_a)^beta), FP64, no FMA, power by
- * left-to-right repeated multiplication, rounded once to FP32. */
-static double bpr64(double F, float c0, float cap, double alpha, int beta, double kappa) {
+ * left-to-right repeated multiplication, rounded once to FP32.  With
+ * `marginal`, the marginal cost d(F c_a)/dF = c0_a (1 + (alpha (beta+1)) p)
+ * that routes the system optimum (total travel time; the second of
+ * Wardrop's principles, section 3). */
+static double bpr64(double F, float c0, float cap, double alpha, int beta, double kappa, int marginal) {
     double r = (F * kappa) / (double)cap;
     double p = r;
     for (int k = 1; k < beta; ++k) p = p * r;
-    return (double)c0 * (1.0 + alpha * p);
+    double g = marginal ? alpha * (double)(beta + 1) : alpha;
+    return (double)c0 * (1.0 + g * p);
 }
 
-int orc_bpr(int32_t m, const int64_t *f_fx, const float *c0, const float *cap, double alpha,
-            int32_t beta, double kappa, float *c_out) {
+int orc_bpr_obj(int32_t m, const int64_t *f_fx, const float *c0, const float *cap, double alpha,
+                int32_t beta, double kappa, int32_t marginal, float *c_out) {
     if (m < 0 || beta < 1) return ORC_EARG;
     int bad = 0;
     for (int32_t a = 0; a < m; ++a) {
-        double c = bpr64((double)f_fx[a] * FX_INV, c0[a], cap[a], alpha, beta, kappa);
+        double c = bpr64((double)f_fx[a] * FX_INV, c0[a], cap[a], alpha, beta, kappa, marginal);
         float c32 = (float)c;
         if (!isfinite(c32)) bad = 1;
         c_out[a] = c32;
     }
     return bad ? ORC_EOVF : ORC_OK;
+}
+
+int orc_bpr(int32_t m, const int64_t *f_fx, const float *c0, const float *cap, double alpha,
+            int32_t beta, double kappa, float *c_out) {
+    return orc_bpr_obj(m, f_fx, c0, cap, alpha, beta, kappa, 0, c_out);
 }
 
 /* Exact sum over links of Q(c_a * x_a * 2^-20): S_cf with x = f, S_cy with x = y. */
@@ -363,9 +375,10 @@ static int effective_rule(double dt_s, int rule) { return isfinite(dt_s) ? rule 
  * truncated, demand added to each loaded link.  y (int64[m]) is overwritten,
  * stop (int32[P], may be NULL) receives the stop node of each leg (q when it
  * completes, -1 when skipped).  Returns 0, ORC_WARN_ABSORB or an error. */
-int orc_aon(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
-            int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
-            double dt_s, int32_t rule, int64_t *y, int32_t *stop, int32_t nthreads) {
+int orc_aon_t(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
+              const float *tcost, int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
+              double dt_s, int32_t rule, int64_t *y, int32_t *stop, int32_t nthreads) {
+    if (!tcost) tcost = cost;
     if (orc_check_csr(n, m, row_ptr, col)) return ORC_ECSR;
     for (int32_t p = 0; p < P; ++p)
         if (orig[p] < 0 || orig[p] >= n || dest[p] < 0 || dest[p] >= n || d_fx[p] < 0) return ORC_EARG;
@@ -406,7 +419,7 @@ int orc_aon(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, co
                 if (d_fx[p] <= 0 || orig[p] == q) { if (stop) stop[p] = -1; continue; }
                 if (!isfinite(D[orig[p]])) { unreach = 1; if (stop) stop[p] = -1; continue; }
                 addctx ac = {y, d_fx[p]};
-                int32_t s = walk_leg(col, succ, cost, orig[p], q, dt32, eff, add_link, &ac);
+                int32_t s = walk_leg(col, succ, tcost, orig[p], q, dt32, eff, add_link, &ac);
                 if (stop) stop[p] = s;
             }
         }
@@ -416,6 +429,13 @@ int orc_aon(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, co
     graph_free(&g);
     if (unreach) return ORC_EUNREACH;
     return absorb ? ORC_WARN_ABSORB : ORC_OK;
+}
+
+/* The trees' own costs clock the truncation (user equilibrium). */
+int orc_aon(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
+            int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
+            double dt_s, int32_t rule, int64_t *y, int32_t *stop, int32_t nthreads) {
+    return orc_aon_t(n, m, row_ptr, col, cost, NULL, P, orig, dest, d_fx, dt_s, rule, y, stop, nthreads);
 }
 
 /* Truncated paths (the link incidence of Eq. 5 under one set of trees): for
@@ -494,13 +514,21 @@ int orc_paths(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
  *   obj = int_0^v c0 (1 + a (kappa s / C)^b) ds = c0 (v + a v p / (b+1)), p = (kappa v / C)^b
  *   der = (y - f) * c(v)          (d obj / d alpha)                         */
 static void ls_terms(double F, double Y, float c0, float cap, double ab, int beta, double kappa,
-                     double alpha, double *obj, double *der) {
+                     double alpha, int so, double *obj, double *der) {
     double t = Y - F;
     double v = F + alpha * t;
     double r = (v * kappa) / (double)cap;
     double p = r;
     for (int k = 1; k < beta; ++k) p = p * r;
     double cost = (double)c0 * (1.0 + ab * p);
+    if (so) {
+        /* system optimum: total travel time v c(v) and its derivative
+         * t (c + v c') = t c0 (1 + (ab (beta+1)) p) */
+        double mc = (double)c0 * (1.0 + (ab * (double)(beta + 1)) * p);
+        *obj = v * cost;
+        *der = t * mc;
+        return;
+    }
     double g = ab * v;
     g = g * p;
     g = g / (double)(beta + 1);
@@ -513,14 +541,14 @@ static void ls_terms(double F, double Y, float c0, float cap, double ab, int bet
  * Cs, Ds: int64[2K] (low, high limb per k). */
 int orc_ls_eval(int32_t m, const int64_t *f, const int64_t *y, const float *c0, const float *cap,
                 double ab, int32_t beta, double kappa, int32_t K, const double *alphas,
-                int64_t *Cs, int64_t *Ds) {
+                int64_t *Cs, int64_t *Ds, int32_t objective) {
     int bad = 0;
     for (int32_t k = 0; k < K; ++k) {
         i128 sc = 0, sd = 0;
         for (int32_t a = 0; a < m; ++a) {
             double obj, der;
             ls_terms((double)f[a] * FX_INV, (double)y[a] * FX_INV, c0[a], cap[a], ab, beta, kappa,
-                     alphas[k], &obj, &der);
+                     alphas[k], objective, &obj, &der);
             sc += quant(obj, &bad);
             sd += quant(der, &bad);
         }
@@ -536,6 +564,7 @@ typedef struct {
     int32_t passes;      /* K-section passes */
     int32_t max_ls;      /* quasi-Newton iteration cap L */
     double T1, T2, dx;   /* Alg. 8 thresholds and Eq. 10 stencil */
+    int32_t objective;   /* OBJ_UE (Beckmann, Eq. 6) or OBJ_SO (total travel time) */
 } ls_opts;
 
 typedef struct {
@@ -548,7 +577,8 @@ static double q2d(i128 v) { return (double)v; }
 
 /* K-section: bracket the root of C' (C is convex in alpha) on [0,1]. */
 static int ksection(int32_t m, const int64_t *f, const int64_t *y, const float *c0, const float *cap,
-                    double ab, int32_t beta, double kappa, int32_t K, int32_t passes, ls_info *info) {
+                    double ab, int32_t beta, double kappa, int32_t K, int32_t passes, int32_t so,
+                    ls_info *info) {
     double lo = 0.0, hi = 1.0;
     double *al = (double *)malloc(sizeof(double) * (size_t)K);
     int64_t *Cs = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)K);
@@ -558,7 +588,7 @@ static int ksection(int32_t m, const int64_t *f, const int64_t *y, const float *
     double result = NAN;
     for (int32_t pass = 0; pass < passes; ++pass) {
         for (int32_t k = 0; k < K; ++k) al[k] = lo + ((hi - lo) * (double)k) / (double)(K - 1);
-        rc = orc_ls_eval(m, f, y, c0, cap, ab, beta, kappa, K, al, Cs, Ds);
+        rc = orc_ls_eval(m, f, y, c0, cap, ab, beta, kappa, K, al, Cs, Ds, so);
         info->evals++;
         if (rc) break;
         int32_t kk = -1;
@@ -590,7 +620,7 @@ static int qn_search(int32_t m, const int64_t *f, const int64_t *y, const float 
     int64_t Cs[6], Ds[6];
     for (int32_t l = 0; l < o->max_ls; ++l) {
         al[0] = alpha - o->dx; al[1] = alpha; al[2] = alpha + o->dx;
-        int rc = orc_ls_eval(m, f, y, c0, cap, ab, beta, kappa, 3, al, Cs, Ds);
+        int rc = orc_ls_eval(m, f, y, c0, cap, ab, beta, kappa, 3, al, Cs, Ds, o->objective);
         info->evals++;
         info->qn_iters++;
         if (rc) return rc;
@@ -599,7 +629,7 @@ static int qn_search(int32_t m, const int64_t *f, const int64_t *y, const float 
         double d1 = (cp - cm) / (2.0 * o->dx);
         double d2 = ((cm - 2.0 * c0v) + cp) / (o->dx * o->dx);
         if (fabs(d1) < o->T1) { info->alpha = alpha; return ORC_OK; }
-        if (!(d2 > 0.0)) return ksection(m, f, y, c0, cap, ab, beta, kappa, o->K, o->passes, info);
+        if (!(d2 > 0.0)) return ksection(m, f, y, c0, cap, ab, beta, kappa, o->K, o->passes, o->objective, info);
         double an = alpha - d1 / d2;
         if (an < 0.0) an = 0.0;
         if (an > 1.0) an = 1.0;
@@ -616,7 +646,7 @@ int orc_line_search(int32_t m, const int64_t *f, const int64_t *y, const float *
     if (o->ls_mode == LS_MSA) { info->alpha = 1.0 / ((double)j + 1.0); return ORC_OK; }
     if (o->ls_mode == LS_QN) return qn_search(m, f, y, c0, cap, ab, beta, kappa, j, o, info);
     if (o->K < 2 || o->passes < 1) return ORC_EARG;
-    return ksection(m, f, y, c0, cap, ab, beta, kappa, o->K, o->passes, info);
+    return ksection(m, f, y, c0, cap, ab, beta, kappa, o->K, o->passes, o->objective, info);
 }
 
 /* f <- f + rint(alpha * (y - f)) (Alg. 6 link-flow update). */
@@ -626,11 +656,11 @@ void orc_fw_update(int32_t m, int64_t *f, const int64_t *y, double alpha) {
 
 /* Beckmann objective of f alone (C at alpha = 0 with y = f), exact. */
 static i128 objective(int32_t m, const int64_t *f, const float *c0, const float *cap, double ab,
-                      int32_t beta, double kappa, int *bad) {
+                      int32_t beta, double kappa, int32_t so, int *bad) {
     i128 s = 0;
     for (int32_t a = 0; a < m; ++a) {
         double obj, der, F = (double)f[a] * FX_INV;
-        ls_terms(F, F, c0[a], cap[a], ab, beta, kappa, 0.0, &obj, &der);
+        ls_terms(F, F, c0[a], cap[a], ab, beta, kappa, 0.0, so, &obj, &der);
         s += quant(obj, bad);
     }
     return s;
@@ -673,23 +703,29 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
                  double *hist_alpha, float *hist_cost, double *gap_hist) {
     memset(st, 0, sizeof(*st));
     double kappa = orc_kappa(o->dt_s);
+    /* the system optimum routes by marginal costs; its trips still take the
+     * actual travel times, which clock the truncation */
+    const int so = o->ls.objective == OBJ_SO;
     float *c = (float *)malloc(sizeof(float) * (size_t)(m > 0 ? m : 1));
+    float *tc = so ? (float *)malloc(sizeof(float) * (size_t)(m > 0 ? m : 1)) : NULL;
     int64_t *y = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
     int64_t *zero = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
     int rc, bad = 0;
     int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
-    /* initial AON at free flow: BPR(0) = c0 exactly */
-    rc = orc_bpr(m, zero, c0, cap, o->alpha_b, o->beta, kappa, c);
+    /* initial AON at free flow: BPR(0) = c0 exactly (the marginal cost too) */
+    rc = orc_bpr_obj(m, zero, c0, cap, o->alpha_b, o->beta, kappa, so, c);
     if (rc < 0) goto done;
-    rc = orc_aon(n, m, row_ptr, col, c, P, orig, dest, d_fx, o->dt_s, o->rule, f, NULL, o->nthreads);
+    if (so) orc_bpr(m, zero, c0, cap, o->alpha_b, o->beta, kappa, tc);
+    rc = orc_aon_t(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, o->dt_s, o->rule, f, NULL, o->nthreads);
     if (rc < 0) goto done;
     st->absorb |= (rc == ORC_WARN_ABSORB);
     if (hist_alpha) hist_alpha[0] = 1.0;
     if (hist_cost) memcpy(hist_cost, c, sizeof(float) * (size_t)m);
     for (int32_t j = 1;; ++j) {
-        rc = orc_bpr(m, f, c0, cap, o->alpha_b, o->beta, kappa, c);
+        rc = orc_bpr_obj(m, f, c0, cap, o->alpha_b, o->beta, kappa, so, c);
         if (rc < 0) goto done;
-        rc = orc_aon(n, m, row_ptr, col, c, P, orig, dest, d_fx, o->dt_s, o->rule, y, NULL, o->nthreads);
+        if (so) orc_bpr(m, f, c0, cap, o->alpha_b, o->beta, kappa, tc);
+        rc = orc_aon_t(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, o->dt_s, o->rule, y, NULL, o->nthreads);
         if (rc < 0) goto done;
         st->absorb |= (rc == ORC_WARN_ABSORB);
         int64_t scf[2], scy[2];
@@ -709,12 +745,13 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
         st->ls_evals += li.evals;
         st->qn_iters += li.qn_iters;
         if (o->fixed_iters <= 0 && o->stop_rule == STOP_OBJ) {
-            /* Converged(f, f_new) of Eq. 7 on the Beckmann objective */
+            /* Converged(f, f_new) of Eq. 7 on the objective (Beckmann, or the total
+             * travel time of the system optimum) */
             int64_t *fn = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
             memcpy(fn, f, sizeof(int64_t) * (size_t)m);
             orc_fw_update(m, fn, y, li.alpha);
-            double b0 = q2d(objective(m, f, c0, cap, o->alpha_b, o->beta, kappa, &bad));
-            double b1 = q2d(objective(m, fn, c0, cap, o->alpha_b, o->beta, kappa, &bad));
+            double b0 = q2d(objective(m, f, c0, cap, o->alpha_b, o->beta, kappa, so, &bad));
+            double b1 = q2d(objective(m, fn, c0, cap, o->alpha_b, o->beta, kappa, so, &bad));
             free(fn);
             if (fabs((b0 - b1) / b0) < o->tol) { st->stopped_by = 2; break; }
         }
@@ -730,10 +767,10 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
         if (hist_alpha) hist_alpha[j] = li.alpha;
         if (hist_cost) memcpy(hist_cost + (size_t)j * (size_t)m, c, sizeof(float) * (size_t)m);
     }
-    st->objective = q2d(objective(m, f, c0, cap, o->alpha_b, o->beta, kappa, &bad)) / SUM_SCALE;
+    st->objective = q2d(objective(m, f, c0, cap, o->alpha_b, o->beta, kappa, so, &bad)) / SUM_SCALE;
     rc = bad ? ORC_EOVF : ORC_OK;
 done:
-    free(c); free(y); free(zero);
+    free(c); free(tc); free(y); free(zero);
     return rc;
 }
 
