@@ -67,7 +67,16 @@ extern "C" {
 #define QDTA_LS_MSA 2       /* alpha_j = 1/(j+1) */
 
 #define QDTA_STOP_GAP 0     /* relative gap (sum c f - sum c y) / sum c f below tol */
-#define QDTA_STOP_OBJ 1     /* relative change of the Beckmann objective below tol (Eq. 7) */
+#define QDTA_STOP_OBJ 1     /* relative change of the objective below tol (Eq. 7) */
+
+/* Which of Wardrop's two principles (section 3) the interval solves: the user
+ * equilibrium the paper adopts (trees by the BPR costs, Beckmann objective of
+ * Eq. 6), or the system optimum (trees by the marginal costs
+ * c + F dc/dF = c0 (1 + alpha (beta+1) (kappa F / C)^beta), objective the total
+ * travel time sum F c(F)).  In both the truncation (Eq. 2) is clocked by the
+ * travel times BPR(f), and the gap and stop rules use the routing costs. */
+#define QDTA_OBJ_UE 0
+#define QDTA_OBJ_SO 1
 
 typedef struct qdta_ctx qdta_ctx;
 
@@ -106,6 +115,7 @@ typedef struct {
     int32_t history_mib;   /* with keep_history: device memory for the iterates' labels, in MiB:
                               0 auto (the free memory less 16 GiB), < 0 none (the residual step
                               grows every tree again); never changes results */
+    int32_t objective;     /* QDTA_OBJ_UE (default) or QDTA_OBJ_SO */
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */
@@ -118,7 +128,8 @@ typedef struct {
                               3 stalled: the line search returned alpha* = 0, so f cannot change */
     int32_t status;        /* QDTA_OK or an error code for this instance */
     double gap;            /* relative gap at the returned iterate */
-    double objective;      /* Beckmann objective at the returned iterate (veh s) */
+    double objective;      /* objective at the returned iterate (veh s): Beckmann, or the total travel
+                              time under QDTA_OBJ_SO */
     double last_alpha;     /* last step size applied */
 } qdta_stats;
 
@@ -172,8 +183,9 @@ int qdta_offsets(qdta_ctx *ctx, int64_t *node_off, int64_t *link_off, int64_t *l
  * (kappa F / C)^beta)), F = f_fx[a] * 2^-20, evaluated in FP64 without fused
  * multiply-add, the power by repeated multiplication.  f_fx int64[total_links],
  * cost float[total_links] (device).  Uses opts->alpha, opts->beta and each
- * instance's dt.  Returns QDTA_EOVF (after the stream completes: this call
- * synchronises) if a cost is not finite. */
+ * instance's dt; under opts->objective = QDTA_OBJ_SO the routing costs
+ * fl32(c0 (1 + (alpha (beta+1)) p)) instead.  Returns QDTA_EOVF (after the
+ * stream completes: this call synchronises) if a cost is not finite. */
 int qdta_bpr(qdta_ctx *ctx, const qdta_opts *opts, const int64_t *f_fx, float *cost);
 
 /* A2 -- shortest-path trees (Get_shortest_path of Alg. 3) on one instance:

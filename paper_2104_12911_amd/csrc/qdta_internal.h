@@ -64,6 +64,8 @@ struct NetDev {
     const int32_t* blk_start;// [nblk] first global link of each chunk
     int32_t ninst, nblk;
     int64_t N, M;
+    int32_t objective;       // 0 user equilibrium (BPR costs route, Beckmann objective, Eq. 6);
+                             // 1 system optimum (marginal costs route, total travel time)
 };
 
 struct DemDev {
@@ -101,8 +103,11 @@ struct FlagsDev {
 hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t count);
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t count);
 
+// cost: the routing costs (marginal ones under net.objective = 1); tcost (may
+// be NULL): the travel times BPR(f) as well
 hipError_t launch_bpr(hipStream_t s, const NetDev& net, const int64_t* f, double alpha, int beta,
-                      float* cost, uint2* radj, const InstState* st, int only_active, int* err);
+                      float* cost, uint2* radj, const InstState* st, int only_active, int* err,
+                      float* tcost = nullptr);
 
 hipError_t launch_gap_sums(hipStream_t s, const NetDev& net, const float* cost, const int64_t* f,
                            const int64_t* y, long long* acc /*[ninst][2][3]*/, const InstState* st, int* err);

@@ -94,23 +94,34 @@ __device__ void wg_acc_add(i128 v, long long* acc, i128* lds) {
     __syncthreads();
 }
 
-// BPR curve (Eq. 1): c0 (1 + alpha (kappa F / C)^beta) in FP64.
-__device__ __forceinline__ double bpr64(double F, float c0, float cap, double alpha, int beta, double kappa) {
+// BPR curve (Eq. 1): c0 (1 + alpha (kappa F / C)^beta) in FP64; with
+// `marginal` the marginal cost d(F c)/dF = c0 (1 + (alpha (beta+1)) p).
+__device__ __forceinline__ double bpr64(double F, float c0, float cap, double alpha, int beta, double kappa,
+                                        int marginal = 0) {
     double r = (F * kappa) / (double)cap;
     double p = r;
     for (int k = 1; k < beta; ++k) p = p * r;
-    return (double)c0 * (1.0 + alpha * p);
+    const double g = marginal ? alpha * (double)(beta + 1) : alpha;
+    return (double)c0 * (1.0 + g * p);
 }
 
-// Beckmann term and its derivative along the FW direction at step alpha.
+// Objective term and its derivative along the FW direction at step alpha:
+// the Beckmann integral (Eq. 6), or under the system optimum the total
+// travel time v c(v) with derivative t c0 (1 + (ab (beta+1)) p).
 __device__ __forceinline__ void ls_terms(double F, double Y, float c0, float cap, double ab, int beta, double kappa,
-                                         double alpha, double& obj, double& der) {
+                                         double alpha, int so, double& obj, double& der) {
     double t = Y - F;
     double v = F + alpha * t;
     double r = (v * kappa) / (double)cap;
     double p = r;
     for (int k = 1; k < beta; ++k) p = p * r;
     double cost = (double)c0 * (1.0 + ab * p);
+    if (so) {
+        const double mc = (double)c0 * (1.0 + (ab * (double)(beta + 1)) * p);
+        obj = v * cost;
+        der = t * mc;
+        return;
+    }
     double g = ab * v;
     g = g * p;
     g = g / (double)(beta + 1);
@@ -157,7 +168,8 @@ __device__ __forceinline__ bool inst_live(const InstState* st, int i) {
 
 __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restrict__ f, double alpha, int beta,
                                              float* __restrict__ cost, uint2* __restrict__ radj,
-                                             const InstState* st, int only_active, int* err) {
+                                             const InstState* st, int only_active, int* err,
+                                             float* __restrict__ tcost) {
     const int b = blockIdx.x;
     const int inst = net.blk_inst[b];
     if (only_active && !inst_live(st, inst)) return;
@@ -166,10 +178,16 @@ __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restri
     const int a1 = min(a0 + kChunk, I.link0 + I.m);
     int bad = 0;
     for (int a = a0 + threadIdx.x; a < a1; a += kWG) {
-        double c = bpr64((double)f[a] * kFxInv, net.c0[a], net.cap[a], alpha, beta, I.kappa);
+        const double F = (double)f[a] * kFxInv;
+        double c = bpr64(F, net.c0[a], net.cap[a], alpha, beta, I.kappa, net.objective);
         float c32 = (float)c;
         if (!(c32 <= 3.4028234663852886e38f)) bad = 1;
         cost[a] = c32;
+        if (tcost) {
+            const float t32 = net.objective ? (float)bpr64(F, net.c0[a], net.cap[a], alpha, beta, I.kappa) : c32;
+            if (!(t32 <= 3.4028234663852886e38f)) bad = 1;
+            tcost[a] = t32;
+        }
         if (radj) {
             radj[net.revpos[a]].y = __float_as_uint(c32);
             net.fadj[a].y = __float_as_uint(c32);
@@ -179,10 +197,10 @@ __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restri
 }
 
 hipError_t launch_bpr(hipStream_t s, const NetDev& net, const int64_t* f, double alpha, int beta, float* cost,
-                      uint2* radj, const InstState* st, int only_active, int* err) {
+                      uint2* radj, const InstState* st, int only_active, int* err, float* tcost) {
     if (net.nblk == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bpr, dim3(net.nblk), dim3(kWG), 0, s, net, f, alpha, beta, cost, radj, st, only_active,
-                       err);
+                       err, tcost);
     return hipGetLastError();
 }
 
@@ -314,7 +332,7 @@ __global__ __launch_bounds__(kWG) void k_ls_eval(NetDev net, const int64_t* __re
         for (int a = a0 + g; a < a1; a += LPB) {
             double obj, der;
             ls_terms((double)f[a] * kFxInv, (double)y[a] * kFxInv, net.c0[a], net.cap[a], alpha_b, beta, I.kappa,
-                     alpha, obj, der);
+                     alpha, net.objective, obj, der);
             sc += quant(obj, bad);
             sd += quant(der, bad);
         }
@@ -457,8 +475,9 @@ hipError_t launch_ls_export(hipStream_t s, int ninst, const long long* ls_acc, i
     return hipGetLastError();
 }
 
-// Beckmann objective of f (slot 0) and of the would-be update f + rint(alpha
-// (y - f)) (slot 1), exact -- the Converged test of Eq. 7.
+// Objective (Beckmann, or total travel time under the system optimum) of f
+// (slot 0) and of the would-be update f + rint(alpha (y - f)) (slot 1),
+// exact -- the Converged test of Eq. 7.
 __global__ __launch_bounds__(kWG) void k_obj_pair(NetDev net, const int64_t* __restrict__ f,
                                                   const int64_t* __restrict__ y, double alpha_b, int beta,
                                                   long long* acc, const InstState* st, int use_alpha, int* err) {
@@ -476,12 +495,12 @@ __global__ __launch_bounds__(kWG) void k_obj_pair(NetDev net, const int64_t* __r
     for (int a = a0 + threadIdx.x; a < a1; a += kWG) {
         double obj, der;
         double F = (double)f[a] * kFxInv;
-        ls_terms(F, F, net.c0[a], net.cap[a], alpha_b, beta, I.kappa, 0.0, obj, der);
+        ls_terms(F, F, net.c0[a], net.cap[a], alpha_b, beta, I.kappa, 0.0, net.objective, obj, der);
         s0 += quant(obj, bad);
         if (use_alpha) {
             int64_t fn = f[a] + (int64_t)__builtin_rint(alpha * (double)(y[a] - f[a]));
             double Fn = (double)fn * kFxInv;
-            ls_terms(Fn, Fn, net.c0[a], net.cap[a], alpha_b, beta, I.kappa, 0.0, obj, der);
+            ls_terms(Fn, Fn, net.c0[a], net.cap[a], alpha_b, beta, I.kappa, 0.0, net.objective, obj, der);
             s1 += quant(obj, bad);
         }
     }

@@ -80,7 +80,7 @@ struct qdta_ctx {
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
-    DBuf<float> cost, cfin;
+    DBuf<float> cost, cfin, tcost;    // routing costs, final times, travel times (system optimum)
     DBuf<uint2> radj;             // reverse adjacency records (source node, cost)
     DBuf<uint2> fadj;             // forward link records (head node, cost)
     DBuf<InstState> st;
@@ -220,6 +220,10 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
         set_err(c, QDTA_EARG, "delta_scale must be finite and >= 0");
         return false;
     }
+    if (o->objective != QDTA_OBJ_UE && o->objective != QDTA_OBJ_SO) {
+        set_err(c, QDTA_EARG, "objective must be QDTA_OBJ_UE or QDTA_OBJ_SO");
+        return false;
+    }
     return true;
 }
 
@@ -317,6 +321,7 @@ int ensure_network(qdta_ctx* c) {
         RC(upload(c, c->fadj, fa));
     }
     RC(dalloc(c, c->cfin, c->M));
+    RC(dalloc(c, c->tcost, c->M));
     RC(dalloc(c, c->st, ni));
     RC(dalloc(c, c->acc, (size_t)ni * 6));
     RC(dalloc(c, c->ls_acc, (size_t)ni * kMaxK * 6));
@@ -335,8 +340,11 @@ int ensure_network(qdta_ctx* c) {
     return QDTA_OK;
 }
 
-NetDev net_view(qdta_ctx* c) {
+// o (may be NULL): the solve options, whose objective selects the routing
+// costs and the objective terms; NULL = user equilibrium (travel times).
+NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
     NetDev v;
+    v.objective = o ? o->objective : 0;
     v.row_ptr = c->row_ptr.p;
     v.col = c->col.p;
     v.c0 = c->c0.p;
@@ -539,8 +547,9 @@ void prof_collect(qdta_ctx* c) {
 }
 
 // One all-or-nothing assignment (A2 + A3) under `cost` (reverse records already set).
-int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop, const InstState* st,
-             bool marks = true) {
+// time_cost: the travel times that clock the truncation; NULL = `cost`.
+int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, const float* time_cost, int64_t* y, int32_t* stop,
+             const InstState* st, bool marks = true) {
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
     FlagsDev fl = flags_view(c);
@@ -561,13 +570,14 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
     if (o->launch_form == 2) {
         for (int64_t qi = 0; qi < c->Q; ++qi)
-            HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, nullptr, y, stop, st, fl, 0, nullptr, nullptr,
+            HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, time_cost, y, stop, st, fl, 0, nullptr, nullptr,
                                     nullptr, c->h_qptr[qi], c->h_qptr[qi + 1]));
     } else {
-        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, nullptr, y, stop, st, fl, 0, nullptr, nullptr,
+        HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, time_cost, y, stop, st, fl, 0, nullptr, nullptr,
                                 nullptr));
     }
-    HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, cost, y, stop, st, fl, scr_view(c),
+    HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, time_cost ? time_cost : cost, y, stop, st, fl,
+                                scr_view(c),
                                 (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
                                 nullptr, 0, nullptr, 0));
     if (marks) RC(prof_mark(c, PH_WALK, 1));
@@ -597,7 +607,7 @@ int pull_state(qdta_ctx* c) {
 // Line search of the current iteration for every live instance (A5).
 int line_search_core(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_t* y,
                      const NetDev* net_in = nullptr) {
-    NetDev net = net_in ? *net_in : net_view(c);
+    NetDev net = net_in ? *net_in : net_view(c, o);
     int ni = (int)c->inst.size();
     int* err = c->flags.p;
     int K = o->ls_mode == QDTA_LS_QN ? 3 : o->K;
@@ -979,7 +989,7 @@ int qdta_bpr(qdta_ctx* c, const qdta_opts* o, const int64_t* f, float* cost) {
     RC(ensure_network(c));
     if (c->dem_dirty) RC(ensure_demand(c, 0));   // kappa of each instance
     RC(clear_flags(c));
-    HIPCHECK(c, launch_bpr(c->stream, net_view(c), f, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
+    HIPCHECK(c, launch_bpr(c->stream, net_view(c, o), f, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
     int h[4];
     RC(read_flags(c, h));
     return flag_code(c, h);
@@ -1080,7 +1090,7 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     HIPCHECK(c, hipMemcpyAsync(c->cost.p, cost, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(c, launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p));
     if (stop) HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(stop), 0xffffffffu, c->P));
-    RC(aon_core(c, o, c->cost.p, y, stop, nullptr));
+    RC(aon_core(c, o, c->cost.p, nullptr, y, stop, nullptr));
     int h[4];
     RC(read_flags(c, h));
     prof_collect(c);
@@ -1099,7 +1109,7 @@ int qdta_ls_eval(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_
     int ni = (int)c->inst.size();
     RC(clear_flags(c));
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->ls_acc.p), 0, (int64_t)ni * K * 6));
-    HIPCHECK(c, launch_ls_eval(c->stream, net_view(c), f, y, o->alpha, o->beta, K, alphas, c->ls_acc.p, nullptr, 0,
+    HIPCHECK(c, launch_ls_eval(c->stream, net_view(c, o), f, y, o->alpha, o->beta, K, alphas, c->ls_acc.p, nullptr, 0,
                                c->flags.p));
     HIPCHECK(c, launch_ls_export(c->stream, ni, c->ls_acc.p, K, sums));
     int h[4];
@@ -1144,7 +1154,7 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solving");
     RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
-    NetDev net = net_view(c);
+    NetDev net = net_view(c, o);
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
     c->solve_id++;
@@ -1156,11 +1166,13 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     // initial AON at free flow: BPR(0) = c0 exactly (first step of Alg. 6)
     HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
     RC(prof_mark(c, PH_BPR, 0));
-    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, c->flags.p));
+    float* tc = o->objective == QDTA_OBJ_SO ? c->tcost.p : nullptr;
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, c->flags.p,
+                           tc));
     RC(prof_mark(c, PH_BPR, 1));
     c->lab_hist_ok.clear();
     if (o->keep_history) RC(plan_label_history(c, o));
-    RC(aon_core(c, o, c->cost.p, c->f.p, nullptr, c->st.p));
+    RC(aon_core(c, o, c->cost.p, tc, c->f.p, nullptr, c->st.p));
     if (o->keep_history) {
         HIPCHECK(c, hipMemcpyAsync(c->hist_cost.p, c->cost.p, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
         RC(stash_labels(c, 0));
@@ -1197,13 +1209,14 @@ void fill_stats(qdta_ctx* c, qdta_stats* hs, int worst, const int* h) {
 // unless the quasi-Newton search is selected.
 int enqueue_iteration(qdta_ctx* c, const qdta_opts* o, bool marks) {
     int ni = (int)c->inst.size();
-    NetDev net = net_view(c);
+    NetDev net = net_view(c, o);
     int* err = c->flags.p;
     const int cap_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
     if (marks) RC(prof_mark(c, PH_BPR, 0));
-    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, err));
+    float* tc = o->objective == QDTA_OBJ_SO ? c->tcost.p : nullptr;
+    HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, c->st.p, 1, err, tc));
     if (marks) RC(prof_mark(c, PH_BPR, 1));
-    RC(aon_core(c, o, c->cost.p, c->y.p, nullptr, c->st.p, marks));
+    RC(aon_core(c, o, c->cost.p, tc, c->y.p, nullptr, c->st.p, marks));
     if (marks) RC(prof_mark(c, PH_GAP, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
     HIPCHECK(c, launch_gap_sums(c->stream, net, c->cost.p, c->f.p, c->y.p, c->acc.p, c->st.p, err));
@@ -1304,7 +1317,7 @@ int fw_iteration(qdta_ctx* c, const qdta_opts* o, int* h) {
 
 int fw_finish(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs) {
     int ni = (int)c->inst.size();
-    NetDev net = net_view(c);
+    NetDev net = net_view(c, o);
     int h[4];
     // objective of the returned iterates
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->acc.p), 0, (int64_t)ni * 6));
@@ -1360,7 +1373,7 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "autotune needs the demand of every instance");
     RC(ensure_demand(c, waves_per_cu(o), 1));            // slots for either kernel form
     RC(apply_rule(c, o));
-    NetDev net = net_view(c);
+    NetDev net = net_view(c, o);
     DemDev dem = dem_view(c);
     // trial costs: BPR of the current flows when an interval was solved, else free flow
     if (!c->solved) HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
@@ -1609,6 +1622,7 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (c->inst.size() != 1) return set_err(c, QDTA_ESTATE, "the frozen-path model takes exactly one instance");
+    if (o->objective != QDTA_OBJ_UE) return set_err(c, QDTA_ESTATE, "the frozen-path model is the user equilibrium's");
     if (!c->solved || c->dem_dirty) return set_err(c, QDTA_ESTATE, "record needs a solved interval");
     if (!o->keep_history) return set_err(c, QDTA_ESTATE, "record needs keep_history during solve");
     const Instance& I = c->inst[0];

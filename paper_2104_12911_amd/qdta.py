@@ -20,6 +20,7 @@ OK, EARG, ECSR, EVAL, EUNREACH, EOVF, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, 
 WABSORB = 1
 RULE_NONE, RULE_CEIL, RULE_FLOOR = 0, 1, 2
 LS_KSECTION, LS_QN, LS_MSA = 0, 1, 2
+OBJ_UE, OBJ_SO = 0, 1
 STOP_GAP, STOP_OBJ = 0, 1
 FX = 1 << 20
 
@@ -40,7 +41,8 @@ class Opts(C.Structure):
                 ("T2", C.c_double), ("dx", C.c_double), ("stop_rule", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("sssp_shape", C.c_int32),
-                ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("history_mib", C.c_int32)]
+                ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("history_mib", C.c_int32),
+                ("objective", C.c_int32)]
 
 
 class Stats(C.Structure):

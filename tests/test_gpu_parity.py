@@ -849,3 +849,70 @@ def test_model_needs_record_for_the_current_solve(torch_dev, q):
         with pytest.raises(q.QdtaError) as e:
             ctx.adjoint_record(opts)
         assert e.value.code == q.ESTATE
+
+
+# ---------------------------------------------------------------------------
+# The system optimum (marginal-cost routing, total travel time)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dt", [float("inf"), 900.0])
+def test_bpr_marginal_bit_exact(torch_dev, q, orc, dt):
+    torch = torch_dev
+    w = synth.config2()
+    rng = np.random.default_rng(21)
+    f = rng.integers(0, 5000 * FX, w.net.m).astype(np.int64)
+    ref, _ = orc.bpr(f, w.net.fftt, w.net.cap, 0.15, 4, dt, marginal=True)
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_demand(0, [], [], [], dt)
+        c = torch.empty(w.net.m, dtype=torch.float32, device="cuda")
+        ctx.bpr(q.default_opts(objective=q.OBJ_SO), dev(torch, f), c)
+        assert np.array_equal(host(c).view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_fw_system_optimum_config1(torch_dev, q, orc, mode):
+    w = synth.config1()
+    st, f, off, (o, d, wfx), rc = _solve(torch_dev, q, [(w.net, w.demand)],
+                                         q.default_opts(fixed_iters=50, ls_mode=mode, objective=q.OBJ_SO))
+    ref = orc.fw_solve(w.net, o, d, wfx, fixed_iters=50, ls_mode=mode, objective=orc.OBJ_SO)
+    _cmp_fw(st[0], None, f, ref)
+    ue = orc.fw_solve(w.net, o, d, wfx, fixed_iters=50, ls_mode=mode)
+    assert not np.array_equal(ue.f, ref.f)
+
+
+def test_fw_system_optimum_truncated(torch_dev, q, orc):
+    """Config 2 with its 900 s horizon: trees by marginal costs, the
+    truncation clocked by the travel times, the objective stop rule."""
+    w = synth.config2()
+    opts = q.default_opts(objective=q.OBJ_SO, stop_rule=q.STOP_OBJ, tol=1e-4, max_iter=6)
+    st, f, off, (o, d, wfx), rc = _solve(torch_dev, q, [(w.net, w.demand)], opts)
+    ref = orc.fw_solve(w.net, o, d, wfx, dt_s=900.0, objective=orc.OBJ_SO, stop_rule=orc.STOP_OBJ, tol=1e-4,
+                       max_iter=6, keep_history=False)
+    _cmp_fw(st[0], None, f, ref)
+
+
+def test_day_system_optimum_chain(torch_dev, q, orc):
+    w = synth.config1()
+    rng = np.random.default_rng(41)
+    days = []
+    for frac in (0.6, 0.4, 0.5):
+        sel = rng.random(w.demand.P) < frac
+        days.append(synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] / 2, 600.0))
+    opts = q.default_opts(keep_history=1, tol=1e-3, max_iter=20, objective=q.OBJ_SO)
+    g = _day_gpu(torch_dev, q, w.net, days, opts)
+    ref, _ = orc.qdta_day(w.net, days, tol=1e-3, max_iter=20, objective=orc.OBJ_SO)
+    for a, b in zip(g, ref):
+        assert a["iters"] == b["iters"]
+        assert np.array_equal(a["f"], b["f"])
+        for x, y in zip(a["res"], b["res"]):
+            assert np.array_equal(x, y)
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_demand(0, w.demand.orig, w.demand.dest, w.demand.trips, w.demand.dt_s)
+        ctx.solve(opts)
+        with pytest.raises(q.QdtaError) as e:
+            ctx.adjoint_record(opts)
+        assert e.value.code == q.ESTATE
+        with pytest.raises(q.QdtaError) as e:
+            ctx.solve(q.default_opts(objective=2))
+        assert e.value.code == q.EARG
