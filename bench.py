@@ -226,7 +226,8 @@ def mode_day(args, torch, qdta):
     ls_mode = {"ksection": qdta.LS_KSECTION, "qn": qdta.LS_QN, "msa": qdta.LS_MSA}[args.ls]
     opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1,
                              launch_form=1 if args.profile_day else 0, tree_waves=args.tree_waves,
-                             waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale, ls_mode=ls_mode)
+                             waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale, ls_mode=ls_mode,
+                             objective=qdta.OBJ_SO if args.objective == "so" else qdta.OBJ_UE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, seg_s, tot_trips, carried = [], [], 0.0, 0
@@ -267,7 +268,8 @@ def mode_day(args, torch, qdta):
     ctx.close()
     print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
-                      "stop_rule": args.stop, "line_search": args.ls, "tree_waves": opts.tree_waves or 4,
+                      "stop_rule": args.stop, "line_search": args.ls, "objective": args.objective,
+                      "tree_waves": opts.tree_waves or 4,
                       "delta_scale": opts.delta_scale or 10.0, "left_after_last_trips": carried / FX,
                       "split_s": {k: round(v, 3) for k, v in split.items()},
                       "iters_per_interval": iters, "seconds_per_interval": [round(x, 3) for x in seg_s]}), flush=True)
@@ -411,6 +413,8 @@ def main():
     ap.add_argument("--profile-day", action="store_true", help="day mode: per-phase event timing (direct launches)")
     ap.add_argument("--stop", default="obj", choices=["obj", "gap"],
                     help="day mode: stop rule, objective change (Eq. 7) or relative gap, both at 1e-4")
+    ap.add_argument("--objective", default="ue", choices=["ue", "so"],
+                    help="day mode: user equilibrium (the paper's) or system optimum (marginal-cost routing)")
     ap.add_argument("--ls", default="ksection", choices=["ksection", "qn", "msa"],
                     help="day mode: step rule (K-section line search, quasi-Newton of Alg. 8, or MSA)")
     args = ap.parse_args()
