@@ -177,9 +177,9 @@ hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem,
 
 // frozen-path model and its reverse pass (OD calibration)
 hipError_t launch_path_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
-                            const int64_t* ptr, int32_t* links, int64_t* len, int* bad);
-hipError_t launch_path_load(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* d,
-                            int64_t* y, int* err);
+                            const int64_t* ptr, int32_t* links, int32_t* leg_of, int64_t* len, int* bad);
+hipError_t launch_path_load(hipStream_t s, int64_t total, const int32_t* links, const int32_t* leg_of,
+                            const double* d, int64_t* y, int* err);
 hipError_t launch_path_gather(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* g,
                               double* dbar, int accumulate);
 hipError_t launch_adj_step(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,

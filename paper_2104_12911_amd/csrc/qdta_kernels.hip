@@ -1705,12 +1705,13 @@ hipError_t launch_trees_out(hipStream_t s, const NetDev& net, const DemDev& dem,
 // The truncated path of every leg under one iterate's trees: the links the
 // walk of that iterate loads (same successor rule, same clock), in walk
 // order.  ptr == NULL counts them into len[l]; otherwise they are written at
-// links[ptr[l]], never past ptr[l + 1].  bad: 1 an origin cannot reach its
+// links[ptr[l]] (and the leg index at leg_of[ptr[l]]), never past ptr[l + 1].  bad: 1 an origin cannot reach its
 // destination, 2 FP32 absorption (the tie fallback's paths are not
 // recorded), 4 a path longer than counted.
 __global__ __launch_bounds__(kWG) void k_path_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                                    const int64_t* __restrict__ ptr, int32_t* __restrict__ links,
-                                                   int64_t* __restrict__ len, int* bad) {
+                                                   int32_t* __restrict__ leg_of, int64_t* __restrict__ len,
+                                                   int* bad) {
     const int l = blockIdx.x * kWG + threadIdx.x;
     if (l >= dem.P) return;
     const int qi = dem.leg_q[l];
@@ -1745,6 +1746,7 @@ __global__ __launch_bounds__(kWG) void k_path_walk(NetDev net, DemDev dem, const
                 break;
             }
             links[at + k] = e;
+            leg_of[at + k] = l;
         }
         ++k;
         tau = nt;
@@ -1755,35 +1757,37 @@ __global__ __launch_bounds__(kWG) void k_path_walk(NetDev net, DemDev dem, const
 }
 
 hipError_t launch_path_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
-                            const int64_t* ptr, int32_t* links, int64_t* len, int* bad) {
+                            const int64_t* ptr, int32_t* links, int32_t* leg_of, int64_t* len, int* bad) {
     if (dem.P == 0) return hipSuccess;
     hipLaunchKernelGGL(k_path_walk, dim3((dem.P + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels, ptr, links,
-                       len, bad);
+                       leg_of, len, bad);
     return hipGetLastError();
 }
 
 // y += rint(d 2^20) along every leg's path: the loading of Eq. 5 for a
 // real-valued demand, exact in int64 whatever the order of the atomics.
-__global__ __launch_bounds__(kWG) void k_path_load(int P, const int64_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ links, const double* __restrict__ d,
+// One lane per (leg, link) entry of the flattened paths, so the link ids
+// and leg indices are read coalesced and long paths spread over lanes.
+__global__ __launch_bounds__(kWG) void k_path_load(int64_t total, const int32_t* __restrict__ links,
+                                                   const int32_t* __restrict__ leg_of, const double* __restrict__ d,
                                                    int64_t* y, int* err) {
-    const int l = blockIdx.x * kWG + threadIdx.x;
-    if (l >= P) return;
-    const double x = d[l] * 1048576.0;
-    if (!(x > -9.0e18 && x < 9.0e18)) {
-        atomicOr(err, 1);
-        return;
+    for (int64_t i = blockIdx.x * (int64_t)kWG + threadIdx.x; i < total; i += (int64_t)gridDim.x * kWG) {
+        const double x = d[leg_of[i]] * 1048576.0;
+        if (!(x > -9.0e18 && x < 9.0e18)) {
+            atomicOr(err, 1);
+            continue;
+        }
+        const int64_t w = (int64_t)__builtin_rint(x);
+        if (w != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&y[links[i]]), (unsigned long long)w);
     }
-    const int64_t w = (int64_t)__builtin_rint(x);
-    if (w == 0) return;
-    for (int64_t k = ptr[l]; k < ptr[l + 1]; ++k)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&y[links[k]]), (unsigned long long)w);
 }
 
-hipError_t launch_path_load(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* d,
-                            int64_t* y, int* err) {
-    if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_path_load, dim3((P + kWG - 1) / kWG), dim3(kWG), 0, s, P, ptr, links, d, y, err);
+hipError_t launch_path_load(hipStream_t s, int64_t total, const int32_t* links, const int32_t* leg_of,
+                            const double* d, int64_t* y, int* err) {
+    if (total == 0) return hipSuccess;
+    const int64_t b = (total + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_path_load, dim3((unsigned)(b < 8192 ? b : 8192)), dim3(kWG), 0, s, total, links, leg_of, d,
+                       y, err);
     return hipGetLastError();
 }
 

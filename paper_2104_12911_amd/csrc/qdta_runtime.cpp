@@ -126,6 +126,8 @@ struct qdta_ctx {
     double adj_ab = 0.15;
     std::vector<DBuf<int64_t>> adj_ptr;   // [J+1] offsets of each leg's path
     std::vector<DBuf<int32_t>> adj_links; // [J+1] link ids in walk order
+    std::vector<DBuf<int32_t>> adj_leg;   // [J+1] the leg of each entry
+    std::vector<int64_t> adj_total;       // [J+1] entries per iterate
     DBuf<int64_t> adj_len, adj_f, adj_y, adj_cur;
     DBuf<double> adj_alpha, adj_fbar, adj_ybar, adj_part, adj_s;
     DBuf<float> adj_cap;
@@ -1636,6 +1638,8 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
     c->adj_fwd = false;
     c->adj_ptr.resize((size_t)J + 1);
     c->adj_links.resize((size_t)J + 1);
+    c->adj_leg.resize((size_t)J + 1);
+    c->adj_total.assign((size_t)J + 1, 0);
     RC(dalloc(c, c->adj_len, (size_t)std::max<int64_t>(P, 1)));
     RC(dalloc(c, c->adj_f, (size_t)(J + 1) * M));
     RC(dalloc(c, c->adj_y, (size_t)(J + 1) * M));
@@ -1660,7 +1664,8 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
                                     delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
         }
         RC(clear_flags(c));
-        HIPCHECK(c, launch_path_walk(c->stream, net, dem, lab, nullptr, nullptr, c->adj_len.p, c->flags.p + 3));
+        HIPCHECK(c, launch_path_walk(c->stream, net, dem, lab, nullptr, nullptr, nullptr, c->adj_len.p,
+                                     c->flags.p + 3));
         if (P) HIPCHECK(c, hipMemcpyAsync(len.data(), c->adj_len.p, sizeof(int64_t) * P, hipMemcpyDeviceToHost,
                                           c->stream));
         int h[4];
@@ -1671,10 +1676,12 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
         for (int64_t l = 0; l < P; ++l) ptr[l + 1] = ptr[l] + len[l];
         RC(dalloc(c, c->adj_ptr[j], (size_t)P + 1));
         RC(dalloc(c, c->adj_links[j], (size_t)std::max<int64_t>(ptr[P], 1)));
+        RC(dalloc(c, c->adj_leg[j], (size_t)std::max<int64_t>(ptr[P], 1)));
+        c->adj_total[j] = ptr[P];
         HIPCHECK(c, hipMemcpyAsync(c->adj_ptr[j].p, ptr.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice,
                                    c->stream));
         HIPCHECK(c, launch_path_walk(c->stream, net_view(c), dem_view(c), lab, c->adj_ptr[j].p, c->adj_links[j].p,
-                                     nullptr, c->flags.p + 3));
+                                     c->adj_leg[j].p, nullptr, c->flags.p + 3));
         RC(read_flags(c, h));
         if (h[3]) return set_err(c, QDTA_ESTATE, "iterate %d: paths changed between the two walks", j);
     }
@@ -1691,7 +1698,7 @@ int qdta_model_forward(qdta_ctx* c, const qdta_opts* o, const double* d, const f
     if (!adj_valid(c)) return set_err(c, QDTA_ESTATE, "no recorded paths for the current solve (qdta_adjoint_record)");
     if (!d || !f_out) return set_err(c, QDTA_EARG, "null array");
     const int64_t M = c->M;
-    const int P = (int)c->P, J = c->adj_J;
+    const int J = c->adj_J;
     c->adj_fwd = false;
     HIPCHECK(c, hipMemcpyAsync(c->adj_cap.p, cap ? cap : c->cap.p, sizeof(float) * M, hipMemcpyDeviceToDevice,
                                c->stream));
@@ -1701,7 +1708,8 @@ int qdta_model_forward(qdta_ctx* c, const qdta_opts* o, const double* d, const f
     for (int j = 0; j <= J; ++j) {
         int64_t* yj = c->adj_y.p + (size_t)j * M;
         HIPCHECK(c, launch_fill_i64(c->stream, yj, 0, M));
-        HIPCHECK(c, launch_path_load(c->stream, P, c->adj_ptr[j].p, c->adj_links[j].p, d, yj, c->flags.p));
+        HIPCHECK(c, launch_path_load(c->stream, c->adj_total[j], c->adj_links[j].p, c->adj_leg[j].p, d, yj,
+                                     c->flags.p));
         if (j == 0) {
             HIPCHECK(c, hipMemcpyAsync(c->adj_cur.p, yj, sizeof(int64_t) * M, hipMemcpyDeviceToDevice, c->stream));
             continue;
