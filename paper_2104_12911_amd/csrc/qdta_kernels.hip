@@ -1791,23 +1791,36 @@ hipError_t launch_path_load(hipStream_t s, int64_t total, const int32_t* links, 
     return hipGetLastError();
 }
 
-// dbar[l] (+)= the sum of g over leg l's path, in walk order: the transpose
-// of the loading.
+// dbar[l] (+)= the sum of g over leg l's path: the transpose of the
+// loading.  A group of 16 lanes per leg reads the link ids coalesced; each
+// lane sums every 16th entry in walk order, then the group adds its 16
+// partial sums by a fixed butterfly, so the result does not vary run to run.
+constexpr int kGatherLanes = 16;
+
 __global__ __launch_bounds__(kWG) void k_path_gather(int P, const int64_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ links,
                                                      const double* __restrict__ g, double* dbar, int accumulate) {
-    const int l = blockIdx.x * kWG + threadIdx.x;
-    if (l >= P) return;
+    const int64_t gid = (blockIdx.x * (int64_t)kWG + threadIdx.x) / kGatherLanes;
+    const int sub = threadIdx.x % kGatherLanes;
+    const bool live = gid < P;
     double acc = 0.0;
-    for (int64_t k = ptr[l]; k < ptr[l + 1]; ++k) acc += g[links[k]];
-    dbar[l] = accumulate ? dbar[l] + acc : acc;
+    if (live) {
+        const int l = (int)gid;
+        for (int64_t k = ptr[l] + sub; k < ptr[l + 1]; k += kGatherLanes) acc += g[links[k]];
+    }
+    for (int o = kGatherLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kGatherLanes);
+    if (live && sub == 0) {
+        const int l = (int)gid;
+        dbar[l] = accumulate ? dbar[l] + acc : acc;
+    }
 }
 
 hipError_t launch_path_gather(hipStream_t s, int P, const int64_t* ptr, const int32_t* links, const double* g,
                               double* dbar, int accumulate) {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_path_gather, dim3((P + kWG - 1) / kWG), dim3(kWG), 0, s, P, ptr, links, g, dbar,
-                       accumulate);
+    const int64_t threads = (int64_t)P * kGatherLanes;
+    hipLaunchKernelGGL(k_path_gather, dim3((unsigned)((threads + kWG - 1) / kWG)), dim3(kWG), 0, s, P, ptr, links, g,
+                       dbar, accumulate);
     return hipGetLastError();
 }
 
