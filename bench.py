@@ -513,7 +513,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {net.n} nodes, {net.m} links, {Q} destinations, {li.total_legs} legs,"
                                f" dt {dem.dt_s:g} s", "delta_scale": opts.delta_scale or 10.0,
-                   "sssp_shape": opts.sssp_shape, "waves_per_cu": opts.waves_per_cu or 32,
+                   "sssp_shape": opts.sssp_shape,
+                   "waves_per_cu": opts.waves_per_cu or (32 if opts.tree_waves == 1 else 24),
                    "tree_waves": opts.tree_waves or 4,
                    "line_search": "K-section K=32 x3", "launch": "HIP graph per FW iteration"},
         "gteps": Q * net.m / sssp_avg_s / 1e9,

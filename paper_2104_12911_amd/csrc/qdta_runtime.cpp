@@ -229,8 +229,11 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     return true;
 }
 
-int waves_per_cu(const qdta_opts* o) { return o->waves_per_cu ? o->waves_per_cu : 32; }
 int tree_waves(const qdta_opts* o) { return o->tree_waves == 1 ? 1 : 4; }
+int waves_per_cu(const qdta_opts* o) {
+    if (o->waves_per_cu) return o->waves_per_cu;
+    return tree_waves(o) == 1 ? 32 : 24;
+}
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
 // Kernel variants 0-5: one wavefront per tree; 8-13: one workgroup per tree
@@ -374,7 +377,8 @@ int64_t tree_words(int64_t n) { return (n + 31) / 32 * 32; }
 // Scratch: one slot per tree in flight, i.e. per wavefront (tree_waves 1) or
 // per workgroup (tree_waves 4); launches never use more slots than exist.
 int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
-    int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1), (int64_t)c->cus * wpc);
+    // every tree takes tw wavefronts; never more than wpc per CU
+    int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1) * (tw == 1 ? 1 : 4), (int64_t)c->cus * wpc);
     slots = (slots + 3) / 4 * 4;
     c->slots = slots;
     const int need = tw == 1 ? slots : slots / 4;
@@ -1403,9 +1407,14 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
         t.tree_waves = k < 0 ? start_tw : tws[k / 12];
         const int sh = t.sssp_shape, tw = t.tree_waves;
         const double sc = t.delta_scale;
+        // the trial's own occupancy (the scratch, sized for one wavefront per
+        // tree, covers both forms; launches never exceed it)
+        int ts = (int)std::min<int64_t>((int64_t)std::max<int64_t>(c->Q, 1) * (tw == 1 ? 1 : 4),
+                                        (int64_t)c->cus * waves_per_cu(&t));
+        ts = (ts + 3) / 4 * 4;
         hipError_t e = hipEventRecord(e0, c->stream);
         if (e == hipSuccess)
-            e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), c->slots, nullptr,
+            e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), ts, nullptr,
                             delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), 1);
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
