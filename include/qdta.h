@@ -326,7 +326,7 @@ int qdta_model_backward(qdta_ctx *ctx, const double *fbar, double *dbar, double 
  * and writes the fastest into opts->sssp_shape, opts->delta_scale and
  * opts->tree_waves (other fields unchanged).  The configuration passed in
  * (zero fields read as the defaults) is timed first, after one untimed
- * launch, and is kept unless another is at least 2% faster.  Results never
+ * launch, and is kept unless another is at least 5% faster.  Results never
  * depend on these fields, only the speed does.  *best_ms_out (host, may be
  * NULL) receives the time of the configuration chosen.  Synchronises. */
 int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best_ms_out);
