@@ -921,7 +921,8 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
             for (int i0 = 0; i0 < fcnt; i0 += 64) {
                 const int i = i0 + lane;
                 const bool h = i < fcnt;
-                const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;   // the label now (see k_sssp_wg)
                 const float dv = __uint_as_float(ent.y);
                 const bool ton = h && dv < thr;
                 const bool tok = h && !ton;
@@ -1184,8 +1185,9 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
                     for (int i0 = 0; i0 < fcnt; i0 += NT) {
                         const int i = i0 + tid;
                         const bool h = i < fcnt;
-                        const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
-                        const bool late = h && __uint_as_float(ld_coherent(&D[ent.x]) & kValueBits) < thr;
+                        uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                        if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;   // the label now
+                        const bool late = h && __uint_as_float(ent.y) < thr;
                         __syncthreads();                  // the chunk is read before it is overwritten
                         if (late) {
                             push_near((int)ent.x);
@@ -1229,7 +1231,12 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
             for (int i0 = 0; i0 < fcnt; i0 += NT) {
                 const int i = i0 + tid;
                 const bool h = i < fcnt;
-                const uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                // key by the label now: a far node improved since its push keeps
+                // its queued flag and is not pushed again, and waiting for the
+                // threshold to pass its old label would make every node it
+                // reaches meanwhile be popped again
+                if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;
                 __syncthreads();
                 if (h && __uint_as_float(ent.y) < thr) {
                     push_near((int)ent.x);
