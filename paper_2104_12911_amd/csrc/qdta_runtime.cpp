@@ -86,7 +86,7 @@ struct qdta_ctx {
     DBuf<InstState> st;
     DBuf<long long> acc, ls_acc;
     DBuf<double> alphas, alpha_arr;
-    DBuf<int> flags;              // [0] overflow, [1] unreach, [2] absorb count
+    DBuf<int> flags;              // [0] overflow, [1] unreach, [2] absorb count, [3] path-record faults
     DBuf<int32_t> absorb_q, int_node;
     DBuf<float> int_tau;
     DBuf<float> hist_cost;
