@@ -21,8 +21,8 @@ d alpha_j = -(dF)/(dF/d alpha) with F = C':
     dF/d alpha = sum t^2 c'(v),   dF/df_a = -c_a + (1 - alpha) t_a c'_a,
     dF/dy_a = c_a + alpha t_a c'_a,   dF/dC_a = t_a dc_a/dC_a,
 
-(v = f + alpha t, c' = dc/dv); a step size at 0 or 1 (bracket end) has zero
-derivative.  Two forward forms:
+(v = f + alpha t, c' = dc/dv); a step size at 0 or 1 (bracket end), or
+one of the fixed MSA sequence, has zero derivative.  Two forward forms:
 
   * contract: the library's own arithmetic -- demand in fixed point
     (rint(d 2^20)), integer loading, the K-section line search with exact
@@ -149,10 +149,12 @@ def forward_exact(path_list, m, d, c0, cap, alpha_b, beta, dt_s):
     return f, states
 
 
-def backward(states, fbar, path_list, c0, cap, alpha_b, beta, dt_s, fixed_point=True):
+def backward(states, fbar, path_list, c0, cap, alpha_b, beta, dt_s, fixed_point=True, fixed_steps=False):
     """Reverse pass: given dL/df (per link, per veh), returns dL/dd (per leg,
     per veh) and dL/dC (per link).  `fixed_point` states hold int64 flows in
-    units of 2^-20 veh (forward_contract), else FP64 veh (forward_exact)."""
+    units of 2^-20 veh (forward_contract), else FP64 veh (forward_exact).
+    `fixed_steps`: the step sizes are a fixed sequence (MSA), not roots, so
+    they carry no derivative."""
     kap = kappa(dt_s)
     m = np.asarray(c0).shape[0]
     fbar = np.array(fbar, dtype=np.float64)
@@ -168,7 +170,7 @@ def backward(states, fbar, path_list, c0, cap, alpha_b, beta, dt_s, fixed_point=
         cost, dcdv, dcdcap = bpr_terms(F + a * t, c0, cap, alpha_b, beta, kap)
         abar = float(np.sum(fbar * t))
         s = 0.0
-        if 0.0 < a < 1.0:
+        if not fixed_steps and 0.0 < a < 1.0:
             Fa = float(np.sum(t * t * dcdv))
             if Fa != 0.0:
                 s = -abar / Fa

@@ -136,3 +136,31 @@ def test_contract_replay_reproduces_solver(orc, dt_s, scale):
                 assert tails[e] == u
                 u = net.col[e]
             assert u == stop[p]
+
+
+def test_fixed_steps_backward_is_lambda_weighted_gather(orc):
+    """With MSA the step sizes are fixed, the flows are linear in the demand,
+    f = sum_j lambda_j L_j d with lambda_j = alpha_j prod_{k>j} (1 - alpha_k)
+    and alpha_0 = 1 (the path weights of Alg. 4), and the capacities do not
+    enter: the reverse pass must give sum_j lambda_j L_j^T g and zero."""
+    from oracle import adjoint as adj
+    net, o, d, trips = _grid_case(float("inf"), 1.0, 13)
+    res, pl = _frozen(orc, net, o, d, trips, float("inf"), 5, ls_mode=orc.LS_MSA)
+    f, st = adj.forward_contract(pl, net.m, trips, net.fftt, net.cap, 0.15, 4, float("inf"), ls_mode=orc.LS_MSA)
+    assert np.array_equal(f, res.f)
+    alphas = [1.0] + [s[2] for s in st[1:]]
+    assert alphas[1:] == [1.0 / (j + 1) for j in range(1, len(alphas))]
+    g = np.random.default_rng(2).standard_normal(net.m)
+    dbar, capbar = adj.backward(st, g, pl, net.fftt, net.cap, 0.15, 4, float("inf"), fixed_steps=True)
+    want = np.zeros(len(trips))
+    J = len(alphas) - 1
+    for j in range(J + 1):
+        lam = alphas[j]
+        for k in range(j + 1, J + 1):
+            lam *= 1.0 - alphas[k]
+        ptr, links = pl[j]
+        for p in range(len(trips)):
+            want[p] += lam * g[links[ptr[p]:ptr[p + 1]]].sum()
+    assert np.allclose(dbar, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+    assert not np.any(capbar)
+
