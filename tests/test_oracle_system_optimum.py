@@ -109,3 +109,56 @@ def test_system_optimum_total_time_below_equilibrium_grid(orc):
     assert tt_so < tt_ue
     assert so.objective == pytest.approx(tt_so, rel=1e-9)
     assert 0 <= so.gap < 1e-2
+
+
+def _tt_root(f, y, c0, cap, ab, beta, kappa):
+    """Root in [0, 1] of d/dalpha sum v c(v), v = F + alpha t, from the
+    polynomial v (c0 + c0 ab (kappa v / C)^beta) expanded in alpha and
+    differentiated by numpy (no marginal-cost formula involved)."""
+    poly = np.poly1d([0.0])
+    for a in range(f.size):
+        F, t = f[a] / FX, (y[a] - f[a]) / FX
+        v = np.poly1d([t, F])
+        base = np.poly1d([kappa * t / cap[a], kappa * F / cap[a]])
+        poly = poly + v * float(c0[a]) + v * float(c0[a]) * ab * base ** beta
+    d = poly.deriv()
+    real = [r.real for r in d.roots if abs(r.imag) < 1e-9 and -1e-9 <= r.real <= 1 + 1e-9]
+    return min(real) if real else None
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_system_optimum_line_search_root(orc, seed):
+    rng = np.random.default_rng(700 + seed)
+    m = 5
+    c0 = rng.uniform(10, 100, m).astype(np.float32)
+    cap = rng.choice([900.0, 1800.0], m).astype(np.float32)
+    f = rng.integers(100 * FX, 900 * FX, m).astype(np.int64)
+    y = rng.integers(0, 300 * FX, m).astype(np.int64)
+    y[0] = 2000 * FX
+    root = _tt_root(f, y, c0, cap, 0.15, 4, 4.0)
+    assert root is not None and 0.0 < root < 1.0
+    a_ks, _, _ = orc.line_search(f, y, c0, cap, 0.15, 4, 900.0, 3, objective=orc.OBJ_SO)
+    assert abs(a_ks - root) < 1e-4
+    a_qn, _, _ = orc.line_search(f, y, c0, cap, 0.15, 4, 900.0, 3, ls_mode=orc.LS_QN, objective=orc.OBJ_SO)
+    assert abs(a_qn - root) < 2e-4
+    ue, _, _ = orc.line_search(f, y, c0, cap, 0.15, 4, 900.0, 3)
+    assert abs(ue - a_ks) > 1e-3          # a different objective, a different step
+
+
+def test_system_optimum_day_trip_conservation(orc):
+    """Under the system optimum too, demand entering an interval = demand
+    completing in it + residual carried out (travel times clock the walk),
+    to within one fixed-point unit per (iterate, leg)."""
+    w = synth.config1()
+    rng = np.random.default_rng(19)
+    days = []
+    for i in range(3):
+        sel = rng.random(w.demand.P) < 0.4
+        days.append(synth.demand.Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] / 3, 600.0))
+    out, left = orc.qdta_day(w.net, days, tol=1e-3, max_iter=20, objective=orc.OBJ_SO)
+    carried = 0
+    for r in out:
+        res = int(r["res"][2].sum())
+        assert abs(r["in_fx"] - (r["done_fx"] + res)) <= (r["iters"] + 1) * r["legs"]
+        carried += res
+    assert carried > 0
