@@ -11,6 +11,13 @@
  *   Alg. 8-9) -> link-flow update.  After an interval, residual demand is
  *   carried to the next one (Alg. 4, Alg. 1).
  *
+ * Also: the system optimum in place of the user equilibrium
+ * (opts->objective, Wardrop's second principle, section 3); checkpoint and
+ * resume between intervals (qdta_get_residual / qdta_set_residual); and the
+ * derivative of a solved interval's flows in the demand and the capacities
+ * at frozen paths, for OD calibration (qdta_adjoint_record,
+ * qdta_model_forward, qdta_model_backward; not in the paper).
+ *
  * Conventions (all entry points):
  *   - Return value: QDTA_OK (0) on success, a negative QDTA_E* code on error
  *     (the context's last-error text says why), a positive QDTA_W* code for a
