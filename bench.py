@@ -388,7 +388,9 @@ def mode_calib(args, torch, qdta):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="aon: timed FW iterations; day: FW iteration cap per interval (use 200); "
+                         "plain: cap of the batched solve; batch: fixed iterations")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
     ap.add_argument("--delta-scale", type=float, default=0.0, help="bucket width / mean link cost (0: library default)")
