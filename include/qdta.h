@@ -42,6 +42,8 @@
  *     (qdta_layout() gives the offsets).
  *   - A link's id ("uid") is its position in the caller's CSR.  Shortest-path
  *     ties are broken towards the lowest uid.
+ *   - Sizes: nodes, links and legs, each summed over a context's instances,
+ *     stay below 2^31 (QDTA_EARG otherwise).
  *   - Contexts are not thread-safe; use one per host thread.
  */
 #ifndef QDTA_H

@@ -400,6 +400,9 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
 int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     RC(ensure_network(c));
     if (!c->dem_dirty) return wpc > 0 ? ensure_scratch(c, c->Q, c->nmax, wpc, tw) : QDTA_OK;
+    int64_t total_legs = 0;
+    for (const Instance& I : c->inst) total_legs += (int64_t)I.orig.size();
+    if (total_legs >= INT32_MAX) return set_err(c, QDTA_EARG, "total legs beyond int32 ids");
     int ni = (int)c->inst.size();
     std::vector<int32_t> qptr{0}, leg_orig, leg_q, dest_node, dest_inst;
     std::vector<int64_t> leg_dfx, dest_lab;
