@@ -359,10 +359,10 @@ def mode_calib(args, torch, qdta):
 
     g = torch.empty(P, dtype=torch.float64, device="cuda")
     capbar = torch.empty(m, dtype=torch.float64, device="cuda")
-    ctx.model_forward(opts, dfin, None, fo)
+    fid = ctx.model_forward(opts, dfin, None, fo)
     fbar = torch.zeros(m, dtype=torch.float64, device="cuda")
     fbar[obs] = 2.0 * (fo[obs] - counts)
-    ctx.model_backward(fbar, g, capbar)
+    ctx.model_backward(fid, fbar, g, capbar)
     gh = g.cpu().numpy()
     fd_err = []
     for l in np.argsort(-np.abs(gh))[:4]:

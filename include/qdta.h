@@ -62,7 +62,7 @@ extern "C" {
 #define QDTA_EVAL (-3)      /* free-flow time or capacity <= 0 or not finite */
 #define QDTA_EUNREACH (-4)  /* a leg's destination is unreachable from its origin */
 #define QDTA_EOVF (-5)      /* fixed-point, cost or exact-sum overflow */
-#define QDTA_ENOMEM (-6)    /* device allocation failed */
+#define QDTA_ENOMEM (-6)    /* device allocation failed, or the bound workspace is too small */
 #define QDTA_EHIP (-7)      /* HIP runtime error (text in last error) */
 #define QDTA_ESTATE (-8)    /* call out of order (e.g. solve before demand) */
 #define QDTA_WABSORB 1      /* FP32 absorption: the tie-rule fallback was used */
@@ -123,9 +123,14 @@ typedef struct {
     int32_t tree_waves;    /* wavefronts that grow one shortest-path tree: 0 auto (4), 4 (a whole
                               workgroup per tree, a quarter as many trees in flight), or 1 */
     int32_t history_mib;   /* with keep_history: device memory for the iterates' labels, in MiB:
-                              0 auto (the free memory less 16 GiB), < 0 none (the residual step
-                              grows every tree again); never changes results */
+                              0 auto (without a workspace: the free device memory less 16 GiB; with
+                              one: what the workspace has left), < 0 none (the residual step grows
+                              every tree again); never changes results */
     int32_t objective;     /* QDTA_OBJ_UE (default) or QDTA_OBJ_SO */
+    int32_t sssp_kernel;   /* shortest-path kernel: 0 auto, 1 node queue (tree_waves and sssp_shape as
+                              above), 2 block-local (a block of node ids is relaxed to closure in LDS per
+                              load; sssp_shape 1..4 = blocks of 128, 128 (two per wavefront per step), 64,
+                              256 nodes; instances of at most 8,192 blocks, else the node queue) */
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */
@@ -157,10 +162,54 @@ const char *qdta_last_error(const qdta_ctx *ctx);
 /* Create a context on HIP device `device`, enqueuing on `stream` (a
  * hipStream_t; NULL = the default stream).  *out receives the context. */
 int qdta_create(qdta_ctx **out, int device, void *stream);
-/* Free the context and its device memory.  Synchronises its stream. */
+/* Free the context and the device memory it allocated (a bound workspace
+ * stays the caller's).  Synchronises its stream. */
 int qdta_destroy(qdta_ctx *ctx);
 /* Change the stream later calls enqueue on. */
 int qdta_set_stream(qdta_ctx *ctx, void *stream);
+
+/* ---- Device memory owned by the caller ------------------------------------
+ * By default the library allocates its own device memory (hipMalloc) as the
+ * networks, the demand and the options need it, and frees it in
+ * qdta_destroy.  A caller that owns the device memory (a torch tensor,
+ * memory shared with other work) sizes a workspace with
+ * qdta_workspace_query and hands it over with qdta_bind_workspace; from then
+ * on every device buffer of the context -- network copies, demand tables,
+ * shortest-path labels and queues, Frank-Wolfe state, per-iterate costs and
+ * labels, the residual accumulator of Alg. 4 -- is carved from it and the
+ * library calls hipMalloc no more.  The inputs are those of the problem
+ * statement (section 3.1: the network, the interval's demand, the BPR and
+ * step-rule options).
+ *
+ * qdta_workspace_query: *bytes (host) receives the device memory a solve
+ * (and, with opts->keep_history, qdta_advance_interval) needs for the
+ * networks added so far and the current demand, or for max_legs legs and
+ * max_dests destinations (over all instances) if these are larger (0: the
+ * current demand's).  max_legs also bounds the residual legs an interval
+ * leaves (before merging, at most one per leg and iterate with weight > 0).
+ * With keep_history, it covers opts->history_mib MiB of
+ * iterate labels when that is > 0 (when it is 0, the labels get whatever the
+ * workspace has left).  The maxima are remembered: once bound, buffers sized
+ * by the demand are carved at them, so later intervals up to those sizes
+ * reuse them.  Host-only: it allocates nothing.
+ * qdta_bind_workspace: dev_ptr (device, aligned to 256 bytes, owned by the
+ * caller, alive until qdta_destroy) of `bytes` bytes.  Call once, after the
+ * networks and demand are set and before any call that uses device memory
+ * (QDTA_ESTATE otherwise).  A call that needs more than is left returns
+ * QDTA_ENOMEM (the text names the size): query again with larger maxima and
+ * bind a larger workspace in a new context (qdta_get_residual /
+ * qdta_set_residual carry the state between intervals).  The label-history
+ * and path-record extras (qdta_adjoint_record, qdta_trees' temporaries) are
+ * carved from what is left.  The library still allocates a small pinned host
+ * mirror of the per-instance state.
+ * qdta_alloc_count: *hip_mallocs (host, may be NULL) receives the number of
+ * hipMalloc calls the context has made, *ws_in_use (may be NULL) the
+ * workspace bytes currently carved -- for callers and tests that check that
+ * no allocation happens. */
+int qdta_workspace_query(qdta_ctx *ctx, const qdta_opts *opts, int64_t max_legs, int64_t max_dests,
+                         size_t *bytes);
+int qdta_bind_workspace(qdta_ctx *ctx, void *dev_ptr, size_t bytes);
+int qdta_alloc_count(const qdta_ctx *ctx, int64_t *hip_mallocs, size_t *ws_in_use);
 
 /* Add a network instance (section 3.1 notation: graph G(V,A), capacity C_a,
  * free-flow time c_0,a).  Host arrays: row_ptr int32[n+1] (row_ptr[0] = 0,
@@ -316,17 +365,21 @@ int qdta_adjoint_record(qdta_ctx *ctx, const qdta_opts *opts);
 /* Forward pass of the model.  d: double[total_legs] (device), veh per leg in
  * the context's leg order (qdta_get_legs); cap: float[total_links] (device)
  * or NULL for the network's capacities; f_out: double[total_links] (device),
- * veh.  Keeps the iterates for qdta_model_backward.  Errors: QDTA_ESTATE (no
+ * veh.  Keeps the iterates for qdta_model_backward and writes the id of this
+ * forward pass to *fwd_id_out (host, may be NULL).  Errors: QDTA_ESTATE (no
  * record for the current solve), QDTA_EOVF (non-finite demand or costs).
  * Synchronises. */
 int qdta_model_forward(qdta_ctx *ctx, const qdta_opts *opts, const double *d, const float *cap,
-                       double *f_out);
+                       double *f_out, uint64_t *fwd_id_out);
 
-/* Reverse pass of the last qdta_model_forward: given fbar = dL/df (double
- * [total_links], device), writes dbar = dL/dd (double[total_legs]) and
- * capbar = dL/dC (double[total_links]), device outputs.  Enqueued on the
- * stream, no synchronisation. */
-int qdta_model_backward(qdta_ctx *ctx, const double *fbar, double *dbar, double *capbar);
+/* Reverse pass of the forward pass fwd_id (the id qdta_model_forward
+ * returned in *fwd_id_out; the context keeps the iterates of its last
+ * forward pass only): given fbar = dL/df (double[total_links], device),
+ * writes dbar = dL/dd (double[total_legs]) and capbar = dL/dC
+ * (double[total_links]), device outputs.  Errors: QDTA_ESTATE when another
+ * forward pass ran after fwd_id (its iterates are gone; run that forward
+ * again).  Enqueued on the stream, no synchronisation. */
+int qdta_model_backward(qdta_ctx *ctx, uint64_t fwd_id, const double *fbar, double *dbar, double *capbar);
 
 /* Autotuner: times the shortest-path launch of the current demand (every
  * instance, under the costs BPR(f) of the last solved iterate, free-flow

@@ -57,7 +57,8 @@ class _FwOpts(C.Structure):
 class _FwStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("ls_evals", C.c_int32), ("qn_iters", C.c_int32),
                 ("absorb", C.c_int32), ("stopped_by", C.c_int32), ("gap", C.c_double),
-                ("objective", C.c_double), ("last_alpha", C.c_double)]
+                ("objective", C.c_double), ("last_alpha", C.c_double), ("gap_fp64", C.c_double),
+                ("objective_fp64", C.c_double)]
 
 
 _lib = None
@@ -102,11 +103,30 @@ def i128(limbs) -> int:
 # thin wrappers
 # ---------------------------------------------------------------------------
 def trips_to_fx(trips) -> np.ndarray:
+    """Trips -> int64 units of 2^-20 vehicle, round half to even (the C
+    routine orc_trips_to_fx, one call per value)."""
     L = lib()
     L.orc_trips_to_fx.restype = C.c_int64
     L.orc_trips_to_fx.argtypes = [C.c_double]
     return np.array([L.orc_trips_to_fx(float(t)) for t in np.asarray(trips, dtype=np.float64)],
                     dtype=np.int64)
+
+
+def trips_to_fx_array(trips) -> np.ndarray:
+    """The same conversion for large arrays: trips * 2^20 is exact (a power of
+    two), and numpy's rint rounds half to even."""
+    return np.rint(np.asarray(trips, dtype=np.float64) * FX).astype(np.int64)
+
+
+def demand_legs(orig, dest, trips):
+    """The legs an interval's demand becomes (the problem statement of section
+    3.1 with the conventions of the fixed-point contract): trips quantised to
+    2^-20 vehicle, legs with equal (origin, destination) summed, legs with
+    origin == destination or no trips dropped, sorted by (destination,
+    origin)."""
+    o, d, w = merge_legs(orig, dest, trips_to_fx_array(trips))
+    keep = (w > 0) & (o != d)
+    return o[keep], d[keep], w[keep]
 
 
 def kappa(dt_s: float) -> float:
@@ -133,6 +153,20 @@ def sum_cx(c, x_fx) -> int:
     L.orc_sum_cx.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_sum_cx(c.shape[0], _p(c), _p(x_fx), _p(out))
     return i128(out)
+
+
+def ref_fp64(f_fx, y_fx, c0, cap, alpha_b, beta, dt_s, objective=OBJ_UE):
+    """FP64 reference (long double, no FP32 costs, no quantised terms) of the
+    relative gap and the objective of flows f with direction y: a dict with
+    scf, scy, gap, objective."""
+    f_fx, y_fx, c0, cap = _i64(f_fx), _i64(y_fx), _f32(c0), _f32(cap)
+    out = np.zeros(4, dtype=np.float64)
+    L = lib()
+    L.orc_ref_fp64.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                               C.c_double, C.c_int32, C.c_void_p]
+    L.orc_ref_fp64(c0.shape[0], _p(f_fx), _p(y_fx), _p(c0), _p(cap), alpha_b, beta, kappa(dt_s), int(objective),
+                   _p(out))
+    return {"scf": out[0], "scy": out[1], "gap": out[2], "objective": out[3]}
 
 
 def tree(net, cost, q):
@@ -224,6 +258,8 @@ class FwResult:
         self.gap = stats.gap
         self.objective = stats.objective
         self.last_alpha = stats.last_alpha
+        self.gap_fp64 = stats.gap_fp64
+        self.objective_fp64 = stats.objective_fp64
         self.hist_alpha = hist_alpha[: stats.iters + 1]
         self.hist_cost = hist_cost[: stats.iters + 1] if hist_cost is not None else None
         self.gaps = gaps[: stats.iters + 1]

@@ -667,6 +667,41 @@ static i128 objective(int32_t m, const int64_t *f, const float *c0, const float 
 }
 
 /* ------------------------------------------------------------------------ */
+/* FP64 reference of an iterate's relative gap and objective                 */
+/* ------------------------------------------------------------------------ */
+
+/* The relative gap (sum c F - sum c Y) / sum c F and the objective of flows f
+ * with all-or-nothing direction y, free of the numeric contract: no FP32
+ * rounding of the costs, no fixed-point quantisation of the terms, every
+ * cost, term and sum in long double (64-bit mantissa), the power by powl.
+ *   cost    c = c0 (1 + ab (kappa F / C)^beta)               (Eq. 1)
+ *           (system optimum: the marginal cost c0 (1 + ab (beta+1) (kappa F / C)^beta))
+ *   Beckmann integral  int_0^F c0 (1 + ab (kappa s / C)^beta) ds
+ *           = c0 F (1 + ab (kappa F / C)^beta / (beta + 1))  (Eq. 6)
+ *           (system optimum: the total travel time F c(F))
+ * out[0] = sum c F, out[1] = sum c Y (veh s), out[2] = gap, out[3] = objective.
+ * A reference for the contract's exact sums, which quantise every term to
+ * 2^-16 and route by FP32 costs. */
+void orc_ref_fp64(int32_t m, const int64_t *f, const int64_t *y, const float *c0, const float *cap,
+                  double ab, int32_t beta, double kappa, int32_t so, double *out) {
+    long double scf = 0.0L, scy = 0.0L, obj = 0.0L;
+    for (int32_t a = 0; a < m; ++a) {
+        long double F = (long double)f[a] / 1048576.0L;
+        long double Y = (long double)y[a] / 1048576.0L;
+        long double p = powl((long double)kappa * F / (long double)cap[a], (long double)beta);
+        long double tt = (long double)c0[a] * (1.0L + (long double)ab * p);
+        long double route = so ? (long double)c0[a] * (1.0L + (long double)ab * (long double)(beta + 1) * p) : tt;
+        scf += route * F;
+        scy += route * Y;
+        obj += so ? F * tt : (long double)c0[a] * F * (1.0L + (long double)ab * p / (long double)(beta + 1));
+    }
+    out[0] = (double)scf;
+    out[1] = (double)scy;
+    out[2] = (double)((scf - scy) / scf);
+    out[3] = (double)obj;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Frank-Wolfe for one interval (Alg. 2 in its link-flow form, Alg. 6)       */
 /* ------------------------------------------------------------------------ */
 
@@ -692,6 +727,8 @@ typedef struct {
     double gap;          /* relative gap at the returned iterate */
     double objective;    /* Beckmann objective at the returned iterate (veh s) */
     double last_alpha;
+    double gap_fp64;     /* the same gap and objective by orc_ref_fp64 (no FP32 costs, no */
+    double objective_fp64; /* quantised terms): the FP64 reference of each reported result */
 } fw_stats;
 
 /* hist_alpha: double[max_iter+1], hist_cost: float[(max_iter+1) * m] (may be
@@ -768,6 +805,13 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
         if (hist_cost) memcpy(hist_cost + (size_t)j * (size_t)m, c, sizeof(float) * (size_t)m);
     }
     st->objective = q2d(objective(m, f, c0, cap, o->alpha_b, o->beta, kappa, so, &bad)) / SUM_SCALE;
+    {
+        /* y holds the direction of the last test, the one the gap was taken on */
+        double ref[4];
+        orc_ref_fp64(m, f, y, c0, cap, o->alpha_b, o->beta, kappa, so, ref);
+        st->gap_fp64 = ref[2];
+        st->objective_fp64 = ref[3];
+    }
     rc = bad ? ORC_EOVF : ORC_OK;
 done:
     free(c); free(tc); free(y); free(zero);

@@ -10,6 +10,9 @@ constexpr int kWG = 256;                 // threads per workgroup (4 wavefronts 
 constexpr int kChunk = 2048;             // links per workgroup in link-parallel kernels
 constexpr uint32_t kInfBits = 0x7f800000u;
 constexpr int kMaxK = 64;                // step sizes per line-search pass
+// block-local shortest-path kernel: blocks per tree its LDS bitmap covers
+// (instances up to kBlkMaxBits * block-size nodes)
+constexpr int kBlkMaxBits = 8192;
 
 // One shortest-path label word: (not-queued flag << 31) | FP32 bits of the
 // distance.

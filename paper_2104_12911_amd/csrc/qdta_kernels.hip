@@ -1270,6 +1270,404 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
     }
 }
 
+// Block-local form of the same delta-stepping.  The node ids of an instance
+// are cut into blocks of B consecutive ids (in Hilbert order a block is a
+// compact patch of the network).  The near queue holds blocks, not nodes: a
+// block is queued (once: a bit per block in LDS) while it holds a queued node
+// whose label is below the bucket bound thr.  A step takes up to NW * KB
+// blocks off the queue; each wavefront, for each of its blocks,
+//   - loads the block's label words and in-link offsets (coalesced) and its
+//     in-link records into LDS;
+//   - relaxes inside the block to closure: every queued node below thr is
+//     taken (flag set with an LDS atomicOr that returns its label) and its
+//     in-links relaxed, those from inside the block by an LDS atomicMin on the
+//     staged word, those from other blocks into a mailbox; repeated until no
+//     queued node below thr is left -- many hops for one load of the block;
+//   - writes the changed words back; a node first queued in this visit at or
+//     above thr goes to the far queue.
+// Then the whole workgroup applies the mailboxes to the labels in memory (a
+// coherent read, then an atomicMin where the candidate is lower), queueing the
+// block of every node it improves below thr and sending to the far queue the
+// nodes it queues at or above thr.  Only one workgroup touches a tree, and
+// the two phases are separated by barriers, so the words a phase-1 wavefront
+// stages are not changed under it.  Whatever the order, the labels reach the
+// least fixed point of D(v) = min_e fl32(D(head e) + c_e), as in k_sssp_wg.
+//   A node is sent to the far queue at most once per tree: it is queued at or
+// above thr only before it is first taken (afterwards its label stays below
+// the thr of that moment), so the far queue holds at most n entries.
+// B: nodes per block (a multiple of 64); KB: blocks per wavefront per step.
+// kBlkMaxBits (qdta_internal.h): blocks per tree the LDS bitmap covers.
+template <int B, int KB>
+__global__ __launch_bounds__(kWG) void k_sssp_blk(NetDev net, DemDev dem, const uint2* __restrict__ radj,
+                                                  label_t* labels, Scratch scr, const InstState* st,
+                                                  const float* __restrict__ delta_inst, int early, int t_begin,
+                                                  int t_end) {
+    constexpr int NT = kWG;
+    constexpr int NW = NT / 64;
+    constexpr int R = B / 64;                   // nodes per lane in a block
+    constexpr int KMAX = NW * KB;               // blocks per step
+    constexpr int kBlkEmax = 3 * B;             // in-link records staged per block (the rest are read in place)
+    constexpr int kBlkMbx = 2 * B;              // mailbox entries (target, candidate) per wavefront and step
+    constexpr int kBig = 8;                     // per wavefront and step: nodes whose cross-block in-links
+                                                // are too many for the mailbox, relaxed in phase 2 by all threads
+    __shared__ uint32_t s_bits[kBlkMaxBits / 32];
+    __shared__ uint32_t s_lab[NW][B];
+    __shared__ int s_rp[NW][B + 1];
+    __shared__ uint2 s_adj[NW][kBlkEmax];
+    // one mailbox and one big-node list per (wavefront, block of the step), so
+    // every block visit starts with room for any one node: each visit takes
+    // at least one node
+    __shared__ uint2 s_mb[NW * KB][kBlkMbx];
+    __shared__ int s_mc[NW * KB];
+    __shared__ uint2 s_big[NW * KB][kBig];
+    __shared__ int s_nbig[NW * KB];
+    __shared__ int s_blk[KMAX];
+    __shared__ int s_t, s_qh, s_qn, s_qt, s_fn;
+    __shared__ uint32_t s_fm;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned long long below = lanes_below(lane);
+    int32_t* ring = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
+    uint2* farq = reinterpret_cast<uint2*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
+    uint32_t* L = s_lab[wv];
+    int* RP = s_rp[wv];
+    uint2* A = s_adj[wv];
+    for (;;) {
+        if (tid == 0) s_t = t_begin + atomicAdd(scr.work, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();
+        if (t >= t_end) break;
+        const int inst = dem.dest_inst[t];
+        if (!inst_live(st, inst)) continue;
+        const InstDev I = net.inst[inst];
+        const int n = I.n, node0 = I.node0;
+        const int* __restrict__ rptr = net.rptr + node0;
+        label_t* D = labels + dem.dest_lab[t];
+        const int root = dem.dest_node[t] - node0;
+        const float delta = delta_inst[inst];
+        const int nb = (n + B - 1) / B;
+        const int qcap = nb + 1;                // ring of block ids; at most nb are queued
+        {
+            uint4* D4 = reinterpret_cast<uint4*>(D);
+            const uint32_t w0 = kNotQueued | kInfBits;
+            const uint4 inf4 = make_uint4(w0, w0, w0, w0);
+            const int n4 = (n + 31) / 32 * 8;
+            for (int i = tid; i < n4; i += NT) D4[i] = inf4;
+        }
+        for (int i = tid; i < (nb + 31) / 32; i += NT) s_bits[i] = 0u;
+        if (tid == 0) {
+            s_qh = 0;
+            s_qn = 0;
+            s_qt = 0;
+            s_fn = 0;
+            s_fm = kInfBits;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            D[root] = 0u;                       // value 0, queued
+            const int b = root / B;
+            s_bits[b >> 5] |= 1u << (b & 31);
+            ring[0] = b;
+            s_qt = 1;
+            s_qn = 1;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        // queue block b unless it is queued (LDS bit); safe from any thread
+        auto push_block = [&](int b) {
+            const uint32_t bit = 1u << (b & 31);
+            if (atomicOr(&s_bits[b >> 5], bit) & bit) return;
+            int pos = atomicAdd(&s_qt, 1);
+            pos = pos % qcap;
+            ring[pos] = b;
+            atomicAdd(&s_qn, 1);
+        };
+        float thr = delta;
+        int fcnt = 0;
+        float fmin = __uint_as_float(kInfBits);
+        int lcur = early ? dem.qptr[t] : 0;
+        const int lend = early ? dem.qptr[t + 1] : 0;
+        for (;;) {
+            for (;;) {
+                const int qn = s_qn;
+                if (qn == 0) break;
+                const int k = qn < KMAX ? qn : KMAX;
+                const int qh = s_qh;
+                __syncthreads();                // every thread has read the counters
+                if (tid < k) {
+                    const int b = ring[(qh + tid) % qcap];
+                    s_blk[tid] = b;
+                    atomicAnd(&s_bits[b >> 5], ~(1u << (b & 31)));
+                }
+                if (tid == 0) {
+                    s_qh = (qh + k) % qcap;
+                    s_qn = qn - k;
+                }
+                if (tid < KMAX) {
+                    s_mc[tid] = 0;
+                    s_nbig[tid] = 0;
+                }
+                __syncthreads();
+                // ---- phase 1: each wavefront relaxes its blocks to closure
+                for (int kb = 0; kb < KB; ++kb) {
+                    const int j = kb * NW + wv;
+                    if (j >= k) break;
+                    const int b = s_blk[j];
+                    uint2* MB = s_mb[j];
+                    uint2* BG = s_big[j];
+                    int mcnt = 0, nbig = 0;
+                    const int v0 = b * B;
+                    const int nv = min(B, n - v0);
+                    uint32_t w0[R];
+                    bool q0[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int i = lane + 64 * r;
+                        w0[r] = i < nv ? ld_coherent(&D[v0 + i]) : (kNotQueued | kInfBits);
+                        q0[r] = !(w0[r] & kNotQueued);
+                        L[i] = w0[r];
+                        RP[i] = i < nv ? rptr[v0 + i] : 0;
+                    }
+                    if (lane == 0) RP[nv] = rptr[v0 + nv];
+                    __builtin_amdgcn_wave_barrier();
+                    const int e_lo = RP[0];
+                    const int E = RP[nv] - e_lo;
+                    for (int x = lane; x < E && x < kBlkEmax; x += 64) A[x] = radj[e_lo + x];
+                    __builtin_amdgcn_wave_barrier();
+                    bool skipped = false;
+                    for (;;) {
+                        bool act[R];
+                        int cc[R];
+                        bool any = false;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int i = lane + 64 * r;
+                            const uint32_t w = i < nv ? L[i] : kNotQueued;
+                            act[r] = !(w & kNotQueued) && __uint_as_float(w) < thr;
+                            cc[r] = 0;
+                            if (act[r]) {
+                                any = true;
+                                for (int e = RP[i]; e < RP[i + 1]; ++e) {
+                                    const int x = e - e_lo;
+                                    const uint32_t src = x < kBlkEmax ? A[x].x : radj[e].x;
+                                    if ((unsigned)((int)src - node0 - v0) >= (unsigned)nv) ++cc[r];
+                                }
+                            }
+                        }
+                        if (__ballot(any) == 0ull) break;
+                        // mailbox room: nodes in (r, lane) order take their cross-block
+                        // in-links while they fit; the rest stay queued for a later visit.
+                        // A node with more than half a mailbox of them ("big") takes one
+                        // of kBig slots instead and is relaxed in phase 2.
+                        bool big[R];
+                        int excl[R], bex[R];
+                        int base = 0, bbase = 0;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            big[r] = act[r] && cc[r] > kBlkMbx / 2;
+                            const int c1 = big[r] ? 0 : cc[r];
+                            int incl = c1;
+                            for (int o = 1; o < 64; o <<= 1) {
+                                const int y = __shfl_up(incl, o);
+                                if (lane >= o) incl += y;
+                            }
+                            excl[r] = base + incl - c1;
+                            base += __shfl(incl, 63);
+                            const unsigned long long bb = __ballot(big[r]);
+                            bex[r] = bbase + __popcll(bb & below);
+                            bbase += __popcll(bb);
+                        }
+                        bool fit[R];
+                        bool anyfit = false, anyskip = false;
+                        int used = 0, bused = 0;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            fit[r] = act[r] && (big[r] ? nbig + bex[r] < kBig : mcnt + excl[r] + cc[r] <= kBlkMbx);
+                            anyfit |= fit[r];
+                            anyskip |= act[r] && !fit[r];
+                            if (fit[r] && !big[r]) used = max(used, excl[r] + cc[r]);
+                            if (fit[r] && big[r]) bused = max(bused, bex[r] + 1);
+                        }
+                        for (int o = 32; o > 0; o >>= 1) {
+                            used = max(used, __shfl_xor(used, o));
+                            bused = max(bused, __shfl_xor(bused, o));
+                        }
+                        if (__ballot(anyskip) != 0ull) skipped = true;
+                        if (__ballot(anyfit) == 0ull) break;
+                        float du[R];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            du[r] = 0.0f;
+                            if (fit[r]) du[r] = __uint_as_float(atomicOr(&L[lane + 64 * r], kNotQueued) & kValueBits);
+                        }
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            if (!fit[r]) continue;
+                            const int i = lane + 64 * r;
+                            if (big[r]) BG[nbig + bex[r]] = make_uint2((uint32_t)(v0 + i), __float_as_uint(du[r]));
+                            int slot = mcnt + excl[r];
+                            for (int e = RP[i]; e < RP[i + 1]; ++e) {
+                                const int x = e - e_lo;
+                                const uint2 rec = x < kBlkEmax ? A[x] : radj[e];
+                                const int sv = (int)rec.x - node0;
+                                const float cd = du[r] + __uint_as_float(rec.y);
+                                const uint32_t cb = __float_as_uint(cd);
+                                const int jj = sv - v0;
+                                if ((unsigned)jj < (unsigned)nv) {
+                                    if (cb < (L[jj] & kValueBits)) atomicMin(&L[jj], cb);
+                                } else if (!big[r]) {
+                                    MB[slot++] = make_uint2((uint32_t)sv, cb);
+                                }
+                            }
+                        }
+                        mcnt += used;
+                        nbig += bused;
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                    // write the changed words back; a node first queued in this visit
+                    // at or above thr goes to the far queue
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int i = lane + 64 * r;
+                        const uint32_t w = i < nv ? L[i] : w0[r];
+                        if (w != w0[r]) D[v0 + i] = w;
+                        const bool far = i < nv && !(w & kNotQueued) && !(__uint_as_float(w) < thr);
+                        const bool tofar = far && !q0[r];
+                        if (far && w != w0[r]) atomicMin(&s_fm, w);
+                        const unsigned long long bf = __ballot(tofar);
+                        if (bf) {
+                            int fb = 0;
+                            if (lane == 0) fb = atomicAdd(&s_fn, __popcll(bf));
+                            fb = __shfl(fb, 0);
+                            if (tofar) farq[fcnt + fb + __popcll(bf & below)] = make_uint2((uint32_t)(v0 + i), w);
+                        }
+                    }
+                    if (skipped && lane == 0) push_block(b);
+                    if (lane == 0) {
+                        s_mc[j] = mcnt;
+                        s_nbig[j] = nbig;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                // ---- phase 2: the mailboxes into the labels in memory
+                auto apply = [&](int sv, uint32_t cb) {
+                    const uint32_t cur = ld_coherent(&D[sv]);
+                    if (cb < (cur & kValueBits)) {
+                        const uint32_t old = atomicMin(&D[sv], cb);
+                        const bool below_thr = __uint_as_float(cb) < thr;
+                        if (old & kNotQueued) {
+                            // this relaxation queued the node
+                            if (below_thr) {
+                                push_block(sv / B);
+                            } else {
+                                const int fp = atomicAdd(&s_fn, 1);
+                                farq[fcnt + fp] = make_uint2((uint32_t)sv, cb);
+                                atomicMin(&s_fm, cb);
+                            }
+                        } else if (!(__uint_as_float(old & kValueBits) < thr)) {
+                            if (below_thr) push_block(sv / B);   // a far node now below thr
+                            else atomicMin(&s_fm, cb);           // a far node improved
+                        }
+                    }
+                };
+                int mtot = 0, moff[KMAX];
+#pragma unroll
+                for (int w = 0; w < KMAX; ++w) {
+                    moff[w] = mtot;
+                    mtot += s_mc[w];
+                }
+                for (int g = tid; g < mtot; g += NT) {
+                    int w = 0;
+#pragma unroll
+                    for (int x = 1; x < KMAX; ++x)
+                        if (g >= moff[x]) w = x;
+                    const uint2 m = s_mb[w][g - moff[w]];
+                    apply((int)m.x, m.y);
+                }
+                // the big nodes' cross-block in-links, spread over the workgroup
+                for (int w = 0; w < KMAX; ++w) {
+                    for (int x = 0; x < s_nbig[w]; ++x) {
+                        const uint2 bg = s_big[w][x];
+                        const int u = (int)bg.x, ub = u / B;
+                        const float du = __uint_as_float(bg.y);
+                        for (int e = rptr[u] + tid; e < rptr[u + 1]; e += NT) {
+                            const uint2 rec = radj[e];
+                            const int sv = (int)rec.x - node0;
+                            if (sv / B != ub) apply(sv, __float_as_uint(du + __uint_as_float(rec.y)));
+                        }
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                fcnt += s_fn;
+                fmin = fminf(fmin, __uint_as_float(s_fm));
+                __syncthreads();
+                if (tid == 0) {
+                    s_fn = 0;
+                    s_fm = kInfBits;
+                }
+                __syncthreads();
+            }
+            // bucket [.., thr) drained: every label below thr is final
+            if (early) {
+                bool pend = false;
+                while (lcur < lend) {
+                    const int l = lcur + tid;
+                    bool p = false;
+                    if (l < lend) {
+                        const int o = dem.leg_orig[l] - node0;
+                        p = !(__uint_as_float(ld_coherent(&D[o]) & kValueBits) < thr);
+                    }
+                    if (__syncthreads_or(p)) { pend = true; break; }
+                    lcur += NT;
+                }
+                if (!pend) break;               // every origin is settled
+            }
+            if (fcnt == 0) break;
+            thr = fmaxf(thr, fmin) + delta;
+            if (!(thr > fmin)) thr = __uint_as_float(__float_as_uint(fmin) + 1u);
+            // move the far nodes below thr (keyed by their labels now) to the
+            // near queue; drop those taken since (flag set)
+            int keep = 0;
+            float km = __uint_as_float(kInfBits);
+            for (int i0 = 0; i0 < fcnt; i0 += NT) {
+                const int i = i0 + tid;
+                const bool h = i < fcnt;
+                uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                uint32_t cur = h ? ld_coherent(&D[ent.x]) : kNotQueued;
+                __syncthreads();                // the chunk is read before it is overwritten
+                const bool live = h && !(cur & kNotQueued);
+                ent.y = cur & kValueBits;
+                if (live && __uint_as_float(ent.y) < thr) {
+                    push_block((int)ent.x / B);
+                } else if (live) {
+                    farq[keep + atomicAdd(&s_fn, 1)] = ent;
+                    atomicMin(&s_fm, ent.y);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                const int fn = s_fn;
+                const float fm = __uint_as_float(s_fm);
+                __syncthreads();
+                if (tid == 0) {
+                    s_fn = 0;
+                    s_fm = kInfBits;
+                }
+                keep += fn;
+                km = fminf(km, fm);
+            }
+            __syncthreads();
+            fcnt = keep;
+            fmin = km;
+        }
+        __syncthreads();
+    }
+}
+
 // Bucket width per instance: delta = scale * (geometric mean link cost of the
 // instance).  The geometric mean follows the typical link; the arithmetic
 // mean is dominated by the few links that congestion makes very slow.
@@ -1317,6 +1715,23 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
     int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
+    if (variant >= 16) {
+        // block-local trees, one workgroup per tree (scratch slot = workgroup)
+        blocks = min(blocks, scr.nslots);
+        if (blocks <= 0) return hipErrorInvalidValue;
+        dim3 g(blocks), b(kWG);
+#define QDTA_SSSP_BLK(B, KB) \
+    hipLaunchKernelGGL((k_sssp_blk<B, KB>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, t_begin, \
+                       t_end)
+        switch (variant - 16) {
+            case 0: QDTA_SSSP_BLK(128, 1); break;
+            case 1: QDTA_SSSP_BLK(128, 2); break;
+            case 2: QDTA_SSSP_BLK(64, 2); break;
+            default: QDTA_SSSP_BLK(256, 1); break;
+        }
+#undef QDTA_SSSP_BLK
+        return hipGetLastError();
+    }
     if (variant >= 8) {
         // one workgroup per tree (scratch slot = workgroup)
         blocks = min(blocks, scr.nslots);

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -52,7 +53,15 @@ struct qdta_ctx {
     int cus = 256;
     std::vector<Instance> inst;
     bool net_dirty = true, dem_dirty = true;
-    std::vector<void*> allocs;
+    std::vector<void*> allocs;    // buffers this context got from hipMalloc
+    int64_t n_hip_malloc = 0;     // hipMalloc calls made (qdta_alloc_count)
+    // caller-owned workspace (qdta_bind_workspace): while one is bound, every
+    // device buffer is carved from it and hipMalloc is never called
+    char* ws_base = nullptr;
+    size_t ws_size = 0;
+    std::map<size_t, size_t> ws_free;   // offset -> length of each free run (coalesced)
+    std::map<size_t, size_t> ws_used;   // offset -> length of each carved buffer
+    int64_t ws_max_legs = 0, ws_max_dests = 0;  // maxima the workspace was sized for
 
     // network layout
     int64_t N = 0, M = 0;
@@ -122,6 +131,7 @@ struct qdta_ctx {
     int adj_J = -1;
     uint64_t adj_gen = 0, adj_solve = 0;
     bool adj_fwd = false;
+    uint64_t adj_fwd_id = 0;      // bumped by every model forward; a backward names the one it reverses
     int adj_is_root = 1, adj_beta = 4;
     double adj_ab = 0.15;
     std::vector<DBuf<int64_t>> adj_ptr;   // [J+1] offsets of each leg's path
@@ -153,38 +163,107 @@ int set_err(qdta_ctx* c, int code, const char* fmt, ...) {
     return code;
 }
 
+#define RC0(x)                  \
+    do {                        \
+        int rc0_ = (x);         \
+        if (rc0_ < 0) return rc0_; \
+    } while (0)
+
 #define HIPCHECK(ctx, expr)                                                                          \
     do {                                                                                             \
         hipError_t e_ = (expr);                                                                      \
         if (e_ != hipSuccess) return set_err(ctx, QDTA_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-template <class T>
-int dalloc(qdta_ctx* c, DBuf<T>& b, size_t n) {
-    if (b.p && b.n >= n && n > 0) return QDTA_OK;
-    if (b.p) {
-        (void)hipFree(b.p);
-        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)b.p);
-        if (it != c->allocs.end()) c->allocs.erase(it);
-        b.p = nullptr;
-        b.n = 0;
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Device memory: from the bound workspace (first fit over its free runs),
+// else from hipMalloc.
+int dev_alloc(qdta_ctx* c, size_t bytes, void** out) {
+    *out = nullptr;
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    if (c->ws_base) {
+        for (auto it = c->ws_free.begin(); it != c->ws_free.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            c->ws_free.erase(it);
+            if (len > bytes) c->ws_free[off + bytes] = len - bytes;
+            c->ws_used[off] = bytes;
+            *out = c->ws_base + off;
+            return QDTA_OK;
+        }
+        size_t largest = 0;
+        for (const auto& r : c->ws_free) largest = std::max(largest, r.second);
+        return set_err(c, QDTA_ENOMEM, "workspace too small: a buffer of %zu bytes does not fit (largest free run %zu "
+                       "of %zu bytes); query again and bind a larger workspace", bytes, largest, c->ws_size);
     }
-    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-    hipError_t e = hipMalloc((void**)&b.p, bytes);
+    hipError_t e = hipMalloc(out, bytes);
+    c->n_hip_malloc++;
     if (e != hipSuccess) {
-        b.p = nullptr;
+        *out = nullptr;
         (void)hipGetLastError();
         return set_err(c, QDTA_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
+    c->allocs.push_back(*out);
+    return QDTA_OK;
+}
+
+void dev_free(qdta_ctx* c, void* p) {
+    if (!p) return;
+    if (c->ws_base) {
+        auto u = c->ws_used.find((size_t)((char*)p - c->ws_base));
+        if (u == c->ws_used.end()) return;
+        size_t off = u->first, len = u->second;
+        c->ws_used.erase(u);
+        auto nx = c->ws_free.lower_bound(off);
+        if (nx != c->ws_free.end() && nx->first == off + len) {   // merge with the next run
+            len += nx->second;
+            nx = c->ws_free.erase(nx);
+        }
+        if (nx != c->ws_free.begin()) {                            // and the previous one
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += len;
+                return;
+            }
+        }
+        c->ws_free[off] = len;
+        return;
+    }
+    (void)hipFree(p);
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+}
+
+template <class T>
+void dfree(qdta_ctx* c, DBuf<T>& b) {
+    dev_free(c, (void*)b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+template <class T>
+int dalloc(qdta_ctx* c, DBuf<T>& b, size_t n) {
+    if (b.p && b.n >= n && n > 0) return QDTA_OK;
+    if (b.p) dfree(c, b);
+    void* p = nullptr;
+    RC0(dev_alloc(c, std::max<size_t>(n, 1) * sizeof(T), &p));
+    b.p = (T*)p;
     b.n = std::max<size_t>(n, 1);
-    c->allocs.push_back((void*)b.p);
     c->gen++;
     return QDTA_OK;
 }
 
+// With a workspace bound, buffers sized by the demand are carved at the
+// maxima the workspace was sized for (qdta_workspace_query), so later
+// intervals reuse them instead of carving again.
+size_t plan_legs(const qdta_ctx* c, size_t n) { return c->ws_base ? std::max<size_t>(n, (size_t)c->ws_max_legs) : n; }
+size_t plan_dests(const qdta_ctx* c, size_t n) { return c->ws_base ? std::max<size_t>(n, (size_t)c->ws_max_dests) : n; }
+
 template <class T>
-int upload(qdta_ctx* c, DBuf<T>& b, const std::vector<T>& h) {
-    int rc = dalloc(c, b, h.size());
+int upload(qdta_ctx* c, DBuf<T>& b, const std::vector<T>& h, size_t min_n = 0) {
+    int rc = dalloc(c, b, std::max(h.size(), min_n));
     if (rc) return rc;
     if (!h.empty()) HIPCHECK(c, hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     return QDTA_OK;
@@ -213,6 +292,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     if (o->max_iter < 0 || o->fixed_iters < 0) { set_err(c, QDTA_EARG, "negative iteration count"); return false; }
     if (o->waves_per_cu < 0 || o->waves_per_cu > 32) { set_err(c, QDTA_EARG, "waves_per_cu must be in 0..32"); return false; }
     if (o->sssp_shape < 0 || o->sssp_shape > 6) { set_err(c, QDTA_EARG, "sssp_shape must be in 0..6"); return false; }
+    if (o->sssp_kernel < 0 || o->sssp_kernel > 2) { set_err(c, QDTA_EARG, "sssp_kernel must be 0, 1 or 2"); return false; }
     if (o->launch_form < 0 || o->launch_form > 2) { set_err(c, QDTA_EARG, "launch_form must be 0, 1 or 2"); return false; }
     if (o->tree_waves != 0 && o->tree_waves != 1 && o->tree_waves != 4) {
         set_err(c, QDTA_EARG, "tree_waves must be 0, 1 or 4");
@@ -229,18 +309,32 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     return true;
 }
 
-int tree_waves(const qdta_opts* o) { return o->tree_waves == 1 ? 1 : 4; }
+// wavefronts per tree: one only for the node-queue kernel asked to run one
+// tree per wavefront; the block-local kernel always takes a workgroup
+int tree_waves(const qdta_opts* o) { return (o->sssp_kernel != 2 && o->tree_waves == 1) ? 1 : 4; }
+// FW updates a solve may apply (iterates 1..this, plus the initial AON)
+int hist_iters(const qdta_opts* o) { return o->fixed_iters > 0 ? o->fixed_iters : std::max(o->max_iter, 0); }
 int waves_per_cu(const qdta_opts* o) {
     if (o->waves_per_cu) return o->waves_per_cu;
     return tree_waves(o) == 1 ? 32 : 24;
 }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
-// Shortest-path kernel shape index (see qdta_opts.sssp_shape): default (4,4).
-// Kernel variants 0-5: one wavefront per tree; 8-13: one workgroup per tree
-// (the default).
-int sssp_variant(const qdta_opts* o) {
+// Block size of each block-local shape (qdta_opts.sssp_shape 1..4)
+int blk_nodes(int shape) { return shape == 3 ? 64 : shape == 4 ? 256 : 128; }
+// Shortest-path kernel variant (see qdta_opts.sssp_kernel / sssp_shape).
+// Variants 0-5: node queue, one wavefront per tree; 8-13: node queue, one
+// workgroup per tree; 16-19: block-local, one workgroup per tree.  The
+// block-local kernel needs every instance within its block bitmap.
+int sssp_variant(const qdta_ctx* c, const qdta_opts* o) {
+    int64_t nmax = 0;
+    for (const Instance& I : c->inst) nmax = std::max<int64_t>(nmax, I.n);
+    const bool fits = nmax <= (int64_t)kBlkMaxBits * blk_nodes(o->sssp_shape);
+    if (o->sssp_kernel == 2 && fits) {
+        const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 4) ? o->sssp_shape - 1 : 1;
+        return 16 + v;
+    }
     const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2;
-    return o->tree_waves == 1 ? v : v + 8;
+    return tree_waves(o) == 1 ? v : v + 8;
 }
 
 // ---------------------------------------------------------------------------
@@ -399,7 +493,8 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
 // wpc = 0: the demand tables only (no shortest-path scratch).
 int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     RC(ensure_network(c));
-    if (!c->dem_dirty) return wpc > 0 ? ensure_scratch(c, c->Q, c->nmax, wpc, tw) : QDTA_OK;
+    if (!c->dem_dirty) return wpc > 0 ? ensure_scratch(c, (int64_t)plan_dests(c, (size_t)c->Q), c->nmax, wpc, tw)
+                                      : QDTA_OK;
     int64_t total_legs = 0;
     for (const Instance& I : c->inst) total_legs += (int64_t)I.orig.size();
     if (total_legs >= INT32_MAX) return set_err(c, QDTA_EARG, "total legs beyond int32 ids");
@@ -447,19 +542,20 @@ int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     c->h_dest_inst = dest_inst;
     c->h_dest_node = dest_node;
     c->h_qptr = qptr;
-    RC(upload(c, c->dest_node, dest_node));
-    RC(upload(c, c->dest_inst, dest_inst));
-    RC(upload(c, c->dest_lab, dest_lab));
-    RC(upload(c, c->qptr, qptr));
-    RC(upload(c, c->leg_orig, leg_orig));
-    RC(upload(c, c->leg_dfx, leg_dfx));
-    RC(upload(c, c->leg_q, leg_q));
+    const size_t pq = plan_dests(c, (size_t)c->Q), pp = plan_legs(c, (size_t)c->P);
+    RC(upload(c, c->dest_node, dest_node, pq));
+    RC(upload(c, c->dest_inst, dest_inst, pq));
+    RC(upload(c, c->dest_lab, dest_lab, pq));
+    RC(upload(c, c->qptr, qptr, pq + 1));
+    RC(upload(c, c->leg_orig, leg_orig, pp));
+    RC(upload(c, c->leg_dfx, leg_dfx, pp));
+    RC(upload(c, c->leg_q, leg_q, pp));
     RC(upload(c, c->d_inst, c->h_inst));
-    RC(dalloc(c, c->labels, c->label_count));
-    RC(dalloc(c, c->absorb_q, (size_t)c->Q));
-    RC(dalloc(c, c->int_node, (size_t)c->P));
-    RC(dalloc(c, c->int_tau, (size_t)c->P));
-    if (wpc > 0) RC(ensure_scratch(c, c->Q, nmax, wpc, tw));
+    RC(dalloc(c, c->labels, std::max(c->label_count, c->ws_base ? pq * (size_t)tree_words(nmax) : 0)));
+    RC(dalloc(c, c->absorb_q, pq));
+    RC(dalloc(c, c->int_node, pp));
+    RC(dalloc(c, c->int_tau, pp));
+    if (wpc > 0) RC(ensure_scratch(c, (int64_t)pq, nmax, wpc, tw));
     c->dem_dirty = false;
     c->solved = false;
     c->lab_hist_ok.clear();
@@ -568,10 +664,10 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, const float* ti
         HIPCHECK(c, launch_delta(c->stream, net, cost, delta_scale(o), c->delta_inst.p, c->logsum.p));
         for (int64_t t = 0; t < c->Q; ++t)
             HIPCHECK(c, launch_trees(c->stream, net, dem, c->radj.p, c->labels.p, scr_view(c), 4, st, c->delta_inst.p,
-                                     sssp_variant(o), 1, (int)t, (int)t + 1));
+                                     sssp_variant(c, o), 1, (int)t, (int)t + 1));
     } else {
         HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->radj.p, c->labels.p, scr_view(c), c->slots, st,
-                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
+                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(c, o), 1));
     }
     if (marks) RC(prof_mark(c, PH_SSSP, 1));
     if (marks) RC(prof_mark(c, PH_WALK, 0));
@@ -689,15 +785,32 @@ int plan_label_history(qdta_ctx* c, const qdta_opts* o) {
     c->lab_hist_ok.clear();
     const size_t per = c->label_count;
     if (per == 0 || o->history_mib < 0) return QDTA_OK;
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-        (void)hipGetLastError();
-        return QDTA_OK;
+    size_t avail = 0, reserve = 0;
+    if (c->ws_base) {
+        // the workspace's largest free run once the current history is given
+        // back, less what the residual pass has still to carve
+        dfree(c, c->lab_hist);
+        for (const auto& r : c->ws_free) avail = std::max(avail, r.second);
+        const int ni = (int)c->inst.size();
+        const size_t hcap = (size_t)(hist_iters(o) + 1) * ni;
+        const size_t rn = plan_legs(c, (size_t)std::max<int64_t>(c->P, 1));
+        if (c->r_dense.n < c->label_count) reserve += align_up(c->label_count * sizeof(int64_t));
+        if (c->st_hist.n < hcap) reserve += align_up(hcap * sizeof(InstState));
+        if (c->lam_hist.n < hcap) reserve += align_up(hcap * sizeof(double));
+        if (c->r_cnt.n < plan_dests(c, (size_t)std::max<int64_t>(c->Q, 1)))
+            reserve += align_up(plan_dests(c, (size_t)std::max<int64_t>(c->Q, 1)) * sizeof(int64_t));
+        if (c->r_orig.n < rn) reserve += 2 * align_up(rn * sizeof(int32_t)) + align_up(rn * sizeof(int64_t));
+    } else {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            return QDTA_OK;
+        }
+        avail = free_b + c->lab_hist.n * sizeof(label_t);
+        reserve = (size_t)16 << 30;
+        if (c->r_dense.n < c->label_count) reserve += (c->label_count - c->r_dense.n) * sizeof(int64_t);
+        reserve += (size_t)c->P * 16;
     }
-    size_t avail = free_b + c->lab_hist.n * sizeof(label_t);
-    size_t reserve = (size_t)16 << 30;
-    if (c->r_dense.n < c->label_count) reserve += (c->label_count - c->r_dense.n) * sizeof(int64_t);
-    reserve += (size_t)c->P * 16;
     if (avail <= reserve) return QDTA_OK;
     size_t budget = avail - reserve;
     if (o->history_mib > 0) budget = std::min(budget, (size_t)o->history_mib << 20);
@@ -706,13 +819,7 @@ int plan_label_history(qdta_ctx* c, const qdta_opts* o) {
     slots = std::min<size_t>(std::min<size_t>(slots, want), 64);
     if (slots == 0) return QDTA_OK;
     if (c->lab_hist.n < slots * per) {
-        if (c->lab_hist.p) {
-            (void)hipFree(c->lab_hist.p);
-            auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->lab_hist.p);
-            if (it != c->allocs.end()) c->allocs.erase(it);
-            c->lab_hist.p = nullptr;
-            c->lab_hist.n = 0;
-        }
+        dfree(c, c->lab_hist);
         if (dalloc(c, c->lab_hist, slots * per) != QDTA_OK) {   // not fatal: recompute instead
             c->err.clear();
             return QDTA_OK;
@@ -741,9 +848,7 @@ int ensure_history(qdta_ctx* c, size_t iters) {
                                    hipMemcpyDeviceToDevice, c->stream));
     if (c->hist_cost.p) {
         HIPCHECK(c, hipStreamSynchronize(c->stream));
-        (void)hipFree(c->hist_cost.p);
-        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->hist_cost.p);
-        if (it != c->allocs.end()) c->allocs.erase(it);
+        dfree(c, c->hist_cost);
     }
     c->hist_cost = nb;
     c->hist_iters_cap = want;
@@ -853,6 +958,93 @@ int qdta_destroy(qdta_ctx* c) {
 int qdta_set_stream(qdta_ctx* c, void* stream) {
     if (!c) return QDTA_EARG;
     c->stream = (hipStream_t)stream;
+    return QDTA_OK;
+}
+
+int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int64_t max_dests, size_t* bytes) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (!bytes || max_legs < 0 || max_dests < 0) return set_err(c, QDTA_EARG, "bad arguments");
+    if (c->inst.empty()) return set_err(c, QDTA_ESTATE, "no network added");
+    // sizes from the host copies of the networks and the current demand, as
+    // ensure_network / ensure_demand / ensure_scratch / the FW and residual
+    // passes will carve them (every buffer rounded up to 256 bytes)
+    const int ni = (int)c->inst.size();
+    int64_t N = 0, M = 0, nblk = 0, Q = 0, P = 0, nmax = 0, words = 0;
+    for (const Instance& I : c->inst) {
+        N += I.n;
+        M += I.m;
+        nblk += (I.m + kChunk - 1) / kChunk;
+        nmax = std::max<int64_t>(nmax, I.n);
+        int64_t q = 0;
+        for (size_t p = 0; p < I.orig.size(); ++p)
+            if (p == 0 || I.dest[p] != I.dest[p - 1]) ++q;
+        Q += q;
+        P += (int64_t)I.orig.size();
+        words += q * tree_words(I.n);
+    }
+    if (N >= INT32_MAX || M >= INT32_MAX) return set_err(c, QDTA_EARG, "total size beyond int32 ids");
+    const size_t pq = (size_t)std::max(Q, max_dests), pp = (size_t)std::max(P, max_legs);
+    const size_t labels = std::max<size_t>((size_t)words, pq * (size_t)tree_words(nmax));
+    size_t b = 0;
+    auto add = [&](size_t n, size_t sz) { b += align_up(std::max<size_t>(n, 1) * sz); };
+    // network and Frank-Wolfe state
+    add(N + 1, 4); add(M, 4); add(M, 4); add(M, 4); add(N + 1, 4); add(M, 4); add(M, 4); add(M, 4);
+    add(nblk, 4); add(nblk, 4); add(ni, sizeof(InstDev));
+    add(M, 8); add(M, 8); add(M, 4); add(M, 8); add(M, 8); add(M, 4); add(M, 4);
+    add(ni, sizeof(InstState)); add((size_t)ni * 6, 8); add((size_t)ni * kMaxK * 6, 8); add((size_t)ni * kMaxK, 8);
+    add(ni, 8); add(4, 4); add(ni, 8);
+    // demand tables and shortest-path labels
+    add(pq, 4); add(pq, 4); add(pq, 8); add(pq + 1, 4); add(pp, 4); add(pp, 8); add(pp, 4);
+    add(labels, 4); add(pq, 4); add(pp, 4); add(pp, 4);
+    // shortest-path scratch (as ensure_scratch sizes it)
+    {
+        const int tw = tree_waves(o), wpc = waves_per_cu(o);
+        int slots = (int)std::min<int64_t>(std::max<int64_t>((int64_t)pq, 1) * (tw == 1 ? 1 : 4),
+                                           (int64_t)c->cus * wpc);
+        slots = (slots + 3) / 4 * 4;
+        const int64_t need = tw == 1 ? slots : slots / 4;
+        const int64_t nm = std::max<int64_t>(nmax, 1) + 65;
+        add((size_t)(need * nm), 4); add((size_t)(need * nm * 2), 4);
+        add(1, 4); add(ni, 4); add(ni, 8);
+    }
+    if (o->keep_history) {
+        const size_t hcap = (size_t)(hist_iters(o) + 1);
+        add((hcap + 1) * (size_t)M, 4);                             // per-iterate costs
+        add(hcap * ni, sizeof(InstState)); add(hcap * ni, 8);       // residual pass: states, weights
+        add(labels, 8); add(pq, 8); add(pp, 4); add(pp, 4); add(pp, 8);  // accumulator, counts, legs out
+        if (o->history_mib > 0) b += align_up((size_t)o->history_mib << 20);
+    }
+    c->ws_max_legs = (int64_t)pp;
+    c->ws_max_dests = (int64_t)pq;
+    *bytes = b;
+    return QDTA_OK;
+}
+
+int qdta_bind_workspace(qdta_ctx* c, void* dev_ptr, size_t bytes) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (c->ws_base || !c->allocs.empty())
+        return set_err(c, QDTA_ESTATE, "bind the workspace once, before any call that uses device memory");
+    if (!dev_ptr || bytes == 0 || ((uintptr_t)dev_ptr % kAlign) != 0)
+        return set_err(c, QDTA_EARG, "workspace must be a non-empty device range aligned to %zu bytes", kAlign);
+    c->ws_base = (char*)dev_ptr;
+    c->ws_size = bytes / kAlign * kAlign;
+    c->ws_free.clear();
+    c->ws_used.clear();
+    c->ws_free[0] = c->ws_size;
+    return QDTA_OK;
+}
+
+int qdta_alloc_count(const qdta_ctx* c, int64_t* hip_mallocs, size_t* ws_in_use) {
+    if (!c) return QDTA_EARG;
+    if (hip_mallocs) *hip_mallocs = c->n_hip_malloc;
+    if (ws_in_use) {
+        size_t u = 0;
+        for (const auto& r : c->ws_used) u += r.second;
+        *ws_in_use = u;
+    }
     return QDTA_OK;
 }
 
@@ -1030,12 +1222,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     DBuf<int64_t> ddl;
     DBuf<label_t> lab;
     auto cleanup = [&]() {
-        for (void* p : {(void*)ddn.p, (void*)ddi.p, (void*)aq.p, (void*)ddl.p, (void*)lab.p}) {
-            if (!p) continue;
-            (void)hipFree(p);
-            auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
-            if (it != c->allocs.end()) c->allocs.erase(it);
-        }
+        for (void* p : {(void*)ddn.p, (void*)ddi.p, (void*)aq.p, (void*)ddl.p, (void*)lab.p}) dev_free(c, p);
     };
     int rc = QDTA_OK;
     do {
@@ -1062,7 +1249,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         if ((e = launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p)))
             { rc = set_err(c, QDTA_EHIP, "scatter: %s", hipGetErrorString(e)); break; }
         if ((e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, lab.p, scr_view(c), slots, nullptr,
-                             delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 0)))
+                             delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(c, o), 0)))
             { rc = set_err(c, QDTA_EHIP, "sssp: %s", hipGetErrorString(e)); break; }
         if ((e = launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(aq.p), 0u, nq)))
             { rc = set_err(c, QDTA_EHIP, "fill: %s", hipGetErrorString(e)); break; }
@@ -1167,7 +1354,8 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
     c->solve_id++;
-    if (o->keep_history) RC(ensure_history(c, 8));
+    // costs of iterates 0..cap+1 (the last one is tested, not applied)
+    if (o->keep_history) RC(ensure_history(c, c->ws_base ? (size_t)hist_iters(o) + 2 : 8));
     for (Instance& I : c->inst) {
         I.hist_alpha.assign(1, 1.0);
         I.solved_iters = -1;
@@ -1418,7 +1606,7 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
         hipError_t e = hipEventRecord(e0, c->stream);
         if (e == hipSuccess)
             e = launch_sssp(c->stream, net, dem, c->cost.p, c->radj.p, c->labels.p, scr_view(c), ts, nullptr,
-                            delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(&t), 1);
+                            delta_scale(&t), c->delta_inst.p, c->logsum.p, sssp_variant(c, &t), 1);
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -1521,8 +1709,10 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
             any[j] |= s.active != 0;
         }
     }
-    RC(dalloc(c, c->st_hist, hst.size()));
-    RC(dalloc(c, c->lam_hist, hlam.size()));
+    // with a workspace: room for every iterate the options allow, carved once
+    const size_t hcap = c->ws_base ? (size_t)(hist_iters(o) + 1) * ni : hst.size();
+    RC(dalloc(c, c->st_hist, std::max(hst.size(), hcap)));
+    RC(dalloc(c, c->lam_hist, std::max(hlam.size(), hcap)));
     HIPCHECK(c, hipMemcpy(c->st_hist.p, hst.data(), sizeof(InstState) * hst.size(), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->lam_hist.p, hlam.data(), sizeof(double) * hlam.size(), hipMemcpyHostToDevice));
     {
@@ -1552,7 +1742,7 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
             lab = c->lab_hist.p + (size_t)j * c->label_count;    // the solve's own trees of iterate j
         } else {
             HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, stj,
-                                    delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
+                                    delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(c, o), 1));
         }
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
         HIPCHECK(c, launch_walk(c->stream, net, dem, lab, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
@@ -1562,7 +1752,7 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
                                     lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0));
     }
     // compact: legs per tree, offsets, then the legs in (destination, origin) order
-    RC(dalloc(c, c->r_cnt, (size_t)std::max<int64_t>(c->Q, 1)));
+    RC(dalloc(c, c->r_cnt, plan_dests(c, (size_t)std::max<int64_t>(c->Q, 1))));
     HIPCHECK(c, launch_resid_count(c->stream, net, dem, c->r_dense.p, c->r_cnt.p));
     std::vector<int64_t> cnt((size_t)c->Q), off((size_t)c->Q);
     if (c->Q) HIPCHECK(c, hipMemcpyAsync(cnt.data(), c->r_cnt.p, sizeof(int64_t) * c->Q, hipMemcpyDeviceToHost,
@@ -1573,9 +1763,10 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         off[t] = total;
         total += cnt[t];
     }
-    RC(dalloc(c, c->r_orig, (size_t)std::max<int64_t>(total, 1)));
-    RC(dalloc(c, c->r_dest, (size_t)std::max<int64_t>(total, 1)));
-    RC(dalloc(c, c->r_w, (size_t)std::max<int64_t>(total, 1)));
+    const size_t rn = plan_legs(c, (size_t)std::max<int64_t>(total, 1));
+    RC(dalloc(c, c->r_orig, rn));
+    RC(dalloc(c, c->r_dest, rn));
+    RC(dalloc(c, c->r_w, rn));
     if (c->Q) HIPCHECK(c, hipMemcpy(c->r_cnt.p, off.data(), sizeof(int64_t) * c->Q, hipMemcpyHostToDevice));
     HIPCHECK(c, launch_resid_write(c->stream, net, dem, c->r_dense.p, c->r_cnt.p, c->r_orig.p, c->r_dest.p,
                                    c->r_w.p));
@@ -1673,7 +1864,7 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
             lab = c->lab_hist.p + (size_t)j * c->label_count;   // the solve's own trees of iterate j
         } else {
             HIPCHECK(c, launch_sssp(c->stream, net, dem, cj, c->radj.p, c->labels.p, scr_view(c), c->slots, nullptr,
-                                    delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(o), 1));
+                                    delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(c, o), 1));
         }
         RC(clear_flags(c));
         HIPCHECK(c, launch_path_walk(c->stream, net, dem, lab, nullptr, nullptr, nullptr, c->adj_len.p,
@@ -1703,7 +1894,8 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
     return QDTA_OK;
 }
 
-int qdta_model_forward(qdta_ctx* c, const qdta_opts* o, const double* d, const float* cap, double* f_out) {
+int qdta_model_forward(qdta_ctx* c, const qdta_opts* o, const double* d, const float* cap, double* f_out,
+                       uint64_t* fwd_id_out) {
     if (!c) return QDTA_EARG;
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
@@ -1738,16 +1930,21 @@ int qdta_model_forward(qdta_ctx* c, const qdta_opts* o, const double* d, const f
     RC(read_flags(c, h));
     RC(flag_code(c, h));
     c->adj_fwd = true;
+    c->adj_fwd_id++;
+    if (fwd_id_out) *fwd_id_out = c->adj_fwd_id;
     c->adj_is_root = o->ls_mode != QDTA_LS_MSA;
     c->adj_ab = o->alpha;
     c->adj_beta = o->beta;
     return QDTA_OK;
 }
 
-int qdta_model_backward(qdta_ctx* c, const double* fbar, double* dbar, double* capbar) {
+int qdta_model_backward(qdta_ctx* c, uint64_t fwd_id, const double* fbar, double* dbar, double* capbar) {
     if (!c) return QDTA_EARG;
     c->err.clear();
     if (!adj_valid(c) || !c->adj_fwd) return set_err(c, QDTA_ESTATE, "backward needs a model forward pass first");
+    if (fwd_id != c->adj_fwd_id)
+        return set_err(c, QDTA_ESTATE, "backward of forward %llu, but the context holds forward %llu's iterates",
+                       (unsigned long long)fwd_id, (unsigned long long)c->adj_fwd_id);
     if (!fbar || !dbar || !capbar) return set_err(c, QDTA_EARG, "null array");
     const int64_t M = c->M;
     const int P = (int)c->P, J = c->adj_J;

@@ -8,7 +8,6 @@ loudly when the library has not been built -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 
 import numpy as np
@@ -30,7 +29,8 @@ EXPORTS = [
     "qdta_get_legs", "qdta_ls_eval", "qdta_line_search", "qdta_fw_update", "qdta_solve", "qdta_get_flows",
     "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_set_residual", "qdta_adjoint_record",
     "qdta_model_forward", "qdta_model_backward", "qdta_fw_begin", "qdta_fw_step",
-    "qdta_profile_enable", "qdta_profile_read", "qdta_autotune",
+    "qdta_profile_enable", "qdta_profile_read", "qdta_autotune", "qdta_workspace_query", "qdta_bind_workspace",
+    "qdta_alloc_count",
 ]
 PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
 
@@ -42,7 +42,7 @@ class Opts(C.Structure):
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("sssp_shape", C.c_int32),
                 ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("history_mib", C.c_int32),
-                ("objective", C.c_int32)]
+                ("objective", C.c_int32), ("sssp_kernel", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -78,6 +78,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not built: run paper_2104_12911_amd/build.py (hipcc, gfx950)")
+        # torch supplies the device memory and the streams, so the library must
+        # run on torch's HIP runtime: load torch first, so that the runtime the
+        # library links against (same soname) resolves to the one torch loaded
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.qdta_default_opts.argtypes = [vp]
@@ -107,8 +111,11 @@ def lib():
         L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64)]
         L.qdta_set_residual.argtypes = [vp, i32, i64, vp, vp, vp]
         L.qdta_adjoint_record.argtypes = [vp, vp]
-        L.qdta_model_forward.argtypes = [vp, vp, vp, vp, vp]
-        L.qdta_model_backward.argtypes = [vp, vp, vp, vp]
+        L.qdta_model_forward.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_uint64)]
+        L.qdta_model_backward.argtypes = [vp, C.c_uint64, vp, vp, vp]
+        L.qdta_workspace_query.argtypes = [vp, vp, i64, i64, C.POINTER(C.c_size_t)]
+        L.qdta_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+        L.qdta_alloc_count.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_size_t)]
         L.qdta_fw_begin.argtypes = [vp, vp]
         L.qdta_fw_step.argtypes = [vp, vp, vp, C.POINTER(i32)]
         L.qdta_profile_enable.argtypes = [vp, i32]
@@ -302,29 +309,49 @@ class Context:
         return self._rc(lib().qdta_adjoint_record(self._h, C.byref(opts)))
 
     def model_forward(self, opts, d, cap, f_out):
+        """Forward pass of the frozen-path model; returns its id (for model_backward)."""
         li = self.layout()
         _check_tensor(d, "float64", li.total_legs, "d")
         if cap is not None:
             _check_tensor(cap, "float32", li.total_links, "cap")
         _check_tensor(f_out, "float64", li.total_links, "f_out")
-        return self._rc(lib().qdta_model_forward(self._h, C.byref(opts), _ptr(d), _ptr(cap), _ptr(f_out)))
+        fid = C.c_uint64(0)
+        self._rc(lib().qdta_model_forward(self._h, C.byref(opts), _ptr(d), _ptr(cap), _ptr(f_out), C.byref(fid)))
+        return fid.value
 
-    def model_backward(self, fbar, dbar, capbar):
+    def model_backward(self, fwd_id, fbar, dbar, capbar):
         li = self.layout()
         _check_tensor(fbar, "float64", li.total_links, "fbar")
         _check_tensor(dbar, "float64", li.total_legs, "dbar")
         _check_tensor(capbar, "float64", li.total_links, "capbar")
-        return self._rc(lib().qdta_model_backward(self._h, _ptr(fbar), _ptr(dbar), _ptr(capbar)))
+        return self._rc(lib().qdta_model_backward(self._h, int(fwd_id), _ptr(fbar), _ptr(dbar), _ptr(capbar)))
+
+    def workspace_query(self, opts, max_legs=0, max_dests=0):
+        """Bytes of device memory the context needs for its networks, the
+        current demand (or max_legs / max_dests if larger) and opts."""
+        b = C.c_size_t(0)
+        self._rc(lib().qdta_workspace_query(self._h, C.byref(opts), int(max_legs), int(max_dests), C.byref(b)))
+        return b.value
+
+    def bind_workspace(self, ws):
+        """Carve every device buffer from ws (a uint8 torch tensor the caller
+        owns and keeps alive); the library then never calls hipMalloc."""
+        if str(ws.dtype) != "torch.uint8" or not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+        self._ws = ws
+        return self._rc(lib().qdta_bind_workspace(self._h, C.c_void_p(ws.data_ptr()), ws.numel()))
+
+    def alloc_count(self):
+        """(hipMalloc calls made by this context, workspace bytes in use)."""
+        n, u = C.c_int64(0), C.c_size_t(0)
+        self._rc(lib().qdta_alloc_count(self._h, C.byref(n), C.byref(u)))
+        return n.value, u.value
 
     def set_residual(self, inst, orig, dest, w_fx):
         o, d, w = _np(orig, np.int32), _np(dest, np.int32), _np(w_fx, np.int64)
         if not (len(o) == len(d) == len(w)):
             raise ValueError("residual arrays differ in length")
         self._rc(lib().qdta_set_residual(self._h, int(inst), len(o), _ptr(o), _ptr(d), _ptr(w)))
-
-
-def kappa(dt_s: float) -> float:
-    return 3600.0 / dt_s if math.isfinite(dt_s) else 1.0
 
 
 def _frozen_path_flows_class():
@@ -334,14 +361,16 @@ def _frozen_path_flows_class():
         """f = M(d, C): the link flows (veh) of a solved interval's Frank-Wolfe
         updates replayed on their frozen paths (qdta_model_forward), with the
         reverse pass of qdta_model_backward.  Needs Context.adjoint_record
-        after the solve; the backward belongs to the most recent forward of
-        that context."""
+        after the solve.  The context keeps the iterates of its last forward
+        pass only: the backward of an earlier one raises (QDTA_ESTATE)
+        instead of returning another pass's gradients."""
 
         @staticmethod
         def forward(ctx, qctx, opts, d, cap):
             li = qctx.layout()
             f = torch.empty(li.total_links, dtype=torch.float64, device=d.device)
-            qctx.model_forward(opts, d.detach().contiguous(), None if cap is None else cap.detach().contiguous(), f)
+            ctx.fwd_id = qctx.model_forward(opts, d.detach().contiguous(),
+                                            None if cap is None else cap.detach().contiguous(), f)
             ctx.qctx = qctx
             ctx.cap_dtype = None if cap is None else cap.dtype
             return f
@@ -352,7 +381,7 @@ def _frozen_path_flows_class():
             li = qctx.layout()
             dbar = torch.empty(li.total_legs, dtype=torch.float64, device=fbar.device)
             capbar = torch.empty(li.total_links, dtype=torch.float64, device=fbar.device)
-            qctx.model_backward(fbar.to(torch.float64).contiguous(), dbar, capbar)
+            qctx.model_backward(ctx.fwd_id, fbar.to(torch.float64).contiguous(), dbar, capbar)
             return None, None, dbar, (None if ctx.cap_dtype is None else capbar.to(ctx.cap_dtype))
 
     return FrozenPathFlows

@@ -53,6 +53,35 @@ def i128(lo, hi):
     return (int(hi) << 64) | (int(lo) & ((1 << 64) - 1))
 
 
+def orc_legs(orc, ctx, dems):
+    """The oracle's own quantisation and merge of each instance's demand;
+    asserts that the library holds exactly these legs, and returns the
+    oracle's copy (concatenated over instances) for the oracle to use."""
+    parts = [orc.demand_legs(dm.orig, dm.dest, dm.trips) for dm in dems]
+    o = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, np.int32)
+    d = np.concatenate([p[1] for p in parts]) if parts else np.zeros(0, np.int32)
+    w = np.concatenate([p[2] for p in parts]) if parts else np.zeros(0, np.int64)
+    lo, ld, lw = ctx.legs()
+    assert np.array_equal(lo, o) and np.array_equal(ld, d) and np.array_equal(lw, w)
+    return o, d, w
+
+
+class _Dem:
+    def __init__(self, orig, dest, trips):
+        self.orig, self.dest, self.trips = np.asarray(orig), np.asarray(dest), np.asarray(trips, np.float64)
+
+
+def fp64_check(st, ref):
+    """The reported gap and objective against the oracle's FP64 reference of
+    the same iterate (long double, no FP32 costs, no quantised terms): within
+    1e-6 (the gap in absolute terms, being relative already; the objective
+    relatively)."""
+    dg = abs(st["gap"] - ref.gap_fp64)
+    do = abs(st["objective"] - ref.objective_fp64) / abs(ref.objective_fp64)
+    assert dg <= 1e-6 and do <= 1e-6, (dg, do)
+    return dg, do
+
+
 # ---------------------------------------------------------------------------
 # A1 -- BPR
 # ---------------------------------------------------------------------------
@@ -168,11 +197,16 @@ def test_trees_metro_network_sample(torch_dev, q, orc):
 # ---------------------------------------------------------------------------
 # A2 + A3 -- all-or-nothing with truncation
 # ---------------------------------------------------------------------------
+def _orc():
+    import oracle
+    return oracle
+
+
 def _aon(torch, q, net, cost, orig, dest, trips, dt, rule, ds=0.0):
     with q.Context() as ctx:
         ctx.add(net)
         ctx.set_demand(0, orig, dest, trips, dt)
-        o, d, wfx = ctx.legs()
+        o, d, wfx = orc_legs(_orc(), ctx, [_Dem(orig, dest, trips)])
         y = torch.empty(net.m, dtype=torch.int64, device="cuda")
         stop = torch.empty(max(len(o), 1), dtype=torch.int32, device="cuda")
         rc = ctx.aon(q.default_opts(trunc_rule=rule, delta_scale=ds), dev(torch, cost.astype(np.float32)), y,
@@ -345,7 +379,7 @@ def _solve(torch, q, nets_dems, opts):
         f = torch.empty(li.total_links, dtype=torch.int64, device="cuda")
         ctx.get_flows(f)
         off = ctx.offsets()
-        legs = ctx.legs()
+        legs = orc_legs(_orc(), ctx, [dem for _, dem in nets_dems])
         return st, host(f), off, legs, rc
 
 
@@ -355,6 +389,7 @@ def _cmp_fw(st, fo, gpu_f, ref):
     assert st["gap"] == ref.gap
     assert abs(st["objective"] - ref.objective) <= 1e-12 * abs(ref.objective)
     assert st["ls_evals"] == ref.ls_evals
+    fp64_check(st, ref)
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
@@ -396,6 +431,7 @@ def test_config3_peak_full_size(torch_dev, q, orc):
     assert np.array_equal(f, ref.f)
     assert st[0]["gap"] == ref.gap
     assert st[0]["iters"] == ref.iters
+    fp64_check(st[0], ref)
 
 
 def test_config4_full_batch_sampled(torch_dev, q, orc):
@@ -667,7 +703,7 @@ def test_autotune_picks_valid_options_and_results_do_not_move(torch_dev, q, orc)
         st, rc = ctx.solve(opts)
         f = torch_dev.empty(w.net.m, dtype=torch_dev.int64, device="cuda")
         ctx.get_flows(f)
-        o, d, wfx = ctx.legs()
+        o, d, wfx = orc_legs(orc, ctx, [dem])
     ref = orc.fw_solve(w.net, o, d, wfx, fixed_iters=3, dt_s=900.0, keep_history=False)
     assert np.array_equal(host(f), ref.f)
 
@@ -720,7 +756,7 @@ def _adj_setup(q, orc, net, dem, iters):
     opts = q.default_opts(fixed_iters=iters, keep_history=1)
     ctx.solve(opts)
     ctx.adjoint_record(opts)
-    o, d, wfx = ctx.legs()
+    o, d, wfx = orc_legs(orc, ctx, [dem])
     res = orc.fw_solve(net, o, d, wfx, dt_s=dem.dt_s, fixed_iters=iters, keep_history=True)
     pl = adj.frozen_paths(net, o, d, wfx, res.hist_cost, dem.dt_s)
     return ctx, opts, (o, d, wfx), res, pl
@@ -770,14 +806,14 @@ def test_model_backward_matches_oracle(torch_dev, q, orc, case):
     try:
         d2, cap2 = _perturbed(net, wfx, 4)
         fo = torch.empty(net.m, dtype=torch.float64, device="cuda")
-        ctx.model_forward(opts, dev(torch, d2), dev(torch, cap2), fo)
+        fid = ctx.model_forward(opts, dev(torch, d2), dev(torch, cap2), fo)
         f2, st2 = adj.forward_contract(pl, net.m, d2, net.fftt, cap2, 0.15, 4, dem.dt_s)
         assert sum(0.0 < s[2] < 1.0 for s in st2[1:]) >= 1
         rng = np.random.default_rng(8)
         fbar = np.where(rng.random(net.m) < 0.2, rng.standard_normal(net.m), 0.0)
         dbar = torch.empty(len(o), dtype=torch.float64, device="cuda")
         capbar = torch.empty(net.m, dtype=torch.float64, device="cuda")
-        ctx.model_backward(dev(torch, fbar), dbar, capbar)
+        ctx.model_backward(fid, dev(torch, fbar), dbar, capbar)
         rd, rc = adj.backward(st2, fbar, pl, net.fftt, cap2, 0.15, 4, dem.dt_s)
         gd, gc = host(dbar), host(capbar)
         assert np.max(np.abs(gd - rd)) <= 1e-9 * np.max(np.abs(rd))
@@ -812,6 +848,43 @@ def test_model_autograd_function(torch_dev, q, orc):
         assert np.max(np.abs(host(dt.grad) - rd)) <= 1e-9 * np.max(np.abs(rd))
         assert ct.grad.dtype == torch.float32
         assert np.allclose(host(ct.grad), rc.astype(np.float32), rtol=1e-6, atol=1e-6 * np.max(np.abs(rc)))
+    finally:
+        ctx.close()
+
+
+def test_model_backward_refuses_a_stale_forward(torch_dev, q, orc):
+    """Two forward passes before one backward: the context holds the second
+    pass's iterates only, so the first pass's backward is refused (through
+    the ABI and through torch.autograd) and the second one's still matches
+    a fresh forward + backward at its own inputs."""
+    torch = torch_dev
+    net, dem, iters = _adj_case("grid_trunc")
+    ctx, opts, (o, d, wfx), res, pl = _adj_setup(q, orc, net, dem, iters)
+    try:
+        d1, cap1 = _perturbed(net, wfx, 11)
+        d2, cap2 = _perturbed(net, wfx, 12)
+        fo = torch.empty(net.m, dtype=torch.float64, device="cuda")
+        id1 = ctx.model_forward(opts, dev(torch, d1), dev(torch, cap1), fo)
+        id2 = ctx.model_forward(opts, dev(torch, d2), dev(torch, cap2), fo)
+        assert id2 != id1
+        fbar = dev(torch, np.linspace(-1.0, 1.0, net.m))
+        dbar = torch.empty(len(o), dtype=torch.float64, device="cuda")
+        capbar = torch.empty(net.m, dtype=torch.float64, device="cuda")
+        with pytest.raises(q.QdtaError) as e:
+            ctx.model_backward(id1, fbar, dbar, capbar)
+        assert e.value.code == q.ESTATE
+        ctx.model_backward(id2, fbar, dbar, capbar)
+        g2 = host(dbar).copy()
+        id3 = ctx.model_forward(opts, dev(torch, d2), dev(torch, cap2), fo)
+        ctx.model_backward(id3, fbar, dbar, capbar)
+        assert np.array_equal(host(dbar), g2)
+        # autograd: two losses built before one backward
+        da = dev(torch, d1).requires_grad_(True)
+        fa = q.frozen_path_flows(ctx, opts, da, None)
+        fb = q.frozen_path_flows(ctx, opts, dev(torch, d2).requires_grad_(True), None)
+        with pytest.raises(q.QdtaError):
+            fa.sum().backward()
+        del fb
     finally:
         ctx.close()
 
