@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qdta_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libqdta_oracle.so")
 
-RULE_NONE, RULE_CEIL, RULE_FLOOR = 0, 1, 2
+RULE_NONE, RULE_CEIL, RULE_FLOOR, RULE_PROGRESS = 0, 1, 2, 3
 LS_KSECTION, LS_QN, LS_MSA = 0, 1, 2
 STOP_GAP, STOP_OBJ = 0, 1
 OBJ_UE, OBJ_SO = 0, 1
@@ -182,19 +182,27 @@ def tree(net, cost, q):
     return D, succ, rc
 
 
-def aon(net, cost, orig, dest, d_fx, dt_s, rule=RULE_CEIL, nthreads=0):
+def aon(net, cost, orig, dest, d_fx, dt_s, rule=RULE_CEIL, nthreads=0, delay=None, want_delay=False):
+    """All-or-nothing loading; delay (float32[P] or None): each leg's carried
+    time to its origin (PROGRESS rule).  Returns (y, stop, rc), plus the stop
+    delays when want_delay."""
     rp, col, cost = _i32(net.row_ptr), _i32(net.col), _f32(cost)
     orig, dest, d_fx = _i32(orig), _i32(dest), _i64(d_fx)
+    tau0 = None if delay is None else _f32(delay)
     y = np.zeros(col.shape[0], dtype=np.int64)
     stop = np.empty(orig.shape[0], dtype=np.int32)
+    sdl = np.zeros(orig.shape[0], dtype=np.float32)
     L = lib()
-    L.orc_aon.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
-                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
-                          C.c_void_p, C.c_int32]
-    rc = L.orc_aon(net.n, col.shape[0], _p(rp), _p(col), _p(cost), orig.shape[0], _p(orig), _p(dest),
-                   _p(d_fx), float(dt_s), rule, _p(y), _p(stop), nthreads)
+    L.orc_aon_d.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_int32]
+    rc = L.orc_aon_d(net.n, col.shape[0], _p(rp), _p(col), _p(cost), None, orig.shape[0], _p(orig), _p(dest),
+                     _p(d_fx), _p(tau0) if tau0 is not None else None, float(dt_s), rule, _p(y), _p(stop), _p(sdl),
+                     nthreads)
     if rc < 0:
         raise RuntimeError(f"orc_aon failed {rc}")
+    if want_delay:
+        return y, stop, sdl, rc
     return y, stop, rc
 
 
@@ -267,10 +275,11 @@ class FwResult:
 
 def fw_solve(net, orig, dest, d_fx, *, alpha_b=0.15, beta=4, dt_s=float("inf"), rule=RULE_CEIL,
              stop_rule=STOP_GAP, tol=1e-4, max_iter=1000, fixed_iters=0, keep_history=True,
-             nthreads=0, **ls_kw) -> FwResult:
+             nthreads=0, delay=None, **ls_kw) -> FwResult:
     rp, col = _i32(net.row_ptr), _i32(net.col)
     c0, cap = _f32(net.fftt), _f32(net.cap)
     orig, dest, d_fx = _i32(orig), _i32(dest), _i64(d_fx)
+    tau0 = None if delay is None else _f32(delay)
     m = col.shape[0]
     cap_iter = fixed_iters if fixed_iters > 0 else max_iter
     o = _FwOpts(alpha_b, beta, rule, float(dt_s), stop_rule, tol, max_iter, fixed_iters,
@@ -283,9 +292,9 @@ def fw_solve(net, orig, dest, d_fx, *, alpha_b=0.15, beta=4, dt_s=float("inf"), 
     L = lib()
     L.orc_fw_solve.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     rc = L.orc_fw_solve(net.n, m, _p(rp), _p(col), _p(c0), _p(cap), orig.shape[0], _p(orig), _p(dest),
-                        _p(d_fx), C.byref(o), _p(f), C.byref(st), _p(ha),
+                        _p(d_fx), _p(tau0) if tau0 is not None else None, C.byref(o), _p(f), C.byref(st), _p(ha),
                         _p(hc) if hc is not None else None, _p(gaps))
     if rc < 0:
         raise RuntimeError(f"orc_fw_solve failed {rc}")
@@ -293,16 +302,18 @@ def fw_solve(net, orig, dest, d_fx, *, alpha_b=0.15, beta=4, dt_s=float("inf"), 
 
 
 def residual(net, f, hist_alpha, hist_cost, orig, dest, d_fx, *, alpha_b=0.15, beta=4, dt_s=900.0,
-             rule=RULE_CEIL):
+             rule=RULE_CEIL, delay=None, want_delay=False):
     rp, col = _i32(net.row_ptr), _i32(net.col)
     c0, cap = _f32(net.fftt), _f32(net.cap)
     orig, dest, d_fx = _i32(orig), _i32(dest), _i64(d_fx)
+    tau0 = None if delay is None else _f32(delay)
     J = len(hist_alpha) - 1
     P = orig.shape[0]
     cap_out = (J + 1) * max(P, 1)
     ro = np.empty(cap_out, np.int32)
     rd = np.empty(cap_out, np.int32)
     rw = np.empty(cap_out, np.int64)
+    rdl = np.zeros(cap_out, np.float32)
     cnt = C.c_int64(0)
     done = C.c_int64(0)
     lam = np.empty(J + 1, np.float64)
@@ -312,56 +323,96 @@ def residual(net, f, hist_alpha, hist_cost, orig, dest, d_fx, *, alpha_b=0.15, b
     L.orc_residual.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.c_int32,
                                C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p]
     rc = L.orc_residual(net.n, col.shape[0], _p(rp), _p(col), _p(c0), _p(cap), alpha_b, beta, float(dt_s),
-                        rule, _p(_i64(f)), J, _p(ha), _p(hc), P, _p(orig), _p(dest), _p(d_fx), _p(ro),
-                        _p(rd), _p(rw), C.byref(cnt), C.byref(done), _p(lam))
+                        rule, _p(_i64(f)), J, _p(ha), _p(hc), P, _p(orig), _p(dest), _p(d_fx),
+                        _p(tau0) if tau0 is not None else None, _p(ro), _p(rd), _p(rw), _p(rdl), C.byref(cnt),
+                        C.byref(done), _p(lam))
     if rc < 0:
         raise RuntimeError(f"orc_residual failed {rc}")
     k = cnt.value
+    if want_delay:
+        return ro[:k].copy(), rd[:k].copy(), rw[:k].copy(), done.value, lam, rdl[:k].copy()
     return ro[:k].copy(), rd[:k].copy(), rw[:k].copy(), done.value, lam
 
 
-def merge_legs(orig, dest, w_fx):
-    """Sum fixed-point legs with equal (origin, destination); sorted by (dest, orig)."""
+def merge_legs(orig, dest, w_fx, delay=None):
+    """Sum fixed-point legs with equal (origin, destination) -- and equal
+    carried delay when `delay` is given (then a fourth array is returned);
+    sorted by (dest, orig, delay)."""
     orig, dest, w_fx = _i32(orig), _i32(dest), _i64(w_fx)
+    if delay is None:
+        if orig.size == 0:
+            return orig, dest, w_fx
+        key = dest.astype(np.int64) * (1 << 31) + orig.astype(np.int64)
+        u, inv = np.unique(key, return_inverse=True)
+        w = np.zeros(u.shape[0], dtype=np.int64)
+        np.add.at(w, inv, w_fx)
+        return (u % (1 << 31)).astype(np.int32), (u // (1 << 31)).astype(np.int32), w
+    dl = _f32(delay)
     if orig.size == 0:
-        return orig, dest, w_fx
-    key = dest.astype(np.int64) * (1 << 31) + orig.astype(np.int64)
-    u, inv = np.unique(key, return_inverse=True)
-    w = np.zeros(u.shape[0], dtype=np.int64)
-    np.add.at(w, inv, w_fx)
-    return (u % (1 << 31)).astype(np.int32), (u // (1 << 31)).astype(np.int32), w
+        return orig, dest, w_fx, dl
+    bits = dl.view(np.uint32).astype(np.int64)           # non-negative floats order like their bits
+    keys = np.stack([bits, orig.astype(np.int64), dest.astype(np.int64)])
+    order = np.lexsort(keys)
+    k = keys[:, order]
+    new = np.ones(order.size, bool)
+    new[1:] = np.any(k[:, 1:] != k[:, :-1], axis=0)
+    grp = np.cumsum(new) - 1
+    w = np.zeros(int(grp[-1]) + 1, dtype=np.int64)
+    np.add.at(w, grp, w_fx[order])
+    first = order[new]
+    return orig[first].copy(), dest[first].copy(), w, dl[first].copy()
 
 
 def qdta_day(net, days, *, alpha_b=0.15, beta=4, rule=RULE_CEIL, tol=1e-4, max_iter=1000,
              stop_rule=STOP_GAP, nthreads=0, **ls_kw):
     """Alg. 1: for each interval, d(i) = d^o(i) + d^r(i), Frank-Wolfe, then
     Alg. 4 for d^r(i+1).  d^r(0) is empty.  Returns per-interval records and
-    the residual left after the last interval (reported, not assigned)."""
+    the residual left after the last interval (reported, not assigned).
+    Under RULE_PROGRESS the residual legs carry their delays (time still
+    needed to reach their origin node), legs are merged by (destination,
+    origin, delay), and the records' "res" hold four arrays."""
+    prog = rule == RULE_PROGRESS
     res_o = np.zeros(0, np.int32)
     res_d = np.zeros(0, np.int32)
     res_w = np.zeros(0, np.int64)
+    res_t = np.zeros(0, np.float32)
     out = []
     for i, dem in enumerate(days):
         o_fx = np.array([int(np.rint(t * FX)) for t in dem.trips], dtype=np.int64) if dem.P else \
             np.zeros(0, np.int64)
-        o, d, w = merge_legs(np.concatenate([dem.orig, res_o]), np.concatenate([dem.dest, res_d]),
-                             np.concatenate([o_fx, res_w]))
+        if prog:
+            o, d, w, t = merge_legs(np.concatenate([dem.orig, res_o]), np.concatenate([dem.dest, res_d]),
+                                    np.concatenate([o_fx, res_w]),
+                                    np.concatenate([np.zeros(dem.P, np.float32), res_t]))
+        else:
+            o, d, w = merge_legs(np.concatenate([dem.orig, res_o]), np.concatenate([dem.dest, res_d]),
+                                 np.concatenate([o_fx, res_w]))
+            t = np.zeros(o.size, np.float32)
         keep = (w > 0) & (o != d)
-        o, d, w = o[keep], d[keep], w[keep]
+        o, d, w, t = o[keep], d[keep], w[keep], t[keep]
         if o.size == 0:
             f = np.zeros(net.m, np.int64)
+            res = (res_o[:0], res_d[:0], res_w[:0]) + ((res_t[:0],) if prog else ())
             out.append({"interval": i, "f": f, "iters": 0, "gap": 0.0, "legs": 0,
-                        "res": (res_o[:0], res_d[:0], res_w[:0]), "done_fx": 0, "in_fx": 0})
-            res_o, res_d, res_w = res_o[:0], res_d[:0], res_w[:0]
+                        "res": res, "done_fx": 0, "in_fx": 0})
+            res_o, res_d, res_w, res_t = res_o[:0], res_d[:0], res_w[:0], res_t[:0]
             continue
         fw = fw_solve(net, o, d, w, alpha_b=alpha_b, beta=beta, dt_s=dem.dt_s, rule=rule, tol=tol,
-                      max_iter=max_iter, stop_rule=stop_rule, nthreads=nthreads, **ls_kw)
-        ro, rd, rw, done, lam = residual(net, fw.f, fw.hist_alpha, fw.hist_cost, o, d, w, alpha_b=alpha_b,
-                                         beta=beta, dt_s=dem.dt_s, rule=rule)
-        res_o, res_d, res_w = merge_legs(ro, rd, rw)
+                      max_iter=max_iter, stop_rule=stop_rule, nthreads=nthreads, delay=t if prog else None,
+                      **ls_kw)
+        ro, rd, rw, done, lam, rt = residual(net, fw.f, fw.hist_alpha, fw.hist_cost, o, d, w, alpha_b=alpha_b,
+                                             beta=beta, dt_s=dem.dt_s, rule=rule, delay=t if prog else None,
+                                             want_delay=True)
+        if prog:
+            res_o, res_d, res_w, res_t = merge_legs(ro, rd, rw, rt)
+            res = (res_o, res_d, res_w, res_t)
+        else:
+            res_o, res_d, res_w = merge_legs(ro, rd, rw)
+            res = (res_o, res_d, res_w)
         out.append({"interval": i, "f": fw.f, "iters": fw.iters, "gap": fw.gap, "legs": int(o.size),
-                    "res": (res_o, res_d, res_w), "done_fx": done, "in_fx": int(w.sum()),
+                    "res": res, "done_fx": done, "in_fx": int(w.sum()),
                     "hist_alpha": fw.hist_alpha, "lambda": lam})
-    return out, (res_o, res_d, res_w)
+    return out, ((res_o, res_d, res_w, res_t) if prog else (res_o, res_d, res_w))

@@ -61,6 +61,7 @@ typedef __int128 i128;
 #define RULE_NONE 0
 #define RULE_CEIL 1
 #define RULE_FLOOR 2
+#define RULE_PROGRESS 3
 
 #define LS_KSECTION 0
 #define LS_QN 1
@@ -321,20 +322,34 @@ int orc_tree(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, c
 
 /* Walks the successor path of leg (s0 -> q) and calls back for every loaded
  * link.  tau accumulates fl32 times with `tcost` (the interval's costs in the
- * Frank-Wolfe loop, the final costs in Alg. 4).
+ * Frank-Wolfe loop, the final costs in Alg. 4), starting from tau0.
  *   CEIL : a link entered before dt is loaded; stop at the first node reached
  *          at or after dt (the worked example of section 6).
  *   FLOOR: a link is loaded only if it is left by dt.
  *   NONE : walk to q.
- * Returns the stop node (q when the leg completes). */
+ *   PROGRESS (the remedy section 3 suggests for intervals shorter than a
+ *          link: track how far a trip got along its link): links are loaded
+ *          as under CEIL, when entered before dt, but a trip that is still on
+ *          a link at dt stops there, at the link's head with the time it still
+ *          needs to reach it, *delay_out = fl32(tau - dt) > 0.  A leg that
+ *          starts with tau0 >= dt is still on its way to s0: it stops there
+ *          with delay fl32(tau0 - dt).  A trip on the last link of its path
+ *          has loaded every link and completes (stop node q).
+ * Returns the stop node (q when the leg completes); *delay_out (may be NULL)
+ * receives the remaining delay, 0 unless PROGRESS stops a trip on a link. */
 typedef void (*load_fn)(void *ctx, int32_t link);
 
 static int32_t walk_leg(const int32_t *col, const int32_t *succ, const float *tcost, int32_t s0,
-                        int32_t q, float dt32, int rule, load_fn fn, void *ctx) {
+                        int32_t q, float dt32, int rule, float tau0, load_fn fn, void *ctx, float *delay_out) {
     int32_t u = s0;
-    float tau = 0.0f;
+    float tau = tau0;
+    if (delay_out) *delay_out = 0.0f;
+    if (rule == RULE_PROGRESS && tau >= dt32) {
+        if (delay_out) *delay_out = tau - dt32;
+        return s0;
+    }
     while (u != q) {
-        if (rule == RULE_CEIL && tau >= dt32) return u;
+        if ((rule == RULE_CEIL || rule == RULE_PROGRESS) && tau >= dt32) return u;
         int32_t e = succ[u];
         if (e < 0) return -1;
         float nt = tau + tcost[e];
@@ -342,6 +357,11 @@ static int32_t walk_leg(const int32_t *col, const int32_t *succ, const float *tc
         if (fn) fn(ctx, e);
         tau = nt;
         u = col[e];
+        if (rule == RULE_PROGRESS && tau > dt32) {
+            if (u == q) return q;
+            if (delay_out) *delay_out = tau - dt32;
+            return u;
+        }
     }
     return q;
 }
@@ -375,9 +395,10 @@ static int effective_rule(double dt_s, int rule) { return isfinite(dt_s) ? rule 
  * truncated, demand added to each loaded link.  y (int64[m]) is overwritten,
  * stop (int32[P], may be NULL) receives the stop node of each leg (q when it
  * completes, -1 when skipped).  Returns 0, ORC_WARN_ABSORB or an error. */
-int orc_aon_t(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
+int orc_aon_d(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
               const float *tcost, int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
-              double dt_s, int32_t rule, int64_t *y, int32_t *stop, int32_t nthreads) {
+              const float *tau0, double dt_s, int32_t rule, int64_t *y, int32_t *stop, float *stop_delay,
+              int32_t nthreads) {
     if (!tcost) tcost = cost;
     if (orc_check_csr(n, m, row_ptr, col)) return ORC_ECSR;
     for (int32_t p = 0; p < P; ++p)
@@ -416,11 +437,15 @@ int orc_aon_t(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
             absorb |= successors(&g, cost, q, D, succ, hop, qu);
             for (int32_t i = b; i < e; ++i) {
                 int32_t p = idx[i];
+                if (stop_delay) stop_delay[p] = 0.0f;
                 if (d_fx[p] <= 0 || orig[p] == q) { if (stop) stop[p] = -1; continue; }
                 if (!isfinite(D[orig[p]])) { unreach = 1; if (stop) stop[p] = -1; continue; }
                 addctx ac = {y, d_fx[p]};
-                int32_t s = walk_leg(col, succ, tcost, orig[p], q, dt32, eff, add_link, &ac);
+                float dl = 0.0f;
+                int32_t s = walk_leg(col, succ, tcost, orig[p], q, dt32, eff, tau0 ? tau0[p] : 0.0f, add_link, &ac,
+                                     &dl);
                 if (stop) stop[p] = s;
+                if (stop_delay) stop_delay[p] = dl;
             }
         }
         free(D); free(succ); free(hop); free(qu); free(h.a);
@@ -429,6 +454,14 @@ int orc_aon_t(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
     graph_free(&g);
     if (unreach) return ORC_EUNREACH;
     return absorb ? ORC_WARN_ABSORB : ORC_OK;
+}
+
+/* Legs that all start at their origin node at the start of the interval. */
+int orc_aon_t(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
+              const float *tcost, int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
+              double dt_s, int32_t rule, int64_t *y, int32_t *stop, int32_t nthreads) {
+    return orc_aon_d(n, m, row_ptr, col, cost, tcost, P, orig, dest, d_fx, NULL, dt_s, rule, y, stop, NULL,
+                     nthreads);
 }
 
 /* The trees' own costs clock the truncation (user equilibrium). */
@@ -480,7 +513,7 @@ int orc_paths(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
             if (d_fx[p] <= 0 || orig[p] == q) continue;
             if (!isfinite(D[orig[p]])) { rc = ORC_EUNREACH; break; }
             pathctx pc = {NULL, 0};
-            walk_leg(col, succ, cost, orig[p], q, dt32, eff, put_link, &pc);
+            walk_leg(col, succ, cost, orig[p], q, dt32, eff, 0.0f, put_link, &pc, NULL);
             len[p] = pc.at;
         }
     }
@@ -496,7 +529,7 @@ int orc_paths(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
                 int32_t p = idx[i];
                 if (d_fx[p] <= 0 || orig[p] == q) continue;
                 pathctx pc = {links + ptr[p], 0};
-                walk_leg(col, succ, cost, orig[p], q, dt32, eff, put_link, &pc);
+                walk_leg(col, succ, cost, orig[p], q, dt32, eff, 0.0f, put_link, &pc, NULL);
             }
         }
     }
@@ -731,12 +764,14 @@ typedef struct {
     double objective_fp64; /* quantised terms): the FP64 reference of each reported result */
 } fw_stats;
 
-/* hist_alpha: double[max_iter+1], hist_cost: float[(max_iter+1) * m] (may be
+/* tau0: float[P] or NULL, each leg's time still needed to reach its origin
+ * (the PROGRESS rule's carried delay; 0 for new demand).
+ * hist_alpha: double[max_iter+1], hist_cost: float[(max_iter+1) * m] (may be
  * NULL): alpha_j and the costs that defined AON j, j = 0 is the initial
  * free-flow AON (alpha_0 = 1).  gap_hist: double[max_iter+1] or NULL. */
 int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *c0,
                  const float *cap, int32_t P, const int32_t *orig, const int32_t *dest,
-                 const int64_t *d_fx, const fw_opts *o, int64_t *f, fw_stats *st,
+                 const int64_t *d_fx, const float *tau0, const fw_opts *o, int64_t *f, fw_stats *st,
                  double *hist_alpha, float *hist_cost, double *gap_hist) {
     memset(st, 0, sizeof(*st));
     double kappa = orc_kappa(o->dt_s);
@@ -753,7 +788,8 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
     rc = orc_bpr_obj(m, zero, c0, cap, o->alpha_b, o->beta, kappa, so, c);
     if (rc < 0) goto done;
     if (so) orc_bpr(m, zero, c0, cap, o->alpha_b, o->beta, kappa, tc);
-    rc = orc_aon_t(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, o->dt_s, o->rule, f, NULL, o->nthreads);
+    rc = orc_aon_d(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, tau0, o->dt_s, o->rule, f, NULL, NULL,
+                   o->nthreads);
     if (rc < 0) goto done;
     st->absorb |= (rc == ORC_WARN_ABSORB);
     if (hist_alpha) hist_alpha[0] = 1.0;
@@ -762,7 +798,8 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
         rc = orc_bpr_obj(m, f, c0, cap, o->alpha_b, o->beta, kappa, so, c);
         if (rc < 0) goto done;
         if (so) orc_bpr(m, f, c0, cap, o->alpha_b, o->beta, kappa, tc);
-        rc = orc_aon_t(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, o->dt_s, o->rule, y, NULL, o->nthreads);
+        rc = orc_aon_d(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, tau0, o->dt_s, o->rule, y, NULL, NULL,
+                       o->nthreads);
         if (rc < 0) goto done;
         st->absorb |= (rc == ORC_WARN_ABSORB);
         int64_t scf[2], scy[2];
@@ -822,7 +859,9 @@ done:
 /* Residual demand after an interval (Alg. 4)                                */
 /* ------------------------------------------------------------------------ */
 
-/* Path flows are keyed by full shortest paths: iterate j routed every leg on
+/* tau0 (may be NULL) and r_delay (may be NULL): the legs' carried delays in
+ * and the residual legs' delays out (the PROGRESS rule; 0 otherwise).
+ * Path flows are keyed by full shortest paths: iterate j routed every leg on
  * the trees of cost vector c_j, and the converged mixture weights them by
  * lambda_j = alpha_j * prod_{k>j} (1 - alpha_k) (alpha_0 = 1).  Every path is
  * re-truncated with the final costs c_fin = BPR(f); a leg that stops at
@@ -833,9 +872,9 @@ done:
 int orc_residual(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *c0,
                  const float *cap, double alpha_b, int32_t beta, double dt_s, int32_t rule,
                  const int64_t *f, int32_t J, const double *hist_alpha, const float *hist_cost,
-                 int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
-                 int32_t *r_orig, int32_t *r_dest, int64_t *r_fx, int64_t *n_out, int64_t *done_fx,
-                 double *lambda_out) {
+                 int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx, const float *tau0,
+                 int32_t *r_orig, int32_t *r_dest, int64_t *r_fx, float *r_delay, int64_t *n_out,
+                 int64_t *done_fx, double *lambda_out) {
     double kappa = orc_kappa(dt_s);
     int eff = effective_rule(dt_s, rule);
     float dt32 = (float)dt_s;
@@ -875,10 +914,12 @@ int orc_residual(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
                 int32_t p = idx[i];
                 if (d_fx[p] <= 0 || orig[p] == q) continue;
                 int64_t w = (int64_t)rint(lam[j] * (double)d_fx[p]);
-                int32_t s = walk_leg(col, succ, cfin, orig[p], q, dt32, eff, NULL, NULL);
+                float dl = 0.0f;
+                int32_t s = walk_leg(col, succ, cfin, orig[p], q, dt32, eff, tau0 ? tau0[p] : 0.0f, NULL, NULL, &dl);
                 if (s == q) { done += w; continue; }
                 if (w == 0) continue;
                 r_orig[cnt] = s; r_dest[cnt] = q; r_fx[cnt] = w;
+                if (r_delay) r_delay[cnt] = dl;
                 cnt++;
             }
         }
