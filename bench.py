@@ -5,13 +5,20 @@ One step = one Frank-Wolfe iteration of the link-flow form (Alg. 6): BPR link
 costs, the all-or-nothing assignment (destination-rooted shortest-path trees,
 truncation, loading), the relative-gap test, the K-section line search on the
 Beckmann objective and the flow update -- i.e. one AON plus everything around
-it.  No stop test ends the run early, so every timed step does the
-whole iteration (a fixed iteration count disables every stop test).  Default workload: the 08:00 interval of the Bay-Area-shaped
-synthetic network (550k nodes, 1.0M links, 5,000 zones).
+it.  No stop test ends the run early, so every timed step does the whole
+iteration (a fixed iteration count disables every stop test).
+
+Default workload: the 08:00 peak interval of the Bay-Area-shaped synthetic
+day (550k nodes, 1.0M links, 5,000 zones) together with the residual demand
+the four intervals before it (07:00-08:00) carry into it (Alg. 1, Alg. 4),
+as in the full-day run: those intervals are solved first, untimed.
 
 Prints one JSON line (rank 0, N = 1).  The SSSP kernel's duration comes from
-HIP events the library records on its own stream; its roofline uses the
-algorithmic bytes per tree 8n + 8m (plus the topology once per launch).
+HIP events the library records on its own stream.  Its roofline uses the
+algorithmic bytes per tree 8n + 8m plus the shared topology once per launch
+(every tree counted whole), and, next to it, the bytes of the work the
+kernel counted (nodes taken and in-links relaxed: trees stop once their
+origins are settled).
 """
 from __future__ import annotations
 
@@ -63,7 +70,12 @@ WG_SHAPES = {1: (1, 2), 2: (1, 4), 3: (2, 4), 4: (4, 4), 5: (2, 2), 6: (4, 2)}
 DS_SHAPES = {1: (1, 4), 2: (2, 4), 3: (4, 4), 4: (4, 8), 5: (8, 8), 6: (1, 1)}
 
 
-def sssp_kernel_name(shape, tree_waves):
+BLK_SHAPES = {1: (128, 1), 2: (128, 2), 3: (64, 2), 4: (256, 1)}
+
+
+def sssp_kernel_name(shape, tree_waves, kernel=1):
+    if kernel == 2:
+        return "k_sssp_blk<%d, %d>" % BLK_SHAPES.get(shape, (128, 2))
     shape = shape if shape in WG_SHAPES else 3
     if (tree_waves or 4) == 1:
         return "k_sssp_ds<%d, %d>" % DS_SHAPES[shape]
@@ -86,46 +98,40 @@ def traffic_entry(kernel_src_hash, kernel):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(w, target_s, nthreads):
-    """The oracle as it stands, on a bounded sample of the same workload:
-    one AON over the legs of the first S destinations (S sized to about
-    `target_s` seconds), one K-section line search over a link sample, BPR
-    over all links; each extrapolated linearly to the full step."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(net, legs, f_fx, dt_s, alpha_b, beta, nthreads):
+    """The oracle as it stands, timed on one whole Frank-Wolfe step of the
+    same workload at the same iterate as the GPU's timed steps: BPR costs of
+    f, the all-or-nothing assignment of every leg (all 5,000 trees, no
+    sampling), the exact gap sums, the K-section line search (3 passes of
+    32 step sizes over all links) and the update."""
     import oracle
-    net, dem = w.net, w.demand
-    d_fx = np.rint(dem.trips * FX).astype(np.int64)
-    dests = np.unique(dem.dest)
-    Q = dests.size
-    cost = net.fftt.copy()
-
-    def aon_sample(S):
-        sel = np.isin(dem.dest, dests[:S])
-        t0 = time.perf_counter()
-        oracle.aon(net, cost, dem.orig[sel], dem.dest[sel], d_fx[sel], dem.dt_s, oracle.RULE_CEIL, nthreads=nthreads)
-        return time.perf_counter() - t0
-
-    S = max(2, min(Q, nthreads))
-    t = aon_sample(S)
-    while t < 0.25 * target_s and S < Q:
-        S = min(Q, int(S * max(2.0, 0.3 * target_s / max(t, 1e-3))))
-        t = aon_sample(S)
-    t_aon = t * Q / S
-    # line search: 3 passes x 32 step sizes on a link sample
-    rng = np.random.default_rng(0)
-    mL = min(net.m, 200_000)
-    f = rng.integers(0, 300 * FX, mL).astype(np.int64)
-    y = rng.integers(0, 600 * FX, mL).astype(np.int64)
+    o, d, w = legs
     t0 = time.perf_counter()
-    oracle.line_search(f, y, net.fftt[:mL], net.cap[:mL], 0.15, 4, dem.dt_s, 1)
-    t_ls = (time.perf_counter() - t0) * net.m / mL
-    t0 = time.perf_counter()
-    oracle.bpr(np.zeros(net.m, np.int64), net.fftt, net.cap, 0.15, 4, dem.dt_s)
-    t_bpr = time.perf_counter() - t0
-    step = t_aon + t_ls + 2 * t_bpr
+    cost, _ = oracle.bpr(f_fx, net.fftt, net.cap, alpha_b, beta, dt_s)
+    t1 = time.perf_counter()
+    y, _, _ = oracle.aon(net, cost, o, d, w, dt_s, oracle.RULE_CEIL, nthreads=nthreads)
+    t2 = time.perf_counter()
+    oracle.sum_cx(cost, f_fx)
+    oracle.sum_cx(cost, y)
+    alpha, _, _ = oracle.line_search(f_fx, y, net.fftt, net.cap, alpha_b, beta, dt_s, 1)
+    oracle.fw_update(f_fx, y, alpha)
+    t3 = time.perf_counter()
+    step = t3 - t0
     return {"value": 1.0 / step, "unit": "AON/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"AON over the legs of {S} of {Q} destinations ({t:.1f} s, {nthreads} threads), "
-                      f"K-section line search over {mL} of {net.m} links, BPR over all links; "
-                      f"extrapolated linearly to one full step ({step:.1f} s)"}
+            "cpu": cpu_model(),
+            "sample": f"one whole FW step at the GPU's last timed iterate: BPR over {net.m} links ({t1 - t0:.2f} s), "
+                      f"AON of all {len(o)} legs over all trees ({t2 - t1:.1f} s, {nthreads} threads), exact gap "
+                      f"sums, K-section line search 3 x 32 and update ({t3 - t2:.2f} s); not extrapolated"}
 
 
 def _ctx_for(qdta, stream, pairs):
@@ -144,6 +150,36 @@ def _solve_timed(torch, ctx, opts):
     return time.perf_counter() - t0, st
 
 
+def batched_vs_plain(torch, qdta, warm_iters=3):
+    """Config 2 (255,754 links, 1,000 destinations, one congested 900 s
+    interval): one FW iteration in the batched form (every tree in one
+    launch, all step sizes in one pass, the iteration replayed as a HIP
+    graph) against the plain form (one launch per destination tree and per
+    step size), both timed at the same iterate after `warm_iters` updates.
+    The two forms give bit-identical iterates."""
+    w = workload("config2")
+    stream = torch.cuda.current_stream()
+    ctx = _ctx_for(qdta, stream, [(w.net, w.demand)])
+    per = {}
+    for form in (0, 2):
+        o = qdta.default_opts(fixed_iters=1 << 30, launch_form=form)
+        ctx.fw_begin(o)
+        for _ in range(warm_iters):
+            ctx.fw_step(qdta.default_opts(fixed_iters=1 << 30))
+        n = 3 if form == 0 else 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            ctx.fw_step(o)
+        torch.cuda.synchronize()
+        per[form] = (time.perf_counter() - t0) / n
+        log(f"config2 form {form}: {per[form] * 1e3:.1f} ms per FW iteration")
+    ctx.close()
+    return {"workload": f"config2: {w.net.n} nodes, {w.net.m} links, 1000 destinations, {w.demand.P} legs, dt 900 s",
+            "batched_iter_ms": per[0] * 1e3, "plain_iter_ms": per[2] * 1e3, "speedup": per[2] / per[0],
+            "iterate": f"FW iteration {warm_iters + 1} (congested)"}
+
+
 def mode_plain(args, torch, qdta):
     """M3 on config 2: per-iteration time of the batched form (every tree in
     one launch, all step sizes in one pass, iteration replayed as a HIP graph)
@@ -154,9 +190,10 @@ def mode_plain(args, torch, qdta):
     stream = torch.cuda.current_stream()
     ctx = _ctx_for(qdta, stream, [(w.net, w.demand)])
     out = {"mode": "plain", "workload": "config2"}
-    opts_b = qdta.default_opts(tol=1e-4, max_iter=args.steps)
+    opts_b = qdta.default_opts(tol=args.tol, max_iter=args.steps)
     t_solve, st = _solve_timed(torch, ctx, opts_b)
-    out.update(batched_solve_s=t_solve, iterations=st[0]["iters"], gap=st[0]["gap"], stopped_by=st[0]["stopped_by"])
+    out.update(tol=args.tol, batched_solve_s=t_solve, iterations=st[0]["iters"], gap=st[0]["gap"],
+               stopped_by=st[0]["stopped_by"])
     log(f"batched solve: {t_solve:.2f} s, {st[0]['iters']} iterations, gap {st[0]['gap']:.3e}, "
         f"stopped_by {st[0]['stopped_by']}")
     per = {}
@@ -224,13 +261,14 @@ def mode_day(args, torch, qdta):
     ctx.add(net)
     stop = qdta.STOP_OBJ if args.stop == "obj" else qdta.STOP_GAP
     ls_mode = {"ksection": qdta.LS_KSECTION, "qn": qdta.LS_QN, "msa": qdta.LS_MSA}[args.ls]
-    opts = qdta.default_opts(stop_rule=stop, tol=1e-4, max_iter=args.steps, keep_history=1,
+    trunc = {"ceil": qdta.RULE_CEIL, "floor": qdta.RULE_FLOOR, "progress": qdta.RULE_PROGRESS}[args.trunc]
+    opts = qdta.default_opts(stop_rule=stop, tol=args.tol, max_iter=args.steps, keep_history=1, trunc_rule=trunc,
                              launch_form=1 if args.profile_day else 0, tree_waves=args.tree_waves,
                              waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale, ls_mode=ls_mode,
                              objective=qdta.OBJ_SO if args.objective == "so" else qdta.OBJ_UE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, seg_s, tot_trips, carried = [], [], 0.0, 0
+    iters, seg_s, gaps, stops, tot_trips, carried = [], [], [], [], 0.0, 0
     split = {"set_demand": 0.0, "solve": 0.0, "advance": 0.0, "residual_out": 0.0}
     if args.profile_day:
         ctx.profile(True)
@@ -256,6 +294,8 @@ def mode_day(args, torch, qdta):
             split[k] += v
         iters.append(st[0]["iters"])
         seg_s.append(te - ta)
+        gaps.append(st[0]["gap"])
+        stops.append(st[0]["stopped_by"])
         carried = int(rw.sum())
         log(f"interval {i}: legs {legs} iters {st[0]['iters']} gap {st[0]['gap']:.2e} "
             f"stop {st[0]['stopped_by']} residual legs {ro.size} ({carried / FX:.0f} trips); "
@@ -268,7 +308,11 @@ def mode_day(args, torch, qdta):
     ctx.close()
     print(json.dumps({"mode": "day", "workload": f"config3 day, scale {args.scale}", "nodes": net.n, "links": net.m,
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
-                      "stop_rule": args.stop, "line_search": args.ls, "objective": args.objective,
+                      "stop_rule": args.stop, "tol": args.tol, "line_search": args.ls, "objective": args.objective,
+                      "truncation": args.trunc,
+                      "intervals_stopped_by": {k: stops.count(v) for k, v in
+                                               (("gap", 1), ("objective_change", 2), ("stall", 3), ("cap", 0))},
+                      "max_abs_gap": max((abs(g) for g in gaps), default=0.0),
                       "tree_waves": opts.tree_waves or 4,
                       "delta_scale": opts.delta_scale or 10.0, "left_after_last_trips": carried / FX,
                       "split_s": {k: round(v, 3) for k, v in split.items()},
@@ -392,12 +436,15 @@ def main():
                     help="aon: timed FW iterations; day: FW iteration cap per interval (use 200); "
                          "plain: cap of the batched solve; batch: fixed iterations")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3"])
     ap.add_argument("--delta-scale", type=float, default=0.0, help="bucket width / mean link cost (0: library default)")
     ap.add_argument("--waves-per-cu", type=int, default=0, help="wavefronts in flight per CU (0: library default)")
     ap.add_argument("--tree-waves", type=int, default=0, help="wavefronts per tree, 1 or 4 (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-plain", action="store_true", help="skip the batched-vs-plain record on config 2")
+    ap.add_argument("--carry", type=int, default=4,
+                    help="aon: earlier intervals solved first to carry their residual into the peak interval")
+    ap.add_argument("--sssp-kernel", type=int, default=0, help="shortest-path kernel (0 library default, 1 node "
+                                                               "queue, 2 block-local)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (MiB) once, for counter calibration")
     ap.add_argument("--no-autotune", action="store_true", help="skip the kernel-shape / bucket-width autotuner")
@@ -419,6 +466,9 @@ def main():
                     help="day mode: user equilibrium (the paper's) or system optimum (marginal-cost routing)")
     ap.add_argument("--ls", default="ksection", choices=["ksection", "qn", "msa"],
                     help="day mode: step rule (K-section line search, quasi-Newton of Alg. 8, or MSA)")
+    ap.add_argument("--tol", type=float, default=1e-4, help="day and plain modes: stop tolerance")
+    ap.add_argument("--trunc", default="ceil", choices=["ceil", "floor", "progress"],
+                    help="day mode: truncation rule (Eq. 2 read as CEIL or FLOOR, or link progress)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -432,24 +482,37 @@ def main():
         {"plain": mode_plain, "batch": mode_batch, "day": mode_day, "calib": mode_calib}[args.mode](args, torch, qdta)
         return
 
-    log(f"generating {args.workload}")
-    w = workload(args.workload)
-    net, dem = w.net, w.demand
-    log(f"network n={net.n} m={net.m}; legs={dem.P} trips={dem.total():.0f} dt={dem.dt_s}")
+    import synth
+    first = synth.configs.PEAK_INTERVAL - args.carry
+    log(f"generating config3 intervals {first}..{synth.configs.PEAK_INTERVAL}")
+    w = synth.config3_window(first)
+    net, days = w.net, w.demand
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = qdta.Context(0, stream)
     ctx.add(net)
+    kern = dict(sssp_kernel=args.sssp_kernel)
+    # the intervals before the peak, solved as in the full day, carry their
+    # residual demand into it (untimed)
+    day_opts = qdta.default_opts(alpha=w.alpha, beta=w.beta, stop_rule=qdta.STOP_OBJ, tol=1e-4, max_iter=200,
+                                 keep_history=1, **kern)
+    for dem in days[:-1]:
+        ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
+        st, _ = ctx.solve(day_opts)
+        ctx.advance_interval(day_opts)
+        log(f"carry-in interval: {dem.P} legs, {st[0]['iters']} FW updates, stop {st[0]['stopped_by']}")
+    ro, rd, rw, _ = ctx.residual(0)
+    dem = days[-1]
     ctx.set_demand(0, dem.orig, dem.dest, dem.trips, dem.dt_s)
-    opts = qdta.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=1 << 30, delta_scale=args.delta_scale,
-                             waves_per_cu=args.waves_per_cu, tree_waves=args.tree_waves)
     li = ctx.layout()
-    Q = int(li.total_dests)
+    Q, P = int(li.total_dests), int(li.total_legs)
+    log(f"peak interval: {dem.P} original legs + {ro.size} residual legs ({rw.sum() / FX:.0f} trips) -> {P} legs")
+    opts = qdta.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=1 << 30, delta_scale=args.delta_scale,
+                             waves_per_cu=args.waves_per_cu, tree_waves=args.tree_waves, **kern)
     if not args.no_autotune and not args.delta_scale:
         opts, best = ctx.autotune(opts, 2000.0)
-        log(f"autotune: sssp_shape={opts.sssp_shape} delta_scale={opts.delta_scale} tree_waves={opts.tree_waves} "
-            f"({best:.1f} ms)")
-    log(f"layout: destinations={Q} legs={li.total_legs}; initial AON")
+        log(f"autotune: kernel={opts.sssp_kernel} sssp_shape={opts.sssp_shape} delta_scale={opts.delta_scale} "
+            f"tree_waves={opts.tree_waves} ({best:.1f} ms)")
     t0 = time.perf_counter()
     ctx.fw_begin(opts)
     log(f"initial AON {time.perf_counter() - t0:.3f} s")
@@ -467,38 +530,49 @@ def main():
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gaps = []
+    gaps, alphas = [], []
     for i in range(args.steps):
         st, live = ctx.fw_step(opts)
         gaps.append(st[0]["gap"])
+        alphas.append(st[0]["last_alpha"])
         log(f"step {i + 1}/{args.steps}: gap={st[0]['gap']:.4e} alpha={st[0]['last_alpha']:.4f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile(False)
+    f_now = torch.empty(net.m, dtype=torch.int64, device="cuda")
+    ctx.get_flows(f_now)
+    f_host = f_now.cpu().numpy()
 
     ms_step = elapsed / args.steps * 1e3
     kernel_timing = "HIP events around the kernel, timed steps"
+    work_nodes, work_links = prof["sssp_work"]
     if prof["sssp"][1] == 0:
         # the timed steps replayed a HIP graph, whose kernels carry no events:
-        # time the same steps once more launched directly (same kernel, same
-        # inputs; only the launch path differs)
+        # time the same number of steps once more launched directly (same
+        # kernels and inputs; only the launch path differs)
         kernel_timing = "HIP events around direct launches of the same number of steps, after the timed graph replays"
         od = qdta.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=1 << 30, delta_scale=opts.delta_scale,
                                sssp_shape=opts.sssp_shape, waves_per_cu=opts.waves_per_cu,
-                               tree_waves=opts.tree_waves, launch_form=1)
+                               tree_waves=opts.tree_waves, sssp_kernel=opts.sssp_kernel, launch_form=1)
         ctx.profile(True)
         for _ in range(args.steps):
             ctx.fw_step(od)
         prof_d = ctx.profile_read()
         ctx.profile(False)
         prof["sssp"] = prof_d["sssp"]
+        prof["walk"] = prof_d["walk"]
     sssp_ms, sssp_n = prof["sssp"]
     sssp_avg_s = sssp_ms / max(sssp_n, 1) / 1e3
     bytes_launch = Q * sssp_bytes_per_tree(net.n, net.m) + 8.0 * net.m + 4.0 * net.n
     achieved = bytes_launch / sssp_avg_s / 1e9
+    # the work the kernel counted over the timed steps: per launch, 8 bytes
+    # per node taken (label written and read) and per in-link relaxed
+    # (label read and written), plus the shared topology once
+    n_launch = max(args.steps, 1)
+    touched = (8.0 * work_nodes + 8.0 * work_links) / n_launch + 8.0 * net.m + 4.0 * net.n
     src = open(os.path.join(ROOT, "paper_2104_12911_amd", "csrc", "qdta_kernels.hip"), "rb").read()
-    kname = sssp_kernel_name(opts.sssp_shape, opts.tree_waves)
+    kname = sssp_kernel_name(opts.sssp_shape, opts.tree_waves, opts.sssp_kernel or 1)
     traffic = traffic_entry(hashlib.sha256(src).hexdigest(), kname)
     result = {
         "metric": METRIC,
@@ -513,26 +587,38 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {net.n} nodes, {net.m} links, {Q} destinations, {li.total_legs} legs,"
-                               f" dt {dem.dt_s:g} s", "delta_scale": opts.delta_scale or 10.0,
-                   "sssp_shape": opts.sssp_shape,
-                   "waves_per_cu": opts.waves_per_cu or (32 if opts.tree_waves == 1 else 24),
-                   "tree_waves": opts.tree_waves or 4,
+        "config": {"workload": f"config3 08:00 peak interval with the residual carried from {args.carry} earlier "
+                               f"intervals: {net.n} nodes, {net.m} links, {Q} destinations, {P} legs "
+                               f"({dem.P} original + {ro.size} residual), dt {dem.dt_s:g} s",
+                   "sssp_kernel": kname, "delta_scale": opts.delta_scale or 10.0,
+                   "waves_per_cu": opts.waves_per_cu or 24,
                    "line_search": "K-section K=32 x3", "launch": "HIP graph per FW iteration"},
         "gteps": Q * net.m / sssp_avg_s / 1e9,
-        "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
+        "gteps_counted": work_links / n_launch / sssp_avg_s / 1e9,
+        "sssp_work_per_launch": {"nodes_taken": work_nodes / n_launch, "links_relaxed": work_links / n_launch,
+                                 "of_full_trees": (work_links / n_launch) / (Q * net.m)},
+        "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if k != "sssp_work"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kname,
-                     "kernel_ms": sssp_avg_s * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel": kname, "kernel_ms": sssp_avg_s * 1e3, "algorithmic_bytes_per_launch": bytes_launch,
+                     "algorithmic_bytes": "8n + 8m per tree (every tree counted whole) + 8m + 4n topology",
+                     "achieved_counted": touched / sssp_avg_s / 1e9,
+                     "frac_counted": touched / sssp_avg_s / 1e9 / HBM_PEAK_GBS,
+                     "counted_bytes": "8 per node taken + 8 per in-link relaxed, as counted by the kernel, "
+                                      "+ topology once",
                      "kernel_timing": kernel_timing},
-        "gap_last": gaps[-1] if gaps else None,
+        "gaps": gaps, "alphas": alphas,
     }
     if not args.no_cpu_baseline:
         nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
         log(f"cpu baseline: oracle with {nthreads} threads")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, nthreads)
+        import oracle
+        legs = oracle.demand_legs(np.concatenate([dem.orig, ro]), np.concatenate([dem.dest, rd]),
+                                  np.concatenate([dem.trips, rw / FX]))
+        result["cpu_baseline"] = cpu_baseline(net, legs, f_host, dem.dt_s, w.alpha, w.beta, nthreads)
     ctx.close()
+    if not args.no_plain:
+        result["batched_vs_plain"] = batched_vs_plain(torch, qdta)
     print(json.dumps(result), flush=True)
 
 

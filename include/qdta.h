@@ -70,6 +70,15 @@ extern "C" {
 #define QDTA_RULE_NONE 0    /* no truncation: walk to the destination */
 #define QDTA_RULE_CEIL 1    /* load a link entered before dt; stop at the first node reached at or after dt */
 #define QDTA_RULE_FLOOR 2   /* load a link only if it is left by dt */
+/* Link progress (section 3's remedy for intervals shorter than a link): load
+ * as CEIL, but a trip still on a link at dt stops at the link's head with the
+ * time it still needs to get there (its delay); the next interval starts it
+ * with that delay on its clock, and a leg whose delay is at or above dt stays
+ * on its way (delay - dt).  A trip on the last link of its path completes.
+ * Residual legs carry their delays (qdta_get_residual, qdta_set_residual)
+ * and merge by (destination, origin, delay).  Not taken by the frozen-path
+ * model (qdta_adjoint_record). */
+#define QDTA_RULE_PROGRESS 3
 
 #define QDTA_LS_KSECTION 0  /* K step sizes per pass, bracket the root of C'(alpha) */
 #define QDTA_LS_QN 1        /* quasi-Newton search of Alg. 8 with the stencil of Eq. 10 */
@@ -127,10 +136,17 @@ typedef struct {
                               one: what the workspace has left), < 0 none (the residual step grows
                               every tree again); never changes results */
     int32_t objective;     /* QDTA_OBJ_UE (default) or QDTA_OBJ_SO */
-    int32_t sssp_kernel;   /* shortest-path kernel: 0 auto, 1 node queue (tree_waves and sssp_shape as
-                              above), 2 block-local (a block of node ids is relaxed to closure in LDS per
-                              load; sssp_shape 1..4 = blocks of 128, 128 (two per wavefront per step), 64,
-                              256 nodes; instances of at most 8,192 blocks, else the node queue) */
+    int32_t sssp_kernel;   /* shortest-path kernel: 0 auto (the node queue), 1 node queue (tree_waves and
+                              sssp_shape as above), 2 block-local (a block of node ids is relaxed to
+                              closure in LDS per load; sssp_shape 1..4 = blocks of 128, 128 (two per
+                              wavefront per step), 64, 256 nodes; instances of at most 8,192 blocks, else
+                              the node queue), 3 node queue with each thread relaxing its own nodes'
+                              in-links (sssp_shape 1..4 = nodes x links per thread 1x4, 2x4, 2x2, 1x2);
+                              the trees are the same whichever runs */
+    int32_t load_form;     /* loading of plain intervals (dt = +inf, every instance plain): 0 auto (walk),
+                              1 walk every leg to its destination, 2 merge the legs' paths children before
+                              parents (two passes over the legs, each link loaded once per tree with the sum
+                              of the demand through it; same int64 flows); truncated intervals always walk */
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */
@@ -264,14 +280,19 @@ int qdta_trees(qdta_ctx *ctx, const qdta_opts *opts, int32_t inst, const float *
  * Alg. 7) under cost float[total_links]: y_fx int64[total_links] (device,
  * overwritten) receives the truncated loading; stop int32[total_legs] (device,
  * may be NULL) the stop node of each leg in qdta_get_legs() order (its
- * destination when the leg completes).  Synchronises; returns
- * QDTA_EUNREACH, QDTA_WABSORB or QDTA_OK. */
-int qdta_aon(qdta_ctx *ctx, const qdta_opts *opts, const float *cost, int64_t *y_fx, int32_t *stop);
+ * destination when the leg completes); stop_delay float[total_legs] (device,
+ * may be NULL) the time the leg still needs to reach its stop node (link-
+ * progress rule; 0 otherwise).  Synchronises; returns QDTA_EUNREACH,
+ * QDTA_WABSORB or QDTA_OK. */
+int qdta_aon(qdta_ctx *ctx, const qdta_opts *opts, const float *cost, int64_t *y_fx, int32_t *stop,
+             float *stop_delay);
 
 /* The current legs of all instances, in the order qdta_aon reports them:
- * grouped by instance, then by destination.  Host outputs of
- * int32/int32/int64[total_legs], local node ids; any may be NULL. */
-int qdta_get_legs(qdta_ctx *ctx, int32_t *host_orig, int32_t *host_dest, int64_t *host_d_fx);
+ * grouped by instance, then by destination (then origin, then delay).  Host
+ * outputs of int32/int32/int64/float[total_legs], local node ids, fixed-point
+ * demand, and each leg's carried delay (link-progress rule; 0 for new
+ * demand); any may be NULL. */
+int qdta_get_legs(qdta_ctx *ctx, int32_t *host_orig, int32_t *host_dest, int64_t *host_d_fx, float *host_delay);
 
 /* A5 -- exact line-search sums (Alg. 9 batched over K step sizes): for every
  * instance i and k < K, C_i(alpha) = sum_a Q(obj_a) and C'_i(alpha) =
@@ -309,8 +330,9 @@ int qdta_solve(qdta_ctx *ctx, const qdta_opts *opts, qdta_stats *host_stats);
 int qdta_fw_begin(qdta_ctx *ctx, const qdta_opts *opts);
 int qdta_fw_step(qdta_ctx *ctx, const qdta_opts *opts, qdta_stats *host_stats, int32_t *live_out);
 
-/* Copies of the solved link flows (int64 fx) and costs BPR(f) (float) over
- * all links, device outputs; either may be NULL. */
+/* Copies of the link flows (int64 fx) and costs BPR(f) (float) over all
+ * links, device outputs, of the solved interval or, during qdta_fw_begin /
+ * qdta_fw_step, of the current iterate. */
 int qdta_get_flows(qdta_ctx *ctx, int64_t *f_fx);
 int qdta_get_costs(qdta_ctx *ctx, const qdta_opts *opts, float *cost);
 
@@ -327,20 +349,22 @@ int qdta_get_costs(qdta_ctx *ctx, const qdta_opts *opts, float *cost);
 int qdta_advance_interval(qdta_ctx *ctx, const qdta_opts *opts);
 
 /* The pending residual demand of instance inst (host outputs).  Call with
- * NULL arrays to get *count; arrays then hold at least *count entries. */
+ * NULL arrays to get *count; arrays then hold at least *count entries.
+ * host_delay (may be NULL): each residual leg's delay (link-progress rule). */
 int qdta_get_residual(qdta_ctx *ctx, int32_t inst, int64_t *count, int32_t *host_orig,
-                      int32_t *host_dest, int64_t *host_w_fx, int64_t *host_done_fx);
+                      int32_t *host_dest, int64_t *host_w_fx, int64_t *host_done_fx, float *host_delay);
 
 /* Resume (Alg. 1): the whole state carried from interval i to i+1 is the
  * residual demand d^r(i+1), so a day stopped after qdta_advance_interval and
  * qdta_get_residual continues, bit for bit, in another context on the same
  * network: qdta_set_residual replaces instance inst's pending residual with
  * count legs (host inputs, copied) in the order qdta_get_residual returns
- * them, strictly increasing by (destination, origin), origin != destination,
- * w_fx > 0; the next qdta_set_demand merges them as it merges its own.
+ * them, strictly increasing by (destination, origin, delay), origin !=
+ * destination, w_fx > 0, delays finite and >= 0 (host_delay NULL: all 0);
+ * the next qdta_set_demand merges them as it merges its own.
  * count = 0 clears it.  Errors: QDTA_EARG (ids out of range, order, weights). */
 int qdta_set_residual(qdta_ctx *ctx, int32_t inst, int64_t count, const int32_t *host_orig,
-                      const int32_t *host_dest, const int64_t *host_w_fx);
+                      const int32_t *host_dest, const int64_t *host_w_fx, const float *host_delay);
 
 /* ---- Derivatives for OD calibration (not in the paper) -------------------
  * The frozen-path model of a solved interval: its J applied Frank-Wolfe
@@ -399,10 +423,15 @@ int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best
  * walk (with the tie fallback), 3 gap sums and stop test, 4 line search,
  * 5 flow update, 6 a whole iteration replayed as a HIP graph (the phases
  * inside a graph are not timed separately).  qdta_profile_enable(ctx, 1) resets and starts the timers,
- * 0 stops them; qdta_profile_read copies the totals (host output). */
+ * 0 stops them; qdta_profile_read copies the totals (host output; synchronises).  The work
+ * counters (sssp_nodes, sssp_links) add up over every shortest-path launch, graph replays
+ * included, from the last qdta_profile_enable on. */
 typedef struct {
     double ms[8];        /* summed duration per phase, milliseconds */
     int64_t count[8];    /* timed occurrences per phase */
+    int64_t sssp_nodes;  /* nodes taken off the shortest-path queues since qdta_profile_enable (a node
+                            taken twice counts twice; the one-wavefront-per-tree kernel does not count) */
+    int64_t sssp_links;  /* in-links relaxed by them */
 } qdta_profile;
 
 int qdta_profile_enable(qdta_ctx *ctx, int32_t on);

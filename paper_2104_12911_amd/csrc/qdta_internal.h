@@ -79,6 +79,7 @@ struct DemDev {
     const int32_t* leg_orig; // [P] global origin node
     const int64_t* leg_dfx;  // [P]
     const int32_t* leg_q;    // [P] global destination index
+    const float* leg_delay;  // [P] time a leg still needs to reach its origin node (link-progress rule), or NULL
     int32_t Q, P;
 };
 
@@ -90,6 +91,7 @@ struct Scratch {
     int64_t nmax;            // >= largest n + 65
     int32_t* work;           // tree work counter
     int32_t nslots;          // slots allocated (a launch is clamped to them)
+    unsigned long long* stats; // [2] nodes taken and in-links relaxed, added up by the kernels
 };
 
 struct FlagsDev {
@@ -155,18 +157,38 @@ hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, cons
                        float* delta_inst, double* logsum, int variant, int early);
 
 // time_cost NULL: the trees' own costs (held in the forward records)
+// Legs the link-progress rule leaves on a link (residual mode): appended as
+// (destination index, node, delay, weight) while fewer than cap are held.
+struct TransitOut {
+    int32_t* q;
+    int32_t* node;
+    float* delay;
+    int64_t* w;
+    unsigned int* n;         // entries appended (may pass cap: then QDTA_EOVF)
+    unsigned int cap;
+};
+
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int64_t* r_dense,
-                       unsigned long long* done_fx, int l_begin = 0, int l_end = -1);
+                       unsigned long long* done_fx, int l_begin = 0, int l_end = -1, float* stop_delay = nullptr,
+                       const TransitOut* tr = nullptr);
+
+// plain-interval loading by children-before-parent accumulation (see the
+// kernels); cnt and acc: scratch indexed like the labels, all zero before and
+// after; every instance must be plain (no truncation)
+hipError_t launch_sweep(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
+                        int64_t* y, int32_t* stop, float* stop_delay, const InstState* st, const FlagsDev& fl,
+                        uint32_t* cnt, int64_t* acc);
 
 hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                            const float* tree_cost, const float* time_cost, int64_t* y, int32_t* stop,
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int64_t* r_dense,
                            unsigned long long* done_fx,
-                           int trees_mode, int32_t* succ_out, int32_t n_out);
+                           int trees_mode, int32_t* succ_out, int32_t n_out, float* stop_delay = nullptr,
+                           const TransitOut* tr = nullptr);
 
 // residual accumulator (indexed like the labels) -> legs in (destination, origin) order
 hipError_t launch_resid_count(hipStream_t s, const NetDev& net, const DemDev& dem, const int64_t* r_dense,

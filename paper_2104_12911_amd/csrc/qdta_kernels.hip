@@ -32,6 +32,7 @@ typedef __int128 i128;
 #define RULE_NONE 0
 #define RULE_CEIL 1
 #define RULE_FLOOR 2
+#define RULE_PROGRESS 3
 
 static constexpr double kFxInv = 1.0 / 1048576.0;   // 2^-20, exact
 static constexpr double kSumQ = 65536.0;            // 2^16
@@ -967,6 +968,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int32_t* nearq = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
     uint2* farq = reinterpret_cast<uint2*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
+    unsigned long long n_taken = 0, n_relaxed = 0;    // counted by every thread alike (uniform values)
     for (;;) {
         if (tid == 0) s_t = t_begin + atomicAdd(scr.work, 1);
         __syncthreads();
@@ -1124,6 +1126,8 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
                 __syncthreads();
                 const int total = base;
                 ncnt -= k;
+                n_taken += (unsigned)k;
+                n_relaxed += (unsigned)total;
                 for (int g0 = 0; g0 < total; g0 += NT * V) {
                     int vv[V];
                     float cd[V];
@@ -1268,6 +1272,320 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
         }
         __syncthreads();
     }
+    if (scr.stats && tid == 0) {
+        atomicAdd(&scr.stats[0], n_taken);
+        atomicAdd(&scr.stats[1], n_relaxed);
+    }
+}
+
+template <int U, int V>
+__global__ __launch_bounds__(kWG) void k_sssp_wn(NetDev net, DemDev dem, const uint2* __restrict__ radj,
+                                                 label_t* labels, Scratch scr, const InstState* st,
+                                                 const float* __restrict__ delta_inst, int early, int t_begin,
+                                                 int t_end) {
+    constexpr int NT = kWG;
+    constexpr int NW = NT / 64;
+    constexpr int NP = NT * U;                    // nodes per step
+    __shared__ int s_pre[NP + 1];
+    __shared__ float s_dw[NP];
+    __shared__ int s_e0[NP];
+    __shared__ int s_rh[64], s_rc[64], s_rhp[64], s_tail[64], s_push[64], s_tpre[64];
+    __shared__ int s_wsum[NW];
+    __shared__ int s_t, s_nn, s_fn;
+    __shared__ uint32_t s_fm;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int32_t* nearq = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
+    uint2* farq = reinterpret_cast<uint2*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
+    unsigned long long n_taken = 0, n_relaxed = 0;    // counted by every thread alike (uniform values)
+    for (;;) {
+        if (tid == 0) s_t = t_begin + atomicAdd(scr.work, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();
+        if (t >= t_end) break;
+        const int inst = dem.dest_inst[t];
+        if (!inst_live(st, inst)) continue;
+        const InstDev I = net.inst[inst];
+        const int n = I.n, node0 = I.node0;
+        const int* __restrict__ rptr = net.rptr + node0;
+        label_t* D = labels + dem.dest_lab[t];
+        const int root = dem.dest_node[t] - node0;
+        const float delta = delta_inst[inst];
+        {
+            uint4* D4 = reinterpret_cast<uint4*>(D);
+            const uint32_t w0 = kNotQueued | kInfBits;
+            const uint4 inf4 = make_uint4(w0, w0, w0, w0);
+            const int n4 = (n + 31) / 32 * 8;
+            for (int i = tid; i < n4; i += NT) D4[i] = inf4;
+        }
+        int rsh = 0;
+        while (((n - 1) >> rsh) >= 64) ++rsh;
+        const int rs = 1 << rsh;
+        const int nranges = ((n - 1) >> rsh) + 1;
+        if (tid < 64) {
+            s_rh[tid] = 0;
+            s_rc[tid] = (tid == (root >> rsh)) ? 1 : 0;
+            s_push[tid] = 0;
+        }
+        if (tid == 0) {
+            s_nn = 0;
+            s_fn = 0;
+            s_fm = kInfBits;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) {
+            D[root] = 0u;                         // value 0, queued
+            nearq[(root >> rsh) * (rs + 1)] = root;
+        }
+        __threadfence_block();
+        __syncthreads();
+        auto ring_at = [&](int r, int pos) -> int32_t* {
+            const int cap = min(rs, n - r * rs) + 1;
+            if (pos >= cap) pos -= cap;
+            return nearq + (int64_t)r * (rs + 1) + pos;
+        };
+        auto push_near = [&](int v) {
+            const int r = v >> rsh;
+            *ring_at(r, s_tail[r] + atomicAdd(&s_push[r], 1)) = v;
+            atomicAdd(&s_nn, 1);
+        };
+        // wavefront 0: tails of the rings for the pushes to come
+        auto open_push = [&]() {
+            if (wv == 0) {
+                const int cap = lane < nranges ? min(rs, n - lane * rs) + 1 : 1;
+                int tl = s_rh[lane] + s_rc[lane];
+                if (tl >= cap) tl -= cap;
+                s_tail[lane] = tl;
+                s_push[lane] = 0;
+            }
+        };
+        // after a pushing phase (all threads past a barrier): counts folded in
+        int ncnt = 1, fcnt = 0;
+        float thr = delta, fmin = __uint_as_float(kInfBits);
+        auto fold = [&]() -> int {
+            __threadfence_block();
+            __syncthreads();
+            const int nn = s_nn, fn = s_fn;
+            const float fm = __uint_as_float(s_fm);
+            __syncthreads();
+            if (wv == 0) {
+                if (lane < nranges) s_rc[lane] += s_push[lane];
+                s_push[lane] = 0;
+            }
+            if (tid == 0) {
+                s_nn = 0;
+                s_fn = 0;
+                s_fm = kInfBits;
+            }
+            ncnt += nn;
+            fcnt += fn;
+            fmin = fminf(fmin, fm);
+            return nn;
+        };
+        int lcur = early ? dem.qptr[t] : 0;
+        const int lend = early ? dem.qptr[t + 1] : 0;
+        for (;;) {
+            while (ncnt > 0) {
+                const int k = ncnt < NP ? ncnt : NP;
+                if (wv == 0) {
+                    const int rc = s_rc[lane], rh = s_rh[lane];
+                    int incl = rc;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int x = __shfl_up(incl, o);
+                        if (lane >= o) incl += x;
+                    }
+                    const int excl = incl - rc;
+                    const int take = max(0, min(rc, NP - excl));
+                    const int cap = lane < nranges ? min(rs, n - lane * rs) + 1 : 1;
+                    s_tpre[lane] = min(excl, NP);
+                    s_rhp[lane] = rh;
+                    int nh = rh + take;
+                    if (nh >= cap) nh -= cap;
+                    s_rh[lane] = nh;
+                    s_rc[lane] = rc - take;
+                    int tl = nh + rc - take;
+                    if (tl >= cap) tl -= cap;
+                    s_tail[lane] = tl;
+                    s_push[lane] = 0;
+                }
+                __syncthreads();
+                // every thread takes up to U nodes and relaxes all their in-links
+                // itself: in-degrees of road networks are small, so the owner
+                // search and the degree prefix sum of k_sssp_wg are left out
+                int wn_[U], e0_[U], e1_[U];
+                float dw_[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = u * NT + tid;
+                    wn_[u] = -1;
+                    e0_[u] = e1_[u] = 0;
+                    dw_[u] = 0.0f;
+                    if (j < k) {
+                        int lo = 0, hi = 64;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_tpre[mid] <= j) lo = mid; else hi = mid;
+                        }
+                        wn_[u] = *ring_at(lo, s_rhp[lo] + (j - s_tpre[lo]));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (wn_[u] < 0) continue;
+                    const uint32_t lw = atomicOr(&D[wn_[u]], kNotQueued);   // dequeue, read the label
+                    e0_[u] = rptr[wn_[u]];
+                    e1_[u] = rptr[wn_[u] + 1];
+                    dw_[u] = __uint_as_float(lw & kValueBits);
+                }
+                ncnt -= k;
+                n_taken += (unsigned)k;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    for (int e = e0_[u]; e < e1_[u]; e += V) {
+                        int vv[V];
+                        float cd[V];
+                        bool ok[V];
+#pragma unroll
+                        for (int x = 0; x < V; ++x) {
+                            ok[x] = e + x < e1_[u];
+                            vv[x] = 0;
+                            cd[x] = 0.0f;
+                            if (ok[x]) {
+                                const uint2 r = radj[e + x];
+                                vv[x] = (int)r.x - node0;
+                                cd[x] = dw_[u] + __uint_as_float(r.y);
+                            }
+                        }
+                        uint32_t cur[V];
+#pragma unroll
+                        for (int x = 0; x < V; ++x) cur[x] = ok[x] ? (ld_coherent(&D[vv[x]]) & kValueBits) : 0u;
+#pragma unroll
+                        for (int x = 0; x < V; ++x) {
+                            const uint32_t cb = __float_as_uint(cd[x]);
+                            if (ok[x] && cb < cur[x] && (atomicMin(&D[vv[x]], cb) & kNotQueued)) {
+                                if (cd[x] < thr) {
+                                    push_near(vv[x]);
+                                } else {
+                                    farq[fcnt + atomicAdd(&s_fn, 1)] = make_uint2((uint32_t)vv[x], cb);
+                                    atomicMin(&s_fm, cb);
+                                }
+                            }
+                        }
+                    }
+                    n_relaxed += (unsigned)(e1_[u] - e0_[u]);
+                }
+                fold();
+            }
+            if (early) {
+                bool pend = false;
+                while (lcur < lend) {
+                    const int l = lcur + tid;
+                    bool p = false;
+                    if (l < lend) {
+                        const int o = dem.leg_orig[l] - node0;
+                        p = !(__uint_as_float(ld_coherent(&D[o]) & kValueBits) < thr);
+                    }
+                    if (__syncthreads_or(p)) { pend = true; break; }
+                    lcur += NT;
+                }
+                if (!pend) {
+                    // exact: queue the far nodes whose current label is below thr
+                    int moved = 0, keep = 0;
+                    float km = __uint_as_float(kInfBits);
+                    open_push();
+                    __syncthreads();
+                    for (int i0 = 0; i0 < fcnt; i0 += NT) {
+                        const int i = i0 + tid;
+                        const bool h = i < fcnt;
+                        uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                        if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;   // the label now
+                        const bool late = h && __uint_as_float(ent.y) < thr;
+                        __syncthreads();                  // the chunk is read before it is overwritten
+                        if (late) {
+                            push_near((int)ent.x);
+                        } else if (h) {
+                            farq[keep + atomicAdd(&s_fn, 1)] = ent;
+                            atomicMin(&s_fm, ent.y);
+                        }
+                        __threadfence_block();
+                        __syncthreads();
+                        const int nn = s_nn, fn = s_fn;
+                        const float fm = __uint_as_float(s_fm);
+                        __syncthreads();
+                        if (tid == 0) {
+                            s_nn = 0;
+                            s_fn = 0;
+                            s_fm = kInfBits;
+                        }
+                        ncnt += nn;
+                        moved += nn;
+                        keep += fn;
+                        km = fminf(km, fm);
+                    }
+                    if (wv == 0) {
+                        if (lane < nranges) s_rc[lane] += s_push[lane];
+                        s_push[lane] = 0;
+                    }
+                    __syncthreads();
+                    fcnt = keep;
+                    fmin = km;
+                    if (moved == 0) break;                // every label below thr is final
+                    continue;
+                }
+            }
+            if (fcnt == 0) break;
+            thr = fmaxf(thr, fmin) + delta;
+            if (!(thr > fmin)) thr = __uint_as_float(__float_as_uint(fmin) + 1u);
+            int keep = 0;
+            float km = __uint_as_float(kInfBits);
+            open_push();
+            __syncthreads();
+            for (int i0 = 0; i0 < fcnt; i0 += NT) {
+                const int i = i0 + tid;
+                const bool h = i < fcnt;
+                uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                // key by the label now: a far node improved since its push keeps
+                // its queued flag and is not pushed again, and waiting for the
+                // threshold to pass its old label would make every node it
+                // reaches meanwhile be popped again
+                if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;
+                __syncthreads();
+                if (h && __uint_as_float(ent.y) < thr) {
+                    push_near((int)ent.x);
+                } else if (h) {
+                    farq[keep + atomicAdd(&s_fn, 1)] = ent;
+                    atomicMin(&s_fm, ent.y);
+                }
+                __threadfence_block();
+                __syncthreads();
+                const int nn = s_nn, fn = s_fn;
+                const float fm = __uint_as_float(s_fm);
+                __syncthreads();
+                if (tid == 0) {
+                    s_nn = 0;
+                    s_fn = 0;
+                    s_fm = kInfBits;
+                }
+                ncnt += nn;
+                keep += fn;
+                km = fminf(km, fm);
+            }
+            if (wv == 0) {
+                if (lane < nranges) s_rc[lane] += s_push[lane];
+                s_push[lane] = 0;
+            }
+            __syncthreads();
+            fcnt = keep;
+            fmin = km;
+        }
+        __syncthreads();
+    }
+    if (scr.stats) {
+        for (int o = 32; o > 0; o >>= 1) n_relaxed += __shfl_xor(n_relaxed, o);
+        if (tid == 0) atomicAdd(&scr.stats[0], n_taken);
+        if (lane == 0) atomicAdd(&scr.stats[1], n_relaxed);
+    }
 }
 
 // Block-local form of the same delta-stepping.  The node ids of an instance
@@ -1331,6 +1649,7 @@ __global__ __launch_bounds__(kWG) void k_sssp_blk(NetDev net, DemDev dem, const 
     uint32_t* L = s_lab[wv];
     int* RP = s_rp[wv];
     uint2* A = s_adj[wv];
+    unsigned long long n_taken = 0, n_relaxed = 0;    // this lane's work, for the counters
     for (;;) {
         if (tid == 0) s_t = t_begin + atomicAdd(scr.work, 1);
         __syncthreads();
@@ -1499,7 +1818,12 @@ __global__ __launch_bounds__(kWG) void k_sssp_blk(NetDev net, DemDev dem, const 
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             du[r] = 0.0f;
-                            if (fit[r]) du[r] = __uint_as_float(atomicOr(&L[lane + 64 * r], kNotQueued) & kValueBits);
+                            if (fit[r]) {
+                                const int i = lane + 64 * r;
+                                du[r] = __uint_as_float(atomicOr(&L[i], kNotQueued) & kValueBits);
+                                n_taken += 1;
+                                n_relaxed += (unsigned)(RP[i + 1] - RP[i]);
+                            }
                         }
                         __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -1666,6 +1990,16 @@ __global__ __launch_bounds__(kWG) void k_sssp_blk(NetDev net, DemDev dem, const 
         }
         __syncthreads();
     }
+    if (scr.stats) {
+        for (int o = 32; o > 0; o >>= 1) {
+            n_taken += __shfl_xor(n_taken, o);
+            n_relaxed += __shfl_xor(n_relaxed, o);
+        }
+        if (lane == 0) {
+            atomicAdd(&scr.stats[0], n_taken);
+            atomicAdd(&scr.stats[1], n_relaxed);
+        }
+    }
 }
 
 // Bucket width per instance: delta = scale * (geometric mean link cost of the
@@ -1715,6 +2049,23 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
     int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
+    if (variant >= 24) {
+        // one workgroup per tree, every thread relaxing its own nodes' in-links
+        blocks = min(blocks, scr.nslots);
+        if (blocks <= 0) return hipErrorInvalidValue;
+        dim3 g(blocks), b(kWG);
+#define QDTA_SSSP_WN(U, V) \
+    hipLaunchKernelGGL((k_sssp_wn<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, t_begin, \
+                       t_end)
+        switch (variant - 24) {
+            case 0: QDTA_SSSP_WN(1, 4); break;
+            case 1: QDTA_SSSP_WN(2, 4); break;
+            case 2: QDTA_SSSP_WN(2, 2); break;
+            default: QDTA_SSSP_WN(1, 2); break;
+        }
+#undef QDTA_SSSP_WN
+        return hipGetLastError();
+    }
     if (variant >= 16) {
         // block-local trees, one workgroup per tree (scratch slot = workgroup)
         blocks = min(blocks, scr.nslots);
@@ -1817,19 +2168,24 @@ __device__ __forceinline__ int succ_rec(const NetDev& net, const label_t* lab, i
 struct WalkOut {
     int64_t* y;
     int32_t* stop;
+    float* stop_delay;           // AON mode, may be NULL: the delay a leg stops with (link-progress rule)
     int residual_mode;
     const double* lambda;        // per instance (residual mode)
     int64_t* r_dense;            // residual accumulator, indexed like the labels
     unsigned long long* done_fx;
+    TransitOut tr;               // residual mode, link-progress rule: legs left on a link
+    int* err;                    // set when the transit list overflows
 };
 
 // Residual mode adds rint(lambda d) of a leg that stops at s short of q to
-// the accumulator word of (tree qi, node s), whose label offset is lab0, and
-// counts the completed weight otherwise.
-__device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q, int64_t lab0, int inst, int node0,
-                                           int64_t d) {
+// the accumulator word of (tree qi, node s), whose label offset is lab0 --
+// or, when it stops on a link with a delay, appends it to the transit list
+// -- and counts the completed weight otherwise.
+__device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q, int qi, int64_t lab0, int inst,
+                                           int node0, int64_t d, float delay) {
     if (!o.residual_mode) {
         if (o.stop) o.stop[l] = s - node0;
+        if (o.stop_delay) o.stop_delay[l] = delay;
         return;
     }
     const int64_t w = (int64_t)__builtin_rint(o.lambda[inst] * (double)d);
@@ -1838,7 +2194,29 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
         return;
     }
     if (w == 0) return;
+    if (delay > 0.0f) {
+        const unsigned int k = atomicAdd(o.tr.n, 1u);
+        if (k < o.tr.cap) {
+            o.tr.q[k] = qi;
+            o.tr.node[k] = s - node0;
+            o.tr.delay[k] = delay;
+            o.tr.w[k] = w;
+        } else {
+            atomicOr(o.err, 1);
+        }
+        return;
+    }
     atomicAdd(reinterpret_cast<unsigned long long*>(&o.r_dense[lab0 + (s - node0)]), (unsigned long long)w);
+}
+
+// One step of the truncated walk (Eq. 2 read as CEIL / FLOOR / NONE, or the
+// link-progress rule): whether a leg at a node at time tau stops there, and
+// after entering a link (new time nt) whether it stops on it.  PROGRESS loads
+// as CEIL; a trip still on a link at dt stops at its head with delay
+// nt - dt (a trip on its last link completes), and a leg that starts with
+// its delay at or above dt is still on its way to its origin.
+__device__ __forceinline__ bool stop_at_node(int rule, float tau, float dt) {
+    return (rule == RULE_CEIL || rule == RULE_PROGRESS) && tau >= dt;
 }
 
 // time_cost: the costs that clock the truncation (Eq. 2); NULL = the trees'
@@ -1864,39 +2242,163 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
         if (o.stop) o.stop[l] = -1;
         return;
     }
-    float tau = 0.0f;
-    for (int hops = 0; u != q; ++hops) {
-        if (I.rule == RULE_CEIL && tau >= I.dt32) break;
-        int head = 0;
-        float ce = 0.0f;
-        const int e = succ_rec(net, lab, node0, u, du, head, ce);
-        if (e < 0 || hops > I.n) {                // absorption: finish in the fallback
-            fl.int_node[l] = u;
-            fl.int_tau[l] = tau;
-            fl.absorb_q[qi] = 1;
-            atomicAdd(fl.absorb_count, 1);
-            return;
+    float tau = dem.leg_delay ? dem.leg_delay[l] : 0.0f;
+    float delay = 0.0f;
+    if (I.rule == RULE_PROGRESS && tau >= I.dt32) {
+        delay = tau - I.dt32;                     // still on its way to its origin
+    } else {
+        for (int hops = 0; u != q; ++hops) {
+            if (stop_at_node(I.rule, tau, I.dt32)) break;
+            int head = 0;
+            float ce = 0.0f;
+            const int e = succ_rec(net, lab, node0, u, du, head, ce);
+            if (e < 0 || hops > I.n) {            // absorption: finish in the fallback
+                fl.int_node[l] = u;
+                fl.int_tau[l] = tau;
+                fl.absorb_q[qi] = 1;
+                atomicAdd(fl.absorb_count, 1);
+                return;
+            }
+            const float nt = tau + (time_cost ? time_cost[e] : ce);
+            if (I.rule == RULE_FLOOR && nt > I.dt32) break;
+            if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
+            tau = nt;
+            u = head;
+            du = lab_val(lab, u - node0);
+            if (I.rule == RULE_PROGRESS && tau > I.dt32) {
+                if (u != q) delay = tau - I.dt32;
+                break;
+            }
         }
-        const float nt = tau + (time_cost ? time_cost[e] : ce);
-        if (I.rule == RULE_FLOOR && nt > I.dt32) break;
-        if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
-        tau = nt;
-        u = head;
-        du = lab_val(lab, u - node0);
     }
-    finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
+    finish_leg(o, l, u, q, qi, dem.dest_lab[qi], inst, node0, d, delay);
 }
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
                        const float* time_cost, int64_t* y, int32_t* stop,
                        const InstState* st, const FlagsDev& fl, int residual_mode, const double* lambda,
                        int64_t* r_dense, unsigned long long* done_fx,
-                       int l_begin, int l_end) {
+                       int l_begin, int l_end, float* stop_delay, const TransitOut* tr) {
     if (l_end < 0) l_end = dem.P;
     if (l_end <= l_begin) return hipSuccess;
-    WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
+    WalkOut o{y, stop, stop_delay, residual_mode, lambda, r_dense, done_fx,
+              tr ? *tr : TransitOut{nullptr, nullptr, nullptr, nullptr, nullptr, 0u}, fl.err_overflow};
     hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels,
                        time_cost, st, fl, o, l_begin, l_end);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// A3, plain intervals: loading by children-before-parent accumulation
+// ---------------------------------------------------------------------------
+// Without truncation every leg of tree q loads its whole path to q, so the
+// flow on the successor link of v is the demand of all legs whose paths pass
+// through v.  Instead of walking every leg to q, the legs' paths are merged:
+//   pass 1 (k_sweep_count): each leg walks from its origin; at every node it
+//     reaches it adds 1 to the node's arrival count and goes on only if it
+//     was the first to arrive -- so each node's count is the number of legs
+//     and path branches that will bring demand into it;
+//   pass 2 (k_sweep_push): each leg starts again with its demand; at a node
+//     it adds what it carries to the node's accumulator and takes one off
+//     the count; the arrival that takes the count to zero is the last, takes
+//     the whole accumulated demand, loads the successor link with it and goes
+//     on to the parent.
+// Every link is loaded once per tree with the integer sum of the demand of
+// the legs that use it: the same int64 y as the walk.  Both scratch arrays
+// (indexed like the labels) are back at zero afterwards.  A tree where a
+// walker meets FP32 absorption is flagged; pass 2 walks its legs as k_walk
+// does (clearing the counts pass 1 left on their paths) and the tie
+// fallback finishes them.  Used only when every instance is plain.
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__global__ __launch_bounds__(kWG) void k_sweep_count(NetDev net, DemDev dem, const label_t* __restrict__ labels,
+                                                     const InstState* st, FlagsDev fl, uint32_t* cnt) {
+    const int l = blockIdx.x * kWG + threadIdx.x;
+    if (l >= dem.P) return;
+    const int qi = dem.leg_q[l];
+    const int inst = dem.dest_inst[qi];
+    if (!inst_live(st, inst)) return;
+    const InstDev I = net.inst[inst];
+    if (I.rule != RULE_NONE) return;
+    const int node0 = I.node0, q = dem.dest_node[qi];
+    const label_t* lab = tree_labels(labels, dem, qi);
+    uint32_t* C = cnt + dem.dest_lab[qi] - node0;       // indexed by global node id
+    int u = dem.leg_orig[l];
+    float du = lab_val(lab, u - node0);
+    if (!(du <= 3.4028234663852886e38f)) return;        // unreachable: reported by pass 2
+    for (int hops = 0; u != q; ++hops) {
+        if (atomicAdd(&C[u], 1u) != 0u) return;         // another arrival goes on from here
+        int head = 0;
+        float ce = 0.0f;
+        const int e = succ_rec(net, lab, node0, u, du, head, ce);
+        if (e < 0 || hops > I.n) {                      // absorption: this tree is walked
+            fl.absorb_q[qi] = 1;
+            return;
+        }
+        u = head;
+        du = lab_val(lab, u - node0);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_sweep_push(NetDev net, DemDev dem, const label_t* __restrict__ labels,
+                                                    const InstState* st, FlagsDev fl, WalkOut o, uint32_t* cnt,
+                                                    int64_t* acc) {
+    const int l = blockIdx.x * kWG + threadIdx.x;
+    if (l >= dem.P) return;
+    const int qi = dem.leg_q[l];
+    const int inst = dem.dest_inst[qi];
+    if (!inst_live(st, inst)) return;
+    const InstDev I = net.inst[inst];
+    const int node0 = I.node0, q = dem.dest_node[qi];
+    const label_t* lab = tree_labels(labels, dem, qi);
+    uint32_t* C = cnt + dem.dest_lab[qi] - node0;
+    int64_t* A = acc + dem.dest_lab[qi] - node0;
+    int u = dem.leg_orig[l];
+    float du = lab_val(lab, u - node0);
+    fl.int_node[l] = -1;
+    if (!(du <= 3.4028234663852886e38f)) {
+        atomicOr(fl.err_unreach, 1);
+        if (o.stop) o.stop[l] = -1;
+        return;
+    }
+    if (o.stop) o.stop[l] = q - node0;                  // without truncation every leg completes
+    if (o.stop_delay) o.stop_delay[l] = 0.0f;
+    const bool sweep = !ld_coherent(&fl.absorb_q[qi]);
+    int64_t carry = dem.leg_dfx[l];
+    for (int hops = 0; u != q; ++hops) {
+        if (sweep) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&A[u]), (unsigned long long)carry);
+            wait_memory();                              // the demand is in before the count drops
+            if (atomicSub(&C[u], 1u) != 1u) return;     // not the last arrival: done
+            carry = (int64_t)atomicExch(reinterpret_cast<unsigned long long*>(&A[u]), 0ull);
+        } else {
+            C[u] = 0u;                                  // a flagged tree: clear what pass 1 counted
+        }
+        int head = 0;
+        float ce = 0.0f;
+        const int e = succ_rec(net, lab, node0, u, du, head, ce);
+        if (e < 0 || hops > I.n) {                      // absorption (flagged trees only): the fallback
+            fl.int_node[l] = u;                         // finishes the leg
+            fl.int_tau[l] = 0.0f;
+            fl.absorb_q[qi] = 1;
+            atomicAdd(fl.absorb_count, 1);
+            return;
+        }
+        atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)carry);
+        u = head;
+        du = lab_val(lab, u - node0);
+    }
+}
+
+hipError_t launch_sweep(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
+                        int64_t* y, int32_t* stop, float* stop_delay, const InstState* st, const FlagsDev& fl,
+                        uint32_t* cnt, int64_t* acc) {
+    if (dem.P == 0) return hipSuccess;
+    const dim3 g((dem.P + kWG - 1) / kWG), b(kWG);
+    hipLaunchKernelGGL(k_sweep_count, g, b, 0, s, net, dem, labels, st, fl, cnt);
+    WalkOut o{y, stop, stop_delay, 0, nullptr, nullptr, nullptr,
+              TransitOut{nullptr, nullptr, nullptr, nullptr, nullptr, 0u}, fl.err_overflow};
+    hipLaunchKernelGGL(k_sweep_push, g, b, 0, s, net, dem, labels, st, fl, o, cnt, acc);
     return hipGetLastError();
 }
 
@@ -1982,8 +2484,9 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                 float tau = fl.int_tau[l];
                 float du = lab_val(lab, u - node0);
                 const int64_t d = dem.leg_dfx[l];
+                float delay = 0.0f;
                 for (int hops = 0; u != q && hops <= n; ++hops) {
-                    if (I.rule == RULE_CEIL && tau >= I.dt32) break;
+                    if (stop_at_node(I.rule, tau, I.dt32)) break;
                     const int e = succ_full(u, du);
                     if (e < 0) break;
                     const float nt = tau + time_cost[e];
@@ -1992,9 +2495,13 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                     tau = nt;
                     u = net.col[e];
                     du = lab_val(lab, u - node0);
+                    if (I.rule == RULE_PROGRESS && tau > I.dt32) {
+                        if (u != q) delay = tau - I.dt32;
+                        break;
+                    }
                 }
                 fl.int_node[l] = -1;
-                finish_leg(o, l, u, q, dem.dest_lab[qi], inst, node0, d);
+                finish_leg(o, l, u, q, qi, dem.dest_lab[qi], inst, node0, d, delay);
             }
         }
         __syncthreads();
@@ -2006,9 +2513,10 @@ hipError_t launch_fallback(hipStream_t s, const NetDev& net, const DemDev& dem, 
                            const InstState* st, const FlagsDev& fl, const Scratch& scr, int slots,
                            int residual_mode, const double* lambda, int64_t* r_dense,
                            unsigned long long* done_fx, int trees_mode,
-                           int32_t* succ_out, int32_t n_out) {
+                           int32_t* succ_out, int32_t n_out, float* stop_delay, const TransitOut* tr) {
     if (dem.Q == 0) return hipSuccess;
-    WalkOut o{y, stop, residual_mode, lambda, r_dense, done_fx};
+    WalkOut o{y, stop, stop_delay, residual_mode, lambda, r_dense, done_fx,
+              tr ? *tr : TransitOut{nullptr, nullptr, nullptr, nullptr, nullptr, 0u}, fl.err_overflow};
     hipLaunchKernelGGL(k_fallback, dim3(slots), dim3(kWG), 0, s, net, dem, labels, tree_cost, time_cost, st, fl, scr,
                        o, trees_mode, succ_out, n_out);
     return hipGetLastError();

@@ -29,9 +29,11 @@ struct Instance {
     double dt_s = INFINITY;
     std::vector<int32_t> orig, dest;
     std::vector<int64_t> dfx;
+    std::vector<float> delay;            // time each leg still needs to reach its origin (link-progress rule)
     // residual carried into the next interval (Alg. 4 output)
     std::vector<int32_t> r_orig, r_dest;
     std::vector<int64_t> r_w;
+    std::vector<float> r_delay;
     int64_t r_done = 0;
     // per-iteration step sizes of the last solve (alpha_0 = 1)
     std::vector<double> hist_alpha;
@@ -79,11 +81,20 @@ struct qdta_ctx {
     size_t label_count = 0;
     DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q;
     DBuf<int64_t> dest_lab, leg_dfx;
+    DBuf<float> leg_delay;
+    // legs the link-progress rule leaves on a link during the residual pass
+    DBuf<int32_t> tr_q, tr_node;
+    DBuf<float> tr_delay;
+    DBuf<int64_t> tr_w;
+    DBuf<unsigned int> tr_n;
     std::vector<int32_t> h_dest_inst, h_dest_node, h_qptr;
     DBuf<label_t> labels;         // 32-bit label words, tree-major, each tree 128-byte aligned
     DBuf<int32_t> nearq, farq;
 
     DBuf<int32_t> work;
+    DBuf<uint32_t> sw_cnt;            // plain-interval loading: arrival counts and accumulators,
+    DBuf<int64_t> sw_acc;             // indexed like the labels, zero between launches
+    DBuf<unsigned long long> sssp_stats;  // nodes taken, in-links relaxed (reset by qdta_profile_enable)
     DBuf<float> delta_inst;
     DBuf<double> logsum;
 
@@ -279,7 +290,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     if (!o) { set_err(c, QDTA_EARG, "opts is NULL"); return false; }
     if (!(o->alpha >= 0.0 && std::isfinite(o->alpha))) { set_err(c, QDTA_EARG, "alpha must be finite and >= 0"); return false; }
     if (o->beta < 1 || o->beta > 16) { set_err(c, QDTA_EARG, "beta must be in 1..16"); return false; }
-    if (o->trunc_rule < 0 || o->trunc_rule > 2) { set_err(c, QDTA_EARG, "bad trunc_rule"); return false; }
+    if (o->trunc_rule < 0 || o->trunc_rule > 3) { set_err(c, QDTA_EARG, "bad trunc_rule"); return false; }
     if (o->ls_mode < 0 || o->ls_mode > 2) { set_err(c, QDTA_EARG, "bad ls_mode"); return false; }
     if (o->K < 3 || o->K > kMaxK) { set_err(c, QDTA_EARG, "K must be in 3..64"); return false; }
     if (o->passes < 1 || o->passes > 8) { set_err(c, QDTA_EARG, "passes must be in 1..8"); return false; }
@@ -292,7 +303,8 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     if (o->max_iter < 0 || o->fixed_iters < 0) { set_err(c, QDTA_EARG, "negative iteration count"); return false; }
     if (o->waves_per_cu < 0 || o->waves_per_cu > 32) { set_err(c, QDTA_EARG, "waves_per_cu must be in 0..32"); return false; }
     if (o->sssp_shape < 0 || o->sssp_shape > 6) { set_err(c, QDTA_EARG, "sssp_shape must be in 0..6"); return false; }
-    if (o->sssp_kernel < 0 || o->sssp_kernel > 2) { set_err(c, QDTA_EARG, "sssp_kernel must be 0, 1 or 2"); return false; }
+    if (o->sssp_kernel < 0 || o->sssp_kernel > 3) { set_err(c, QDTA_EARG, "sssp_kernel must be 0..3"); return false; }
+    if (o->load_form < 0 || o->load_form > 2) { set_err(c, QDTA_EARG, "load_form must be 0, 1 or 2"); return false; }
     if (o->launch_form < 0 || o->launch_form > 2) { set_err(c, QDTA_EARG, "launch_form must be 0, 1 or 2"); return false; }
     if (o->tree_waves != 0 && o->tree_waves != 1 && o->tree_waves != 4) {
         set_err(c, QDTA_EARG, "tree_waves must be 0, 1 or 4");
@@ -311,7 +323,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 
 // wavefronts per tree: one only for the node-queue kernel asked to run one
 // tree per wavefront; the block-local kernel always takes a workgroup
-int tree_waves(const qdta_opts* o) { return (o->sssp_kernel != 2 && o->tree_waves == 1) ? 1 : 4; }
+int tree_waves(const qdta_opts* o) { return (o->sssp_kernel < 2 && o->tree_waves == 1) ? 1 : 4; }
 // FW updates a solve may apply (iterates 1..this, plus the initial AON)
 int hist_iters(const qdta_opts* o) { return o->fixed_iters > 0 ? o->fixed_iters : std::max(o->max_iter, 0); }
 int waves_per_cu(const qdta_opts* o) {
@@ -332,6 +344,10 @@ int sssp_variant(const qdta_ctx* c, const qdta_opts* o) {
     if (o->sssp_kernel == 2 && fits) {
         const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 4) ? o->sssp_shape - 1 : 1;
         return 16 + v;
+    }
+    if (o->sssp_kernel == 3) {
+        const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 4) ? o->sssp_shape - 1 : 1;
+        return 24 + v;
     }
     const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2;
     return tree_waves(o) == 1 ? v : v + 8;
@@ -485,6 +501,10 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
         c->scr_nmax = nm;
     }
     RC(dalloc(c, c->work, 1));
+    if (!c->sssp_stats.p) {
+        RC(dalloc(c, c->sssp_stats, 2));
+        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->sssp_stats.p), 0, 2));
+    }
     RC(dalloc(c, c->delta_inst, c->inst.size()));
     RC(dalloc(c, c->logsum, c->inst.size()));
     return QDTA_OK;
@@ -501,6 +521,7 @@ int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     int ni = (int)c->inst.size();
     std::vector<int32_t> qptr{0}, leg_orig, leg_q, dest_node, dest_inst;
     std::vector<int64_t> leg_dfx, dest_lab;
+    std::vector<float> leg_delay;
     c->leg_off.assign(ni + 1, 0);
     c->dest_off.assign(ni + 1, 0);
     int64_t nmax = 0, lab = 0;
@@ -524,6 +545,7 @@ int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
             while (p < I.orig.size() && I.dest[p] == q) {
                 leg_orig.push_back(d.node0 + I.orig[p]);
                 leg_dfx.push_back(I.dfx[p]);
+                leg_delay.push_back(p < I.delay.size() ? I.delay[p] : 0.0f);
                 leg_q.push_back(qi);
                 ++p;
             }
@@ -550,6 +572,7 @@ int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     RC(upload(c, c->leg_orig, leg_orig, pp));
     RC(upload(c, c->leg_dfx, leg_dfx, pp));
     RC(upload(c, c->leg_q, leg_q, pp));
+    RC(upload(c, c->leg_delay, leg_delay, pp));
     RC(upload(c, c->d_inst, c->h_inst));
     RC(dalloc(c, c->labels, std::max(c->label_count, c->ws_base ? pq * (size_t)tree_words(nmax) : 0)));
     RC(dalloc(c, c->absorb_q, pq));
@@ -587,6 +610,7 @@ DemDev dem_view(qdta_ctx* c) {
     v.leg_orig = c->leg_orig.p;
     v.leg_dfx = c->leg_dfx.p;
     v.leg_q = c->leg_q.p;
+    v.leg_delay = c->leg_delay.p;
     v.Q = (int32_t)c->Q;
     v.P = (int32_t)c->P;
     return v;
@@ -599,6 +623,7 @@ Scratch scr_view(qdta_ctx* c) {
     s.nmax = c->scr_nmax;
     s.work = c->work.p;
     s.nslots = c->scr_slots;
+    s.stats = c->sssp_stats.p;
     return s;
 }
 
@@ -653,8 +678,31 @@ void prof_collect(qdta_ctx* c) {
 
 // One all-or-nothing assignment (A2 + A3) under `cost` (reverse records already set).
 // time_cost: the travel times that clock the truncation; NULL = `cost`.
+// Plain-interval loading by merged paths: asked for, every instance plain,
+// batched launches.
+bool use_sweep(const qdta_ctx* c, const qdta_opts* o) {
+    if (o->load_form != 2 || o->launch_form == 2) return false;
+    for (const InstDev& d : c->h_inst)
+        if (d.rule != QDTA_RULE_NONE) return false;
+    return true;
+}
+
+// Its scratch, allocated (and cleared) before any launch that may be captured.
+int ensure_sweep(qdta_ctx* c, const qdta_opts* o) {
+    if (!use_sweep(c, o)) return QDTA_OK;
+    if (c->sw_cnt.n < c->label_count || !c->sw_cnt.p) {
+        RC(dalloc(c, c->sw_cnt, c->label_count));
+        HIPCHECK(c, launch_fill_u32(c->stream, c->sw_cnt.p, 0u, (int64_t)c->sw_cnt.n));
+    }
+    if (c->sw_acc.n < c->label_count || !c->sw_acc.p) {
+        RC(dalloc(c, c->sw_acc, c->label_count));
+        HIPCHECK(c, launch_fill_i64(c->stream, c->sw_acc.p, 0, (int64_t)c->sw_acc.n));
+    }
+    return QDTA_OK;
+}
+
 int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, const float* time_cost, int64_t* y, int32_t* stop,
-             const InstState* st, bool marks = true) {
+             const InstState* st, bool marks = true, float* stop_delay = nullptr) {
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
     FlagsDev fl = flags_view(c);
@@ -673,18 +721,21 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, const float* ti
     if (marks) RC(prof_mark(c, PH_WALK, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, y, 0, c->M));
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
-    if (o->launch_form == 2) {
+    if (use_sweep(c, o)) {
+        HIPCHECK(c, launch_sweep(c->stream, net, dem, c->labels.p, y, stop, stop_delay, st, fl, c->sw_cnt.p,
+                                 c->sw_acc.p));
+    } else if (o->launch_form == 2) {
         for (int64_t qi = 0; qi < c->Q; ++qi)
             HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, time_cost, y, stop, st, fl, 0, nullptr, nullptr,
-                                    nullptr, c->h_qptr[qi], c->h_qptr[qi + 1]));
+                                    nullptr, c->h_qptr[qi], c->h_qptr[qi + 1], stop_delay));
     } else {
         HIPCHECK(c, launch_walk(c->stream, net, dem, c->labels.p, time_cost, y, stop, st, fl, 0, nullptr, nullptr,
-                                nullptr));
+                                nullptr, 0, -1, stop_delay));
     }
     HIPCHECK(c, launch_fallback(c->stream, net, dem, c->labels.p, cost, time_cost ? time_cost : cost, y, stop, st, fl,
                                 scr_view(c),
                                 (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 0, nullptr, nullptr,
-                                nullptr, 0, nullptr, 0));
+                                nullptr, 0, nullptr, 0, stop_delay));
     if (marks) RC(prof_mark(c, PH_WALK, 1));
     return QDTA_OK;
 }
@@ -857,24 +908,28 @@ int ensure_history(qdta_ctx* c, size_t iters) {
 
 int64_t trips_fx(double t) { return (int64_t)std::nearbyint(t * 1048576.0); }
 
-// Sort legs by (dest, orig) and sum equal pairs; drop zero and orig == dest.
-void merge_legs(std::vector<int32_t>& o, std::vector<int32_t>& d, std::vector<int64_t>& w) {
+// Sort legs by (dest, orig, delay) and sum equal ones; drop zero and
+// orig == dest.  Delays are non-negative floats, which order like their bits.
+void merge_legs(std::vector<int32_t>& o, std::vector<int32_t>& d, std::vector<int64_t>& w, std::vector<float>& t) {
+    t.resize(o.size(), 0.0f);
+    auto key = [&](size_t i) { return std::make_tuple(d[i], o[i], __builtin_bit_cast(uint32_t, t[i])); };
     std::vector<size_t> idx(o.size());
     std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return d[a] != d[b] ? d[a] < d[b] : o[a] < o[b]; });
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return key(a) < key(b); });
     std::vector<int32_t> no, nd;
     std::vector<int64_t> nw;
+    std::vector<float> nt;
     for (size_t k = 0; k < idx.size(); ++k) {
         size_t i = idx[k];
-        if (!nd.empty() && nd.back() == d[i] && no.back() == o[i]) nw.back() += w[i];
-        else { no.push_back(o[i]); nd.push_back(d[i]); nw.push_back(w[i]); }
+        if (k > 0 && key(idx[k - 1]) == key(i)) nw.back() += w[i];
+        else { no.push_back(o[i]); nd.push_back(d[i]); nw.push_back(w[i]); nt.push_back(t[i]); }
     }
     size_t j = 0;
     for (size_t k = 0; k < no.size(); ++k) {
-        if (nw[k] > 0 && no[k] != nd[k]) { no[j] = no[k]; nd[j] = nd[k]; nw[j] = nw[k]; ++j; }
+        if (nw[k] > 0 && no[k] != nd[k]) { no[j] = no[k]; nd[j] = nd[k]; nw[j] = nw[k]; nt[j] = nt[k]; ++j; }
     }
-    no.resize(j); nd.resize(j); nw.resize(j);
-    o.swap(no); d.swap(nd); w.swap(nw);
+    no.resize(j); nd.resize(j); nw.resize(j); nt.resize(j);
+    o.swap(no); d.swap(nd); w.swap(nw); t.swap(nt);
 }
 
 }  // namespace
@@ -996,8 +1051,9 @@ int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int6
     add(ni, sizeof(InstState)); add((size_t)ni * 6, 8); add((size_t)ni * kMaxK * 6, 8); add((size_t)ni * kMaxK, 8);
     add(ni, 8); add(4, 4); add(ni, 8);
     // demand tables and shortest-path labels
-    add(pq, 4); add(pq, 4); add(pq, 8); add(pq + 1, 4); add(pp, 4); add(pp, 8); add(pp, 4);
+    add(pq, 4); add(pq, 4); add(pq, 8); add(pq + 1, 4); add(pp, 4); add(pp, 8); add(pp, 4); add(pp, 4);
     add(labels, 4); add(pq, 4); add(pp, 4); add(pp, 4);
+    if (o->load_form == 2) { add(labels, 4); add(labels, 8); }   // plain-interval loading by merged paths
     // shortest-path scratch (as ensure_scratch sizes it)
     {
         const int tw = tree_waves(o), wpc = waves_per_cu(o);
@@ -1007,13 +1063,17 @@ int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int6
         const int64_t need = tw == 1 ? slots : slots / 4;
         const int64_t nm = std::max<int64_t>(nmax, 1) + 65;
         add((size_t)(need * nm), 4); add((size_t)(need * nm * 2), 4);
-        add(1, 4); add(ni, 4); add(ni, 8);
+        add(1, 4); add(2, 8); add(ni, 4); add(ni, 8);
     }
     if (o->keep_history) {
         const size_t hcap = (size_t)(hist_iters(o) + 1);
         add((hcap + 1) * (size_t)M, 4);                             // per-iterate costs
         add(hcap * ni, sizeof(InstState)); add(hcap * ni, 8);       // residual pass: states, weights
         add(labels, 8); add(pq, 8); add(pp, 4); add(pp, 4); add(pp, 8);  // accumulator, counts, legs out
+        if (o->trunc_rule == QDTA_RULE_PROGRESS) {                       // legs left on links
+            const size_t tc = std::max(pp, hcap * (size_t)std::max<int64_t>(P, 1));
+            add(tc, 4); add(tc, 4); add(tc, 4); add(tc, 8); add(1, 4);
+        }
         if (o->history_mib > 0) b += align_up((size_t)o->history_mib << 20);
     }
     c->ws_max_legs = (int64_t)pp;
@@ -1096,47 +1156,58 @@ int qdta_set_demand(qdta_ctx* c, int32_t inst, int32_t P, const int32_t* orig, c
         d.push_back(dest[p]);
         w.push_back(trips_fx(trips[p]));
     }
-    // the pending residual is already in (destination, origin) order with
-    // positive weights and origin != destination: sort the new legs alone,
-    // then merge the two runs (equal legs add up)
-    merge_legs(o, d, w);
+    // the pending residual is already in (destination, origin, delay) order
+    // with positive weights and origin != destination: sort the new legs
+    // alone (no delay), then merge the two runs (equal legs add up)
+    std::vector<float> t;
+    merge_legs(o, d, w, t);
     if (!I.r_orig.empty()) {
         const size_t na = o.size(), nb = I.r_orig.size();
         std::vector<int32_t> mo, md;
         std::vector<int64_t> mw;
+        std::vector<float> mt;
         mo.reserve(na + nb);
         md.reserve(na + nb);
         mw.reserve(na + nb);
+        mt.reserve(na + nb);
+        auto key_a = [&](size_t i) { return std::make_tuple(d[i], o[i], __builtin_bit_cast(uint32_t, t[i])); };
+        auto key_b = [&](size_t i) {
+            return std::make_tuple(I.r_dest[i], I.r_orig[i], __builtin_bit_cast(uint32_t, I.r_delay[i]));
+        };
         size_t a = 0, b = 0;
         while (a < na || b < nb) {
             int cmp;
             if (a == na) cmp = 1;
             else if (b == nb) cmp = -1;
-            else if (d[a] != I.r_dest[b]) cmp = d[a] < I.r_dest[b] ? -1 : 1;
-            else cmp = o[a] < I.r_orig[b] ? -1 : (o[a] > I.r_orig[b] ? 1 : 0);
+            else cmp = key_a(a) < key_b(b) ? -1 : (key_b(b) < key_a(a) ? 1 : 0);
             if (cmp <= 0) {
                 mo.push_back(o[a]);
                 md.push_back(d[a]);
                 mw.push_back(w[a] + (cmp == 0 ? I.r_w[b] : 0));
+                mt.push_back(t[a]);
                 ++a;
                 if (cmp == 0) ++b;
             } else {
                 mo.push_back(I.r_orig[b]);
                 md.push_back(I.r_dest[b]);
                 mw.push_back(I.r_w[b]);
+                mt.push_back(I.r_delay[b]);
                 ++b;
             }
         }
         o.swap(mo);
         d.swap(md);
         w.swap(mw);
+        t.swap(mt);
     }
     I.orig.swap(o);
     I.dest.swap(d);
     I.dfx.swap(w);
+    I.delay.swap(t);
     I.r_orig.clear();
     I.r_dest.clear();
     I.r_w.clear();
+    I.r_delay.clear();
     I.dt_s = dt_s;
     I.has_demand = true;
     I.solved_iters = -1;
@@ -1169,7 +1240,7 @@ int qdta_offsets(qdta_ctx* c, int64_t* node_off, int64_t* link_off, int64_t* leg
     return QDTA_OK;
 }
 
-int qdta_get_legs(qdta_ctx* c, int32_t* ho, int32_t* hd, int64_t* hw) {
+int qdta_get_legs(qdta_ctx* c, int32_t* ho, int32_t* hd, int64_t* hw, float* ht) {
     if (!c) return QDTA_EARG;
     size_t k = 0;
     for (const Instance& I : c->inst) {
@@ -1177,6 +1248,7 @@ int qdta_get_legs(qdta_ctx* c, int32_t* ho, int32_t* hd, int64_t* hw) {
             if (ho) ho[k] = I.orig[p];
             if (hd) hd[k] = I.dest[p];
             if (hw) hw[k] = I.dfx[p];
+            if (ht) ht[k] = p < I.delay.size() ? I.delay[p] : 0.0f;
         }
     }
     return QDTA_OK;
@@ -1273,20 +1345,22 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
     return rc;
 }
 
-int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop) {
+int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int32_t* stop, float* stop_delay) {
     if (!c) return QDTA_EARG;
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!cost || !y) return set_err(c, QDTA_EARG, "null array");
     RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
+    RC(ensure_sweep(c, o));
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
     NetDev net = net_view(c);
     HIPCHECK(c, hipMemcpyAsync(c->cost.p, cost, sizeof(float) * c->M, hipMemcpyDeviceToDevice, c->stream));
     HIPCHECK(c, launch_scatter_rcost(c->stream, net, c->cost.p, c->radj.p));
     if (stop) HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(stop), 0xffffffffu, c->P));
-    RC(aon_core(c, o, c->cost.p, nullptr, y, stop, nullptr));
+    if (stop_delay) HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(stop_delay), 0u, c->P));
+    RC(aon_core(c, o, c->cost.p, nullptr, y, stop, nullptr, true, stop_delay));
     int h[4];
     RC(read_flags(c, h));
     prof_collect(c);
@@ -1350,6 +1424,7 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solving");
     RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
+    RC(ensure_sweep(c, o));
     NetDev net = net_view(c, o);
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
@@ -1541,6 +1616,7 @@ int qdta_fw_step(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs, int32_t* live_
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (c->fw_j < 0 || c->dem_dirty) return set_err(c, QDTA_ESTATE, "qdta_fw_step needs qdta_fw_begin");
+    RC(ensure_sweep(c, o));
     int h[4] = {0, 0, 0, 0};
     if (c->fw_live) RC(fw_iteration(c, o, h));
     else {
@@ -1645,6 +1721,8 @@ int qdta_profile_enable(qdta_ctx* c, int32_t on) {
         }
     }
     c->prof_on = on ? 1 : 0;
+    if (c->sssp_stats.p)
+        HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->sssp_stats.p), 0, 2));
     return QDTA_OK;
 }
 
@@ -1655,12 +1733,19 @@ int qdta_profile_read(qdta_ctx* c, qdta_profile* out) {
         out->ms[p] = c->prof_ms[p];
         out->count[p] = c->prof_n[p];
     }
+    if (c->sssp_stats.p) {
+        unsigned long long h[2] = {0, 0};
+        HIPCHECK(c, hipMemcpyAsync(h, c->sssp_stats.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        out->sssp_nodes = (int64_t)h[0];
+        out->sssp_links = (int64_t)h[1];
+    }
     return QDTA_OK;
 }
 
 int qdta_get_flows(qdta_ctx* c, int64_t* f) {
     if (!c || !f) return QDTA_EARG;
-    if (!c->solved) return set_err(c, QDTA_ESTATE, "no solved interval");
+    if (!c->solved && c->fw_j < 0) return set_err(c, QDTA_ESTATE, "no solved or running interval");
     HIPCHECK(c, hipMemcpyAsync(f, c->f.p, sizeof(int64_t) * c->M, hipMemcpyDeviceToDevice, c->stream));
     return QDTA_OK;
 }
@@ -1668,7 +1753,7 @@ int qdta_get_flows(qdta_ctx* c, int64_t* f) {
 int qdta_get_costs(qdta_ctx* c, const qdta_opts* o, float* cost) {
     if (!c || !cost) return QDTA_EARG;
     if (!opts_ok(c, o)) return QDTA_EARG;
-    if (!c->solved) return set_err(c, QDTA_ESTATE, "no solved interval");
+    if (!c->solved && c->fw_j < 0) return set_err(c, QDTA_ESTATE, "no solved or running interval");
     HIPCHECK(c, launch_bpr(c->stream, net_view(c), c->f.p, o->alpha, o->beta, cost, nullptr, nullptr, 0, c->flags.p));
     return QDTA_OK;
 }
@@ -1730,6 +1815,22 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
     const size_t zero_after = c->r_dense_zero;
     c->r_dense_zero = 0;
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->done_fx.p), 0, ni));
+    // the link-progress rule leaves legs on links: they go to a transit list
+    // (at most one entry per iterate and leg)
+    bool progress = false;
+    for (int i = 0; i < ni; ++i) progress |= c->h_inst[i].rule == QDTA_RULE_PROGRESS;
+    TransitOut tr{nullptr, nullptr, nullptr, nullptr, nullptr, 0u};
+    if (progress) {
+        const size_t cap = plan_legs(c, (size_t)(J + 1) * (size_t)std::max<int64_t>(c->P, 1));
+        if (cap >= UINT32_MAX) return set_err(c, QDTA_EARG, "too many legs in transit for one pass");
+        RC(dalloc(c, c->tr_q, cap));
+        RC(dalloc(c, c->tr_node, cap));
+        RC(dalloc(c, c->tr_delay, cap));
+        RC(dalloc(c, c->tr_w, cap));
+        RC(dalloc(c, c->tr_n, 1));
+        HIPCHECK(c, launch_fill_u32(c->stream, c->tr_n.p, 0u, 1));
+        tr = TransitOut{c->tr_q.p, c->tr_node.p, c->tr_delay.p, c->tr_w.p, c->tr_n.p, (unsigned int)cap};
+    }
     for (int j = 0; j <= J; ++j) {
         if (!any[j]) continue;
         const InstState* stj = c->st_hist.p + (size_t)j * ni;
@@ -1746,10 +1847,11 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         }
         HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
         HIPCHECK(c, launch_walk(c->stream, net, dem, lab, c->cfin.p, nullptr, nullptr, stj, fl, 1, lamj,
-                                c->r_dense.p, c->done_fx.p));
+                                c->r_dense.p, c->done_fx.p, 0, -1, nullptr, progress ? &tr : nullptr));
         HIPCHECK(c, launch_fallback(c->stream, net, dem, lab, cj, c->cfin.p, nullptr, nullptr, stj, fl,
                                     scr_view(c), (int)std::min<int64_t>(c->scr_slots, std::max<int64_t>(c->Q, 1)), 1,
-                                    lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0));
+                                    lamj, c->r_dense.p, c->done_fx.p, 0, nullptr, 0, nullptr,
+                                    progress ? &tr : nullptr));
     }
     // compact: legs per tree, offsets, then the legs in (destination, origin) order
     RC(dalloc(c, c->r_cnt, plan_dests(c, (size_t)std::max<int64_t>(c->Q, 1))));
@@ -1780,6 +1882,24 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
     std::vector<unsigned long long> done(ni);
     HIPCHECK(c, hipMemcpyAsync(done.data(), c->done_fx.p, sizeof(unsigned long long) * ni, hipMemcpyDeviceToHost,
                                c->stream));
+    unsigned int ntr = 0;
+    std::vector<int32_t> tq, tnode;
+    std::vector<float> tdl;
+    std::vector<int64_t> tw;
+    if (progress) {
+        HIPCHECK(c, hipMemcpyAsync(&ntr, c->tr_n.p, sizeof(ntr), hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        ntr = std::min(ntr, tr.cap);
+        tq.resize(ntr); tnode.resize(ntr); tdl.resize(ntr); tw.resize(ntr);
+        if (ntr) {
+            HIPCHECK(c, hipMemcpyAsync(tq.data(), c->tr_q.p, sizeof(int32_t) * ntr, hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(c, hipMemcpyAsync(tnode.data(), c->tr_node.p, sizeof(int32_t) * ntr, hipMemcpyDeviceToHost,
+                                       c->stream));
+            HIPCHECK(c, hipMemcpyAsync(tdl.data(), c->tr_delay.p, sizeof(float) * ntr, hipMemcpyDeviceToHost,
+                                       c->stream));
+            HIPCHECK(c, hipMemcpyAsync(tw.data(), c->tr_w.p, sizeof(int64_t) * ntr, hipMemcpyDeviceToHost, c->stream));
+        }
+    }
     int h[4];
     RC(read_flags(c, h));                  // synchronises the stream
     c->r_dense_zero = zero_after;
@@ -1794,8 +1914,22 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
         I.r_dest.resize(k1 - k);
         for (int64_t x = k; x < k1; ++x) I.r_dest[x - k] = c->h_dest_node[hq[x]] - c->h_inst[i].node0;
         I.r_w.assign(hw.begin() + k, hw.begin() + k1);
+        I.r_delay.assign((size_t)(k1 - k), 0.0f);
         I.r_done = (int64_t)done[i];
         k = k1;
+    }
+    if (ntr) {
+        // legs on links join their instance's residual; the merge sorts by
+        // (destination, origin, delay) and adds up equal legs
+        for (unsigned int x = 0; x < ntr; ++x) {
+            const int qi = tq[x];
+            Instance& I = c->inst[c->h_dest_inst[qi]];
+            I.r_orig.push_back(tnode[x]);
+            I.r_dest.push_back(c->h_dest_node[qi] - c->h_inst[c->h_dest_inst[qi]].node0);
+            I.r_w.push_back(tw[x]);
+            I.r_delay.push_back(tdl[x]);
+        }
+        for (Instance& I : c->inst) merge_legs(I.r_orig, I.r_dest, I.r_w, I.r_delay);
     }
     c->solved = false;
     RC(flag_code(c, h));
@@ -1803,7 +1937,7 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
 }
 
 int qdta_get_residual(qdta_ctx* c, int32_t inst, int64_t* count, int32_t* ho, int32_t* hd, int64_t* hw,
-                      int64_t* done) {
+                      int64_t* done, float* ht) {
     if (!c || !count) return QDTA_EARG;
     if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
     const Instance& I = c->inst[inst];
@@ -1812,6 +1946,7 @@ int qdta_get_residual(qdta_ctx* c, int32_t inst, int64_t* count, int32_t* ho, in
     if (ho) std::copy(I.r_orig.begin(), I.r_orig.end(), ho);
     if (hd) std::copy(I.r_dest.begin(), I.r_dest.end(), hd);
     if (hw) std::copy(I.r_w.begin(), I.r_w.end(), hw);
+    if (ht) std::copy(I.r_delay.begin(), I.r_delay.end(), ht);
     return QDTA_OK;
 }
 
@@ -1826,6 +1961,8 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
     if (!c) return QDTA_EARG;
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
+    if (o->trunc_rule == QDTA_RULE_PROGRESS)
+        return set_err(c, QDTA_EARG, "the frozen-path model does not take the link-progress rule");
     if (c->inst.size() != 1) return set_err(c, QDTA_ESTATE, "the frozen-path model takes exactly one instance");
     if (o->objective != QDTA_OBJ_UE) return set_err(c, QDTA_ESTATE, "the frozen-path model is the user equilibrium's");
     if (!c->solved || c->dem_dirty) return set_err(c, QDTA_ESTATE, "record needs a solved interval");
@@ -1964,7 +2101,7 @@ int qdta_model_backward(qdta_ctx* c, uint64_t fwd_id, const double* fbar, double
 }
 
 int qdta_set_residual(qdta_ctx* c, int32_t inst, int64_t count, const int32_t* ho, const int32_t* hd,
-                      const int64_t* hw) {
+                      const int64_t* hw, const float* ht) {
     if (!c) return QDTA_EARG;
     c->err.clear();
     if (inst < 0 || inst >= (int32_t)c->inst.size()) return set_err(c, QDTA_EARG, "no instance %d", inst);
@@ -1974,12 +2111,22 @@ int qdta_set_residual(qdta_ctx* c, int32_t inst, int64_t count, const int32_t* h
         if (ho[p] < 0 || ho[p] >= I.n || hd[p] < 0 || hd[p] >= I.n || ho[p] == hd[p])
             return set_err(c, QDTA_EARG, "residual leg %lld: bad nodes", (long long)p);
         if (hw[p] <= 0) return set_err(c, QDTA_EARG, "residual leg %lld: weight <= 0", (long long)p);
-        if (p > 0 && !(hd[p - 1] < hd[p] || (hd[p - 1] == hd[p] && ho[p - 1] < ho[p])))
-            return set_err(c, QDTA_EARG, "residual leg %lld: not in (destination, origin) order", (long long)p);
+        const float tp = ht ? ht[p] : 0.0f;
+        if (!(tp >= 0.0f) || !std::isfinite(tp)) return set_err(c, QDTA_EARG, "residual leg %lld: bad delay", (long long)p);
+        if (p > 0) {
+            const float tq = ht ? ht[p - 1] : 0.0f;
+            const auto a = std::make_tuple(hd[p - 1], ho[p - 1], __builtin_bit_cast(uint32_t, tq));
+            const auto b = std::make_tuple(hd[p], ho[p], __builtin_bit_cast(uint32_t, tp));
+            if (!(a < b))
+                return set_err(c, QDTA_EARG, "residual leg %lld: not in (destination, origin, delay) order",
+                               (long long)p);
+        }
     }
     I.r_orig.assign(ho, ho + count);
     I.r_dest.assign(hd, hd + count);
     I.r_w.assign(hw, hw + count);
+    if (ht) I.r_delay.assign(ht, ht + count);
+    else I.r_delay.assign((size_t)count, 0.0f);
     I.r_done = 0;
     return QDTA_OK;
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libqdta.so")
 
 OK, EARG, ECSR, EVAL, EUNREACH, EOVF, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 WABSORB = 1
-RULE_NONE, RULE_CEIL, RULE_FLOOR = 0, 1, 2
+RULE_NONE, RULE_CEIL, RULE_FLOOR, RULE_PROGRESS = 0, 1, 2, 3
 LS_KSECTION, LS_QN, LS_MSA = 0, 1, 2
 OBJ_UE, OBJ_SO = 0, 1
 STOP_GAP, STOP_OBJ = 0, 1
@@ -42,7 +42,7 @@ class Opts(C.Structure):
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("sssp_shape", C.c_int32),
                 ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("history_mib", C.c_int32),
-                ("objective", C.c_int32), ("sssp_kernel", C.c_int32)]
+                ("objective", C.c_int32), ("sssp_kernel", C.c_int32), ("load_form", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -60,7 +60,8 @@ class LayoutInfo(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("count", C.c_int64 * 8)]
+    _fields_ = [("ms", C.c_double * 8), ("count", C.c_int64 * 8), ("sssp_nodes", C.c_int64),
+                ("sssp_links", C.c_int64)]
 
 
 class QdtaError(RuntimeError):
@@ -99,8 +100,8 @@ def lib():
         L.qdta_offsets.argtypes = [vp, vp, vp, vp, vp]
         L.qdta_bpr.argtypes = [vp, vp, vp, vp]
         L.qdta_trees.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
-        L.qdta_aon.argtypes = [vp, vp, vp, vp, vp]
-        L.qdta_get_legs.argtypes = [vp, vp, vp, vp]
+        L.qdta_aon.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.qdta_get_legs.argtypes = [vp, vp, vp, vp, vp]
         L.qdta_ls_eval.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.qdta_line_search.argtypes = [vp, vp, vp, vp, i32, vp]
         L.qdta_fw_update.argtypes = [vp, vp, vp, vp]
@@ -108,8 +109,8 @@ def lib():
         L.qdta_get_flows.argtypes = [vp, vp]
         L.qdta_get_costs.argtypes = [vp, vp, vp]
         L.qdta_advance_interval.argtypes = [vp, vp]
-        L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64)]
-        L.qdta_set_residual.argtypes = [vp, i32, i64, vp, vp, vp]
+        L.qdta_get_residual.argtypes = [vp, i32, C.POINTER(i64), vp, vp, vp, C.POINTER(i64), vp]
+        L.qdta_set_residual.argtypes = [vp, i32, i64, vp, vp, vp, vp]
         L.qdta_adjoint_record.argtypes = [vp, vp]
         L.qdta_model_forward.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_uint64)]
         L.qdta_model_backward.argtypes = [vp, C.c_uint64, vp, vp, vp]
@@ -231,11 +232,13 @@ class Context:
         self._rc(lib().qdta_offsets(self._h, *[_ptr(a) for a in arrs]))
         return dict(zip(["node", "link", "leg", "dest"], arrs))
 
-    def legs(self):
+    def legs(self, with_delay=False):
+        """(orig, dest, d_fx) of the current legs; with_delay adds their carried delays."""
         P = self.layout().total_legs
         o, d, w = np.zeros(P, np.int32), np.zeros(P, np.int32), np.zeros(P, np.int64)
-        self._rc(lib().qdta_get_legs(self._h, _ptr(o), _ptr(d), _ptr(w)))
-        return o, d, w
+        t = np.zeros(P, np.float32)
+        self._rc(lib().qdta_get_legs(self._h, _ptr(o), _ptr(d), _ptr(w), _ptr(t)))
+        return (o, d, w, t) if with_delay else (o, d, w)
 
     # --- hot-path pieces (device tensors) ------------------------------------
     def bpr(self, opts, f_fx, cost):
@@ -245,8 +248,8 @@ class Context:
         return self._rc(lib().qdta_trees(self._h, C.byref(opts), int(inst), _ptr(cost), int(dest.numel()), _ptr(dest),
                                          _ptr(dist), _ptr(succ)), allow=(OK, WABSORB))
 
-    def aon(self, opts, cost, y_fx, stop=None):
-        return self._rc(lib().qdta_aon(self._h, C.byref(opts), _ptr(cost), _ptr(y_fx), _ptr(stop)),
+    def aon(self, opts, cost, y_fx, stop=None, stop_delay=None):
+        return self._rc(lib().qdta_aon(self._h, C.byref(opts), _ptr(cost), _ptr(y_fx), _ptr(stop), _ptr(stop_delay)),
                         allow=(OK, WABSORB))
 
     def ls_eval(self, opts, f_fx, y_fx, alphas, sums):
@@ -286,7 +289,9 @@ class Context:
     def profile_read(self):
         p = Profile()
         self._rc(lib().qdta_profile_read(self._h, C.byref(p)))
-        return {name: (p.ms[i], p.count[i]) for i, name in enumerate(PHASES)}
+        out = {name: (p.ms[i], p.count[i]) for i, name in enumerate(PHASES)}
+        out["sssp_work"] = (p.sssp_nodes, p.sssp_links)
+        return out
 
     def get_flows(self, f_fx):
         self._rc(lib().qdta_get_flows(self._h, _ptr(f_fx)))
@@ -297,13 +302,17 @@ class Context:
     def advance_interval(self, opts):
         return self._rc(lib().qdta_advance_interval(self._h, C.byref(opts)), allow=(OK, WABSORB))
 
-    def residual(self, inst):
+    def residual(self, inst, with_delay=False):
+        """(orig, dest, w_fx, done_fx) of the pending residual; with_delay:
+        (orig, dest, w_fx, delay, done_fx)."""
         cnt, done = C.c_int64(), C.c_int64()
-        self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), None, None, None, C.byref(done)))
+        self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), None, None, None, C.byref(done), None))
         k = cnt.value
         o, d, w = np.zeros(k, np.int32), np.zeros(k, np.int32), np.zeros(k, np.int64)
-        self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), _ptr(o), _ptr(d), _ptr(w), C.byref(done)))
-        return o, d, w, done.value
+        t = np.zeros(k, np.float32)
+        self._rc(lib().qdta_get_residual(self._h, int(inst), C.byref(cnt), _ptr(o), _ptr(d), _ptr(w), C.byref(done),
+                                         _ptr(t)))
+        return (o, d, w, t, done.value) if with_delay else (o, d, w, done.value)
 
     def adjoint_record(self, opts):
         return self._rc(lib().qdta_adjoint_record(self._h, C.byref(opts)))
@@ -347,11 +356,12 @@ class Context:
         self._rc(lib().qdta_alloc_count(self._h, C.byref(n), C.byref(u)))
         return n.value, u.value
 
-    def set_residual(self, inst, orig, dest, w_fx):
+    def set_residual(self, inst, orig, dest, w_fx, delay=None):
         o, d, w = _np(orig, np.int32), _np(dest, np.int32), _np(w_fx, np.int64)
-        if not (len(o) == len(d) == len(w)):
+        t = None if delay is None else _np(delay, np.float32)
+        if not (len(o) == len(d) == len(w)) or (t is not None and len(t) != len(o)):
             raise ValueError("residual arrays differ in length")
-        self._rc(lib().qdta_set_residual(self._h, int(inst), len(o), _ptr(o), _ptr(d), _ptr(w)))
+        self._rc(lib().qdta_set_residual(self._h, int(inst), len(o), _ptr(o), _ptr(d), _ptr(w), _ptr(t)))
 
 
 def _frozen_path_flows_class():

@@ -135,6 +135,18 @@ def config3(interval: int = PEAK_INTERVAL) -> Workload:
     return Workload("config3", net, days[interval], extra={"zones": zones, "interval": interval})
 
 
+def config3_window(first: int, last: int = PEAK_INTERVAL) -> Workload:
+    """The config-3 network with the original legs of intervals first..last
+    of the same 19M-trip day (a list, one Demand per interval): running the
+    earlier ones carries their residual demand into the last, as in the full
+    day."""
+    net, zones, odr, tr = _config3_net(1.0)
+    want = set(range(first, last + 1))
+    days = day_demand(net.xy, zones, 19_000_000, odr, intervals=want)
+    return Workload("config3_window", net, [days[i] for i in range(first, last + 1)],
+                    extra={"zones": zones, "first": first, "last": last})
+
+
 def config3_day(scale: float = 1.0) -> Workload:
     """Full day (96 intervals) on the config-3 network; `scale` < 1 shrinks
     nodes, links, zones and trips together (1/20 scale for oracle runs)."""

@@ -434,6 +434,88 @@ def test_config3_peak_full_size(torch_dev, q, orc):
     fp64_check(st[0], ref)
 
 
+def test_config3_peak_interior_steps_and_residual_full_size(torch_dev, q, orc):
+    """The 1.0M-link network with the 08:00 legs plus those of the three
+    intervals before it carried in as residual demand (synthetic legs set
+    with qdta_set_residual; congested), dt = 900 s, CEIL.  For each of three
+    Frank-Wolfe updates, the direction y_j (the GPU's own BPR and AON on the
+    GPU's previous iterate, in a second context), the step size alpha_j and
+    the flows f_j equal the oracle's element by element, at least two steps
+    lying inside (0, 1); then the residual demand of Alg. 4 after those
+    updates equals the oracle's leg for leg."""
+    torch = torch_dev
+
+    def say(msg):                                  # the oracle's full-size legs take minutes: show progress
+        print(f"[interior full size] {msg}", flush=True)
+
+    w = synth.config3_window(29)
+    say("inputs generated")
+    net, peak, carried = w.net, w.demand[-1], w.demand[:-1]
+    co = np.concatenate([x.orig for x in carried])
+    cd = np.concatenate([x.dest for x in carried])
+    ct = np.concatenate([x.trips for x in carried])
+    ro_in, rd_in, rw_in = orc.demand_legs(co, cd, ct)
+    o, d, wfx = orc.merge_legs(np.concatenate([peak.orig, ro_in]), np.concatenate([peak.dest, rd_in]),
+                               np.concatenate([orc.trips_to_fx_array(peak.trips), rw_in]))
+    keep = (wfx > 0) & (o != d)
+    o, d, wfx = o[keep], d[keep], wfx[keep]
+    opts = q.default_opts(alpha=w.alpha, beta=w.beta, fixed_iters=3, keep_history=1)
+
+    def ctx_for():
+        c = q.Context()
+        c.add(net)
+        c.set_residual(0, ro_in, rd_in, rw_in)
+        c.set_demand(0, peak.orig, peak.dest, peak.trips, peak.dt_s)
+        return c
+
+    ctx, side = ctx_for(), ctx_for()
+    try:
+        lo, ld, lw = ctx.legs()
+        assert np.array_equal(lo, o) and np.array_equal(ld, d) and np.array_equal(lw, wfx)
+        f = torch.empty(net.m, dtype=torch.int64, device="cuda")
+        cost = torch.empty(net.m, dtype=torch.float32, device="cuda")
+        y = torch.empty(net.m, dtype=torch.int64, device="cuda")
+        ctx.fw_begin(opts)
+        ctx.get_flows(f)
+        fo, _, _ = orc.aon(net, net.fftt, o, d, wfx, 900.0)
+        assert np.array_equal(host(f), fo)
+        say("initial AON equal")
+        hist_alpha, hist_cost, interior = [1.0], [net.fftt.astype(np.float32)], 0
+        for j in (1, 2, 3):
+            f_prev = host(f).copy()
+            co_j, _ = orc.bpr(fo, net.fftt, net.cap, w.alpha, w.beta, 900.0)
+            yo, _, _ = orc.aon(net, co_j, o, d, wfx, 900.0)
+            ao, _, _ = orc.line_search(fo, yo, net.fftt, net.cap, w.alpha, w.beta, 900.0, j)
+            fo = orc.fw_update(fo, yo, ao)
+            # the GPU's direction from its own costs of its own previous iterate
+            side.bpr(opts, dev(torch, f_prev), cost)
+            side.aon(opts, cost, y)
+            assert np.array_equal(host(cost).view(np.uint32), co_j.view(np.uint32)), j
+            assert np.array_equal(host(y), yo), j
+            st, _ = ctx.fw_step(opts)
+            ctx.get_flows(f)
+            assert st[0]["last_alpha"] == ao, j
+            assert np.array_equal(host(f), fo), j
+            interior += 0.0 < ao < 1.0
+            say(f"update {j} equal, alpha {ao}")
+            hist_alpha.append(ao)
+            hist_cost.append(co_j)
+        assert interior >= 2
+        st, live = ctx.fw_step(opts)                 # the final test; the interval is solved
+        assert not live and st[0]["iters"] == 3
+        ctx.advance_interval(opts)
+        g_o, g_d, g_w, g_done = ctx.residual(0)
+        r_o, r_d, r_w, done, _ = orc.residual(net, fo, np.array(hist_alpha), np.stack(hist_cost), o, d, wfx,
+                                              alpha_b=w.alpha, beta=w.beta, dt_s=900.0)
+        r_o, r_d, r_w = orc.merge_legs(r_o, r_d, r_w)
+        say(f"residual: {r_o.size} legs")
+        assert np.array_equal(g_o, r_o) and np.array_equal(g_d, r_d) and np.array_equal(g_w, r_w)
+        assert g_done == done and r_o.size > 100_000
+    finally:
+        ctx.close()
+        side.close()
+
+
 def test_config4_full_batch_sampled(torch_dev, q, orc):
     """All 64 uneven networks at full size in one context (4.7M links,
     33,840 trees; one launch sequence per FW iteration, replayed as a HIP
