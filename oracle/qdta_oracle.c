@@ -892,41 +892,64 @@ int orc_residual(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
     graph_build(&g, n, m, row_ptr, col);
     int32_t *qptr;
     int32_t *idx = legs_by_dest(n, P, dest, &qptr);
-    float *D = (float *)malloc(sizeof(float) * (size_t)n);
-    int32_t *succ = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t *qu = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    heap_t h = {0};
-    int64_t cnt = 0, done = 0;
+    /* trees of different (iterate, destination) pairs are independent: they
+     * run in parallel, each leg's outcome goes to its own slot j * P + i (i =
+     * its rank among the legs sorted by destination), and the slots are
+     * gathered afterwards in the order (j, destination, leg) */
+    size_t nslot = (size_t)(J + 1) * (size_t)(P > 0 ? P : 1);
+    int32_t *t_orig = (int32_t *)malloc(sizeof(int32_t) * nslot);
+    int64_t *t_w = (int64_t *)calloc(nslot, sizeof(int64_t));
+    float *t_dl = (float *)malloc(sizeof(float) * nslot);
+    int64_t done = 0;
     for (int32_t j = 0; j <= J; ++j) {
         if (!(lam[j] > 0.0)) continue;
         const float *cj = hist_cost + (size_t)j * (size_t)m;
-        for (int32_t q = 0; q < n; ++q) {
-            int32_t b = qptr[q], e = qptr[q + 1];
-            if (b == e) continue;
-            int any = 0;
-            for (int32_t i = b; i < e; ++i)
-                if (d_fx[idx[i]] > 0 && orig[idx[i]] != q) { any = 1; break; }
-            if (!any) continue;
-            dijkstra_to(&g, cj, q, D, &h);
-            successors(&g, cj, q, D, succ, hop, qu);
-            for (int32_t i = b; i < e; ++i) {
-                int32_t p = idx[i];
-                if (d_fx[p] <= 0 || orig[p] == q) continue;
-                int64_t w = (int64_t)rint(lam[j] * (double)d_fx[p]);
-                float dl = 0.0f;
-                int32_t s = walk_leg(col, succ, cfin, orig[p], q, dt32, eff, tau0 ? tau0[p] : 0.0f, NULL, NULL, &dl);
-                if (s == q) { done += w; continue; }
-                if (w == 0) continue;
-                r_orig[cnt] = s; r_dest[cnt] = q; r_fx[cnt] = w;
-                if (r_delay) r_delay[cnt] = dl;
-                cnt++;
+#pragma omp parallel reduction(+ : done)
+        {
+            float *D = (float *)malloc(sizeof(float) * (size_t)n);
+            int32_t *succ = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+            int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+            int32_t *qu = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+            heap_t h = {0};
+#pragma omp for schedule(dynamic, 1)
+            for (int32_t q = 0; q < n; ++q) {
+                int32_t b = qptr[q], e = qptr[q + 1];
+                if (b == e) continue;
+                int any = 0;
+                for (int32_t i = b; i < e; ++i)
+                    if (d_fx[idx[i]] > 0 && orig[idx[i]] != q) { any = 1; break; }
+                if (!any) continue;
+                dijkstra_to(&g, cj, q, D, &h);
+                successors(&g, cj, q, D, succ, hop, qu);
+                for (int32_t i = b; i < e; ++i) {
+                    int32_t p = idx[i];
+                    if (d_fx[p] <= 0 || orig[p] == q) continue;
+                    int64_t w = (int64_t)rint(lam[j] * (double)d_fx[p]);
+                    float dl = 0.0f;
+                    int32_t s = walk_leg(col, succ, cfin, orig[p], q, dt32, eff, tau0 ? tau0[p] : 0.0f, NULL, NULL,
+                                         &dl);
+                    if (s == q) { done += w; continue; }
+                    size_t k = (size_t)j * (size_t)P + (size_t)i;
+                    t_orig[k] = s;
+                    t_w[k] = w;
+                    t_dl[k] = dl;
+                }
             }
+            free(D); free(succ); free(hop); free(qu); free(h.a);
         }
     }
+    int64_t cnt = 0;
+    for (int32_t j = 0; j <= J; ++j)
+        for (int32_t i = 0; i < P; ++i) {
+            size_t k = (size_t)j * (size_t)P + (size_t)i;
+            if (t_w[k] == 0) continue;
+            r_orig[cnt] = t_orig[k]; r_dest[cnt] = dest[idx[i]]; r_fx[cnt] = t_w[k];
+            if (r_delay) r_delay[cnt] = t_dl[k];
+            cnt++;
+        }
+    free(t_orig); free(t_w); free(t_dl);
     *n_out = cnt;
     *done_fx = done;
-    free(D); free(succ); free(hop); free(qu); free(h.a);
     free(idx); free(qptr); free(lam); free(cfin);
     graph_free(&g);
     return ORC_OK;

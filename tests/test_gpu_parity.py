@@ -505,9 +505,18 @@ def test_config3_peak_interior_steps_and_residual_full_size(torch_dev, q, orc):
         assert not live and st[0]["iters"] == 3
         ctx.advance_interval(opts)
         g_o, g_d, g_w, g_done = ctx.residual(0)
-        r_o, r_d, r_w, done, _ = orc.residual(net, fo, np.array(hist_alpha), np.stack(hist_cost), o, d, wfx,
-                                              alpha_b=w.alpha, beta=w.beta, dt_s=900.0)
-        r_o, r_d, r_w = orc.merge_legs(r_o, r_d, r_w)
+        # the oracle's residual pass by groups of destinations (residual legs of
+        # different destinations never merge), reporting progress in between
+        parts, done = [], 0
+        dq = np.unique(d)
+        for k, grp in enumerate(np.array_split(dq, 8)):
+            sel = np.isin(d, grp)
+            p_o, p_d, p_w, p_done, _ = orc.residual(net, fo, np.array(hist_alpha), np.stack(hist_cost), o[sel],
+                                                    d[sel], wfx[sel], alpha_b=w.alpha, beta=w.beta, dt_s=900.0)
+            parts.append((p_o, p_d, p_w))
+            done += p_done
+            say(f"oracle residual, destination group {k + 1} of 8")
+        r_o, r_d, r_w = orc.merge_legs(*(np.concatenate(x) for x in zip(*parts)))
         say(f"residual: {r_o.size} legs")
         assert np.array_equal(g_o, r_o) and np.array_equal(g_d, r_d) and np.array_equal(g_w, r_w)
         assert g_done == done and r_o.size > 100_000
