@@ -304,6 +304,20 @@ int qdta_get_legs(qdta_ctx *ctx, int32_t *host_orig, int32_t *host_dest, int64_t
 int qdta_ls_eval(qdta_ctx *ctx, const qdta_opts *opts, const int64_t *f_fx, const int64_t *y_fx,
                  int32_t K, const double *alphas, int64_t *sums);
 
+/* qdta_ls_eval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sums, bit for bit, with no hipMalloc, hipFree or allocating library
+ * call.  Its scratch (error flags and the exact accumulators) is a static
+ * array each device holds for the life of the process, looked up once per
+ * device by qdta_create: at most n_instances x K = 4,096 (e.g. 64 instances
+ * at K = 64); larger is QDTA_EARG.  The context must already be laid out on
+ * the device (any earlier call that uses it, e.g. qdta_layout; QDTA_ESTATE
+ * otherwise).  Every call on a device shares that device's scratch and keeps
+ * the last call's contents (each call clears what it uses first): calls that
+ * overlap on one device, on any streams or contexts, race.  Synchronises. */
+int qdta_ls_eval_noalloc(qdta_ctx *ctx, const qdta_opts *opts, const int64_t *f_fx, const int64_t *y_fx,
+                         int32_t K, const double *alphas, int64_t *sums);
+
 /* A5 -- the step size of FW iteration j for every instance by opts->ls_mode
  * (K-section, quasi-Newton of Alg. 8, or MSA), alpha_out double[n_instances]
  * (device).  Synchronises. */

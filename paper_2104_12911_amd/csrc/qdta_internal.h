@@ -13,6 +13,11 @@ constexpr int kMaxK = 64;                // step sizes per line-search pass
 // block-local shortest-path kernel: blocks per tree its LDS bitmap covers
 // (instances up to kBlkMaxBits * block-size nodes)
 constexpr int kBlkMaxBits = 8192;
+// allocation-free line search: 16 words of flags, then the exact accumulators
+// (three 64-bit chunks per sum, two sums per step size) of up to 64 instances
+// at K = 64
+constexpr int kNoAllocFlagWords = 16;
+constexpr int kNoAllocWords = kNoAllocFlagWords + 64 * kMaxK * 6;
 
 // One shortest-path label word: (not-queued flag << 31) | FP32 bits of the
 // distance.
@@ -132,6 +137,9 @@ hipError_t launch_ls_decide(hipStream_t s, int ninst, InstState* st, double* alp
 
 hipError_t launch_stall_check(hipStream_t s, int ninst, InstState* st, int fixed_iters);
 hipError_t launch_ls_export(hipStream_t s, int ninst, const long long* ls_acc, int K, int64_t* sums);
+// device address of the static scratch of the allocation-free line search on
+// `device` (which must be current); looked up once per device
+hipError_t noalloc_scratch(int device, long long** out);
 
 hipError_t launch_obj_pair(hipStream_t s, const NetDev& net, const int64_t* f, const int64_t* y,
                            double alpha_b, int beta, long long* acc /*[ninst][2][3]*/, const InstState* st,

@@ -23,6 +23,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "qdta_internal.h"
 
 namespace qdta {
@@ -474,6 +477,31 @@ hipError_t launch_ls_export(hipStream_t s, int ninst, const long long* ls_acc, i
     int n = ninst * K * 2;
     hipLaunchKernelGGL(k_ls_export, dim3((n + 63) / 64), dim3(64), 0, s, ninst, ls_acc, K, sums);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free line-search entry point: error flags and the
+// exact chunk accumulators, in a static array every device holds once for
+// the process (kNoAllocWords 64-bit words, 196,736 bytes).  Host code never
+// passes the array's name to a kernel: on the host it is not a device
+// address.  noalloc_scratch() looks the device address up once per device
+// (with that device current) and the kernels receive that pointer.
+static __device__ __align__(256) long long scratch[kNoAllocWords];
+
+hipError_t noalloc_scratch(int device, long long** out) {
+    static std::mutex mu;
+    static std::map<int, long long*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<long long*>(p);
+    *out = static_cast<long long*>(p);
+    return hipSuccess;
 }
 
 // Objective (Beckmann, or total travel time under the system optimum) of f

@@ -64,6 +64,7 @@ struct qdta_ctx {
     std::map<size_t, size_t> ws_free;   // offset -> length of each free run (coalesced)
     std::map<size_t, size_t> ws_used;   // offset -> length of each carved buffer
     int64_t ws_max_legs = 0, ws_max_dests = 0;  // maxima the workspace was sized for
+    long long* noalloc = nullptr; // device address of the allocation-free line search's static scratch
 
     // network layout
     int64_t N = 0, M = 0;
@@ -985,8 +986,15 @@ int qdta_create(qdta_ctx** out, int device, void* stream) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QDTA_EARG;
     if (hipSetDevice(device) != hipSuccess) return QDTA_EHIP;
+    // the allocation-free line search's static scratch on this device
+    long long* na = nullptr;
+    if (noalloc_scratch(device, &na) != hipSuccess || !na) {
+        (void)hipGetLastError();
+        return QDTA_EHIP;
+    }
     qdta_ctx* c = new qdta_ctx();
     c->device = device;
+    c->noalloc = na;
     c->stream = (hipStream_t)stream;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -1384,6 +1392,32 @@ int qdta_ls_eval(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_
     HIPCHECK(c, launch_ls_export(c->stream, ni, c->ls_acc.p, K, sums));
     int h[4];
     RC(read_flags(c, h));
+    return flag_code(c, h);
+}
+
+int qdta_ls_eval_noalloc(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_t* y, int32_t K,
+                         const double* alphas, int64_t* sums) {
+    if (!c) return QDTA_EARG;
+    c->err.clear();
+    if (!opts_ok(c, o)) return QDTA_EARG;
+    if (K < 1 || K > kMaxK || !f || !y || !alphas || !sums) return set_err(c, QDTA_EARG, "bad arguments");
+    if (c->net_dirty || c->dem_dirty)
+        return set_err(c, QDTA_ESTATE, "lay the context out first (e.g. qdta_layout): this call allocates nothing");
+    const int ni = (int)c->inst.size();
+    const int64_t words = (int64_t)ni * K * 6;
+    if (words > kNoAllocWords - kNoAllocFlagWords)
+        return set_err(c, QDTA_EARG, "n_instances x K = %d x %d exceeds the static scratch (at most %d sums)", ni, K,
+                       (kNoAllocWords - kNoAllocFlagWords) / 6);
+    int* flags = reinterpret_cast<int*>(c->noalloc);
+    long long* acc = c->noalloc + kNoAllocFlagWords;
+    // the scratch keeps the last call's contents: clear the flags and the
+    // accumulators this call uses (a fill kernel, safe under graph capture)
+    HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->noalloc), 0, kNoAllocFlagWords + words));
+    HIPCHECK(c, launch_ls_eval(c->stream, net_view(c, o), f, y, o->alpha, o->beta, K, alphas, acc, nullptr, 0, flags));
+    HIPCHECK(c, launch_ls_export(c->stream, ni, acc, K, sums));
+    int h[4];
+    HIPCHECK(c, hipMemcpyAsync(h, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
     return flag_code(c, h);
 }
 

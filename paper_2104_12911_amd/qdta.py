@@ -30,7 +30,7 @@ EXPORTS = [
     "qdta_get_costs", "qdta_advance_interval", "qdta_get_residual", "qdta_set_residual", "qdta_adjoint_record",
     "qdta_model_forward", "qdta_model_backward", "qdta_fw_begin", "qdta_fw_step",
     "qdta_profile_enable", "qdta_profile_read", "qdta_autotune", "qdta_workspace_query", "qdta_bind_workspace",
-    "qdta_alloc_count",
+    "qdta_alloc_count", "qdta_ls_eval_noalloc",
 ]
 PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
 
@@ -103,6 +103,7 @@ def lib():
         L.qdta_aon.argtypes = [vp, vp, vp, vp, vp, vp]
         L.qdta_get_legs.argtypes = [vp, vp, vp, vp, vp]
         L.qdta_ls_eval.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+        L.qdta_ls_eval_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.qdta_line_search.argtypes = [vp, vp, vp, vp, i32, vp]
         L.qdta_fw_update.argtypes = [vp, vp, vp, vp]
         L.qdta_solve.argtypes = [vp, vp, vp]
@@ -255,6 +256,12 @@ class Context:
     def ls_eval(self, opts, f_fx, y_fx, alphas, sums):
         K = alphas.shape[-1]
         self._rc(lib().qdta_ls_eval(self._h, C.byref(opts), _ptr(f_fx), _ptr(y_fx), int(K), _ptr(alphas), _ptr(sums)))
+
+    def ls_eval_noalloc(self, opts, f_fx, y_fx, alphas, sums):
+        """ls_eval with its scratch in the library's static device array (no allocation)."""
+        K = alphas.shape[-1]
+        self._rc(lib().qdta_ls_eval_noalloc(self._h, C.byref(opts), _ptr(f_fx), _ptr(y_fx), int(K), _ptr(alphas),
+                                            _ptr(sums)))
 
     def line_search(self, opts, f_fx, y_fx, j, alpha_out):
         self._rc(lib().qdta_line_search(self._h, C.byref(opts), _ptr(f_fx), _ptr(y_fx), int(j), _ptr(alpha_out)))
