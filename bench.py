@@ -73,13 +73,20 @@ DS_SHAPES = {1: (1, 4), 2: (2, 4), 3: (4, 4), 4: (4, 8), 5: (8, 8), 6: (1, 1)}
 BLK_SHAPES = {1: (128, 1), 2: (128, 2), 3: (64, 2), 4: (256, 1)}
 
 
+WN_SHAPES = {1: (1, 4), 2: (2, 4), 3: (2, 2), 4: (1, 2)}
+
+
 def sssp_kernel_name(shape, tree_waves, kernel=1):
     if kernel == 2:
         return "k_sssp_blk<%d, %d>" % BLK_SHAPES.get(shape, (128, 2))
+    if kernel == 3:
+        return "k_sssp_wn<%d, %d>" % WN_SHAPES.get(shape, (2, 4))
     shape = shape if shape in WG_SHAPES else 3
+    if kernel == 4:
+        return "k_sssp_wg<%d, %d, true>" % WG_SHAPES[shape]
     if (tree_waves or 4) == 1:
         return "k_sssp_ds<%d, %d>" % DS_SHAPES[shape]
-    return "k_sssp_wg<%d, %d>" % WG_SHAPES[shape]
+    return "k_sssp_wg<%d, %d, false>" % WG_SHAPES[shape]
 
 
 def traffic_entry(kernel_src_hash, kernel):
@@ -191,7 +198,18 @@ def mode_plain(args, torch, qdta):
     ctx = _ctx_for(qdta, stream, [(w.net, w.demand)])
     out = {"mode": "plain", "workload": "config2"}
     opts_b = qdta.default_opts(tol=args.tol, max_iter=args.steps)
-    t_solve, st = _solve_timed(torch, ctx, opts_b)
+    # the batched solve, step by step so that long runs report progress
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fw_begin(opts_b)
+    live, k = True, 0
+    while live:
+        st, live = ctx.fw_step(opts_b)
+        k += 1
+        if k % 1000 == 0:
+            log(f"batched solve: {k} steps, gap {st[0]['gap']:.3e}, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
     out.update(tol=args.tol, batched_solve_s=t_solve, iterations=st[0]["iters"], gap=st[0]["gap"],
                stopped_by=st[0]["stopped_by"])
     log(f"batched solve: {t_solve:.2f} s, {st[0]['iters']} iterations, gap {st[0]['gap']:.3e}, "
@@ -444,7 +462,8 @@ def main():
     ap.add_argument("--carry", type=int, default=4,
                     help="aon: earlier intervals solved first to carry their residual into the peak interval")
     ap.add_argument("--sssp-kernel", type=int, default=0, help="shortest-path kernel (0 library default, 1 node "
-                                                               "queue, 2 block-local)")
+                                                               "queue, 2 block-local, 3 node per thread, 4 node "
+                                                               "queue over the chain-contracted search)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (MiB) once, for counter calibration")
     ap.add_argument("--no-autotune", action="store_true", help="skip the kernel-shape / bucket-width autotuner")
@@ -572,7 +591,8 @@ def main():
     n_launch = max(args.steps, 1)
     touched = (8.0 * work_nodes + 8.0 * work_links) / n_launch + 8.0 * net.m + 4.0 * net.n
     src = open(os.path.join(ROOT, "paper_2104_12911_amd", "csrc", "qdta_kernels.hip"), "rb").read()
-    kname = sssp_kernel_name(opts.sssp_shape, opts.tree_waves, opts.sssp_kernel or 1)
+    kname = sssp_kernel_name(opts.sssp_shape, opts.tree_waves,
+                             opts.sssp_kernel or (1 if opts.tree_waves == 1 else 4))
     traffic = traffic_entry(hashlib.sha256(src).hexdigest(), kname)
     result = {
         "metric": METRIC,

@@ -136,13 +136,19 @@ typedef struct {
                               one: what the workspace has left), < 0 none (the residual step grows
                               every tree again); never changes results */
     int32_t objective;     /* QDTA_OBJ_UE (default) or QDTA_OBJ_SO */
-    int32_t sssp_kernel;   /* shortest-path kernel: 0 auto (the node queue), 1 node queue (tree_waves and
-                              sssp_shape as above), 2 block-local (a block of node ids is relaxed to
-                              closure in LDS per load; sssp_shape 1..4 = blocks of 128, 128 (two per
-                              wavefront per step), 64, 256 nodes; instances of at most 8,192 blocks, else
-                              the node queue), 3 node queue with each thread relaxing its own nodes'
-                              in-links (sssp_shape 1..4 = nodes x links per thread 1x4, 2x4, 2x2, 1x2);
-                              the trees are the same whichever runs */
+    int32_t sssp_kernel;   /* shortest-path kernel: 0 auto (4, or 1 when tree_waves = 1), 1 node queue
+                              (tree_waves and sssp_shape as above), 2 block-local (a block of node ids is
+                              relaxed to closure in LDS per load; sssp_shape 1..4 = blocks of 128, 128
+                              (two per wavefront per step), 64, 256 nodes; instances of at most 8,192
+                              blocks, else the node queue), 3 node queue with each thread relaxing its own
+                              nodes' in-links (sssp_shape 1..4 = nodes x links per thread 1x4, 2x4, 2x2,
+                              1x2), 4 node queue (one workgroup per tree, sssp_shape as above) over the
+                              chain-contracted network: nodes with exactly two neighbours that are no
+                              tree's destination are left out of the search, each run of at most 8 of them
+                              between two kept nodes is relaxed as one link applying its link costs one
+                              by one, and their labels are filled from the run's ends after the search
+                              (built on the host when first needed and again when a destination is a
+                              left-out node).  The trees are the same whichever runs */
     int32_t load_form;     /* loading of plain intervals (dt = +inf, every instance plain): 0 auto (walk),
                               1 walk every leg to its destination, 2 merge the legs' paths children before
                               parents (two passes over the legs, each link loaded once per tree with the sum

@@ -13,6 +13,9 @@ constexpr int kMaxK = 64;                // step sizes per line-search pass
 // block-local shortest-path kernel: blocks per tree its LDS bitmap covers
 // (instances up to kBlkMaxBits * block-size nodes)
 constexpr int kBlkMaxBits = 8192;
+// chain-contracted search: most nodes one chain holds (longer runs of
+// two-neighbour nodes are cut by keeping a node)
+constexpr int kChainMax = 8;
 // allocation-free line search: 16 words of flags, then the exact accumulators
 // (three 64-bit chunks per sum, two sums per step size) of up to 64 instances
 // at K = 64
@@ -68,6 +71,20 @@ struct NetDev {
     const int32_t* revpos;   // [M]   position of link a in the reverse arrays
     uint2* fadj;             // [M]   forward records (head, cost bits): the costs the trees are grown with
     const InstDev* inst;     // [ninst]
+    // chain contraction (NULL until built): the search's reverse CSR over the
+    // kept nodes, whose records are 2 words (source, cost bits) or, for a
+    // chain, (source | 1 << 31, word offset of its cost block: count, then
+    // the costs in the order they are added); cslot[a] is the word that
+    // holds link a's cost there (-1 none)
+    const int32_t* crptr;    // [N+1]
+    uint32_t* cbuf;
+    const int32_t* cslot;    // [M]
+    const uint2* anc;        // [N] nodes whose labels must be final before the node's own is (itself if kept)
+    const int32_t* inst_chain;// [ninst+1] chains of each instance
+    const int32_t* ch_ptr;   // [C+1] first node of each chain in ch_node
+    const int2* ch_end;      // [C] kept ends (u, v): u next to the chain's first node, v next to its last
+    const int32_t* ch_node;  // chain nodes, u to v
+    const int2* ch_link;     // per chain node: (link to the next node toward v, link to the previous toward u), -1 none
     const int32_t* blk_inst; // [nblk] instance of each link chunk
     const int32_t* blk_start;// [nblk] first global link of each chunk
     int32_t ninst, nblk;
@@ -154,6 +171,8 @@ hipError_t launch_fw_update(hipStream_t s, const NetDev& net, int64_t* f, const 
 hipError_t launch_copy_alpha(hipStream_t s, int ninst, const InstState* st, double* out);
 hipError_t launch_after_update(hipStream_t s, int ninst, InstState* st);
 hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, uint2* radj);
+// contracted records' costs from the forward link records (after a rebuild)
+hipError_t launch_cslot_init(hipStream_t s, const NetDev& net);
 
 hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, double delta_scale, float* delta_inst,
                         double* logsum);

@@ -195,6 +195,10 @@ __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restri
         if (radj) {
             radj[net.revpos[a]].y = __float_as_uint(c32);
             net.fadj[a].y = __float_as_uint(c32);
+            if (net.cbuf) {
+                const int w = net.cslot[a];
+                if (w >= 0) net.cbuf[w] = __float_as_uint(c32);
+            }
         }
     }
     if (bad) atomicOr(err, 1);
@@ -601,12 +605,29 @@ __global__ __launch_bounds__(kWG) void k_scatter_rcost(NetDev net, const float* 
     for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG) {
         radj[net.revpos[a]].y = __float_as_uint(cost[a]);
         net.fadj[a].y = __float_as_uint(cost[a]);
+        if (net.cbuf) {
+            const int w = net.cslot[a];
+            if (w >= 0) net.cbuf[w] = __float_as_uint(cost[a]);
+        }
     }
 }
 
 hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* cost, uint2* radj) {
     if (net.M == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_rcost, dim3(grid_for(net.M)), dim3(kWG), 0, s, net, cost, radj);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kWG) void k_cslot_init(NetDev net) {
+    for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG) {
+        const int w = net.cslot[a];
+        if (w >= 0) net.cbuf[w] = net.fadj[a].y;
+    }
+}
+
+hipError_t launch_cslot_init(hipStream_t s, const NetDev& net) {
+    if (net.M == 0 || !net.cbuf) return hipSuccess;
+    hipLaunchKernelGGL(k_cslot_init, dim3(grid_for(net.M)), dim3(kWG), 0, s, net);
     return hipGetLastError();
 }
 
@@ -970,6 +991,60 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
     }
 }
 
+// Candidate label of a shortcut's source: the target's label plus each cost
+// of the chain in turn (blk[0] = number of costs, then the costs), rounded to
+// FP32 after every addition as the link-by-link relaxations would be.
+__device__ __forceinline__ float chain_fold(const uint32_t* __restrict__ blk, float d) {
+    const uint4 h = *reinterpret_cast<const uint4*>(blk);
+    const int len = (int)h.x;
+    d = d + __uint_as_float(h.y);
+    if (len > 1) d = d + __uint_as_float(h.z);
+    if (len > 2) d = d + __uint_as_float(h.w);
+    for (int i = 3; i < len; i += 4) {
+        const uint4 g = *reinterpret_cast<const uint4*>(blk + 1 + i);
+        d = d + __uint_as_float(g.x);
+        if (i + 1 < len) d = d + __uint_as_float(g.y);
+        if (i + 2 < len) d = d + __uint_as_float(g.z);
+        if (i + 3 < len) d = d + __uint_as_float(g.w);
+    }
+    return d;
+}
+
+// Labels of the chain nodes of one tree from its chain ends' labels (after
+// the search): for chain node x_j, the fold from v through x_k..x_j and the
+// fold from u through x_1..x_j, each only over links that exist, and the
+// lesser of the two.  Bouncing inside a chain never beats this, since each
+// addition of a non-negative cost keeps or raises a value.
+__device__ __forceinline__ void chain_fill(const NetDev& net, label_t* D, int node0, int inst, int tid, int nt) {
+    const int c1 = net.inst_chain[inst + 1];
+    for (int ch = net.inst_chain[inst] + tid; ch < c1; ch += nt) {
+        const int2 uv = net.ch_end[ch];
+        const float du = __uint_as_float(ld_coherent(&D[uv.x - node0]) & kValueBits);
+        const float dv = __uint_as_float(ld_coherent(&D[uv.y - node0]) & kValueBits);
+        if (!(du < __uint_as_float(kInfBits)) && !(dv < __uint_as_float(kInfBits))) continue;
+        const int j0 = net.ch_ptr[ch], k = net.ch_ptr[ch + 1] - j0;
+        float lv[kChainMax];
+        float l = du;
+#pragma unroll
+        for (int j = 0; j < kChainMax; ++j) {
+            if (j < k) {
+                const int e = net.ch_link[j0 + j].y;
+                l = e >= 0 ? l + __uint_as_float(net.fadj[e].y) : __uint_as_float(kInfBits);
+                lv[j] = l;
+            }
+        }
+        float r = dv;
+#pragma unroll
+        for (int j = kChainMax - 1; j >= 0; --j) {
+            if (j < k) {
+                const int e = net.ch_link[j0 + j].x;
+                r = e >= 0 ? r + __uint_as_float(net.fadj[e].y) : __uint_as_float(kInfBits);
+                D[net.ch_node[j0 + j] - node0] = kNotQueued | __float_as_uint(fminf(lv[j], r));
+            }
+        }
+    }
+}
+
 // Workgroup-per-tree form of the same delta-stepping: the four wavefronts of
 // a workgroup grow one tree together, popping up to 256 U nodes per step
 // from the lowest node-id ranges, so a quarter as many trees are in flight
@@ -978,7 +1053,13 @@ __global__ __launch_bounds__(kWG) void k_sssp_ds(NetDev net, DemDev dem, const u
 // counts) is in LDS; a step is: wavefront 0 takes the pops from the lowest
 // ranges; every thread pops; a workgroup prefix sum of the in-degrees;
 // every thread relaxes V in-links per chunk; the counts are folded in.
-template <int U, int V>
+//
+// CT: the chain-contracted search.  Nodes left out by the contraction are
+// never queued; the kept nodes' in-links come from the contracted records
+// (a chain's record adds its link costs one at a time); a leg whose origin
+// is left out waits for the kept nodes its label depends on; after the
+// search the chain nodes' labels are filled from their chains' ends.
+template <int U, int V, bool CT>
 __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const uint2* __restrict__ radj,
                                                  label_t* labels, Scratch scr, const InstState* st,
                                                  const float* __restrict__ delta_inst, int early, int t_begin,
@@ -1007,7 +1088,8 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
         if (!inst_live(st, inst)) continue;
         const InstDev I = net.inst[inst];
         const int n = I.n, node0 = I.node0;
-        const int* __restrict__ rptr = net.rptr + node0;
+        const int* __restrict__ rptr = (CT ? net.crptr : net.rptr) + node0;
+        const uint2* __restrict__ recs = CT ? reinterpret_cast<const uint2*>(net.cbuf) : radj;
         label_t* D = labels + dem.dest_lab[t];
         const int root = dem.dest_node[t] - node0;
         const float delta = delta_inst[inst];
@@ -1173,9 +1255,14 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
                                 if (s_pre[mid] <= g) lo = mid; else hi = mid;
                             }
                             const int e = s_e0[lo] + (g - s_pre[lo]);
-                            const uint2 r = radj[e];
-                            vv[x] = (int)r.x - node0;
-                            cd[x] = s_dw[lo] + __uint_as_float(r.y);
+                            const uint2 r = recs[e];
+                            if (CT && (r.x & kNotQueued)) {
+                                vv[x] = (int)(r.x & kValueBits) - node0;
+                                cd[x] = chain_fold(net.cbuf + r.y, s_dw[lo]);
+                            } else {
+                                vv[x] = (int)r.x - node0;
+                                cd[x] = s_dw[lo] + __uint_as_float(r.y);
+                            }
                         }
                     }
                     uint32_t cur[V];
@@ -1202,8 +1289,14 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
                     const int l = lcur + tid;
                     bool p = false;
                     if (l < lend) {
-                        const int o = dem.leg_orig[l] - node0;
-                        p = !(__uint_as_float(ld_coherent(&D[o]) & kValueBits) < thr);
+                        if (CT) {
+                            const uint2 an = net.anc[dem.leg_orig[l]];
+                            p = !(__uint_as_float(ld_coherent(&D[(int)an.x - node0]) & kValueBits) < thr &&
+                                  __uint_as_float(ld_coherent(&D[(int)an.y - node0]) & kValueBits) < thr);
+                        } else {
+                            const int o = dem.leg_orig[l] - node0;
+                            p = !(__uint_as_float(ld_coherent(&D[o]) & kValueBits) < thr);
+                        }
                     }
                     if (__syncthreads_or(p)) { pend = true; break; }
                     lcur += NT;
@@ -1297,6 +1390,10 @@ __global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const u
             __syncthreads();
             fcnt = keep;
             fmin = km;
+        }
+        if (CT) {
+            __syncthreads();
+            chain_fill(net, D, node0, inst, tid, NT);
         }
         __syncthreads();
     }
@@ -2077,6 +2174,26 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
     int blocks = (slots + (kWG / 64) - 1) / (kWG / 64);
+    if (variant >= 32) {
+        // chain-contracted search, one workgroup per tree (scratch slot = workgroup)
+        if (!net.cbuf) return hipErrorInvalidValue;
+        blocks = min(blocks, scr.nslots);
+        if (blocks <= 0) return hipErrorInvalidValue;
+        dim3 g(blocks), b(kWG);
+#define QDTA_SSSP_CT(U, V) \
+    hipLaunchKernelGGL((k_sssp_wg<U, V, true>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, \
+                       t_begin, t_end)
+        switch (variant - 32) {
+            case 0: QDTA_SSSP_CT(1, 2); break;
+            case 1: QDTA_SSSP_CT(1, 4); break;
+            case 2: QDTA_SSSP_CT(2, 4); break;
+            case 3: QDTA_SSSP_CT(4, 4); break;
+            case 4: QDTA_SSSP_CT(2, 2); break;
+            default: QDTA_SSSP_CT(4, 2); break;
+        }
+#undef QDTA_SSSP_CT
+        return hipGetLastError();
+    }
     if (variant >= 24) {
         // one workgroup per tree, every thread relaxing its own nodes' in-links
         blocks = min(blocks, scr.nslots);
@@ -2117,8 +2234,8 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
         if (blocks <= 0) return hipErrorInvalidValue;
         dim3 g(blocks), b(kWG);
 #define QDTA_SSSP_WG(U, V) \
-    hipLaunchKernelGGL((k_sssp_wg<U, V>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, t_begin, \
-                       t_end)
+    hipLaunchKernelGGL((k_sssp_wg<U, V, false>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst, early, \
+                       t_begin, t_end)
         switch (variant - 8) {
             case 0: QDTA_SSSP_WG(1, 2); break;
             case 1: QDTA_SSSP_WG(1, 4); break;

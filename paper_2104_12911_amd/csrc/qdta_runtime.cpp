@@ -99,6 +99,16 @@ struct qdta_ctx {
     DBuf<float> delta_inst;
     DBuf<double> logsum;
 
+    // chain contraction of the search (opts.sssp_kernel = 4), built for the
+    // roots (destinations) seen so far
+    std::vector<uint8_t> croot, cleft;   // nodes kept as roots; nodes the search leaves out
+    bool c_built = false;
+    int64_t c_chains = 0, c_left = 0;
+    DBuf<int32_t> crptr, cslot, ch_ptr, ch_node, inst_chain;
+    DBuf<uint32_t> cbuf;
+    DBuf<uint2> anc;
+    DBuf<int2> ch_end, ch_link;
+
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
     DBuf<float> cost, cfin, tcost;    // routing costs, final times, travel times (system optimum)
@@ -190,6 +200,8 @@ int set_err(qdta_ctx* c, int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+void evict_label_history(qdta_ctx* c);
+
 // Device memory: from the bound workspace (first fit over its free runs),
 // else from hipMalloc.
 int dev_alloc(qdta_ctx* c, size_t bytes, void** out) {
@@ -212,6 +224,15 @@ int dev_alloc(qdta_ctx* c, size_t bytes, void** out) {
     }
     hipError_t e = hipMalloc(out, bytes);
     c->n_hip_malloc++;
+    if (e != hipSuccess && c->lab_hist.p) {
+        // the label history only saves the residual pass from growing the
+        // trees again, and it was sized from the free memory: give it back
+        // (the pass then grows them) and try once more
+        (void)hipGetLastError();
+        evict_label_history(c);
+        e = hipMalloc(out, bytes);
+        c->n_hip_malloc++;
+    }
     if (e != hipSuccess) {
         *out = nullptr;
         (void)hipGetLastError();
@@ -253,6 +274,13 @@ void dfree(qdta_ctx* c, DBuf<T>& b) {
     dev_free(c, (void*)b.p);
     b.p = nullptr;
     b.n = 0;
+}
+
+void evict_label_history(qdta_ctx* c) {
+    (void)hipStreamSynchronize(c->stream);   // work queued on it may still read the history
+    dfree(c, c->lab_hist);
+    c->lab_hist_ok.clear();
+    c->gen++;                        // a captured iteration may copy labels into it
 }
 
 template <class T>
@@ -304,7 +332,7 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     if (o->max_iter < 0 || o->fixed_iters < 0) { set_err(c, QDTA_EARG, "negative iteration count"); return false; }
     if (o->waves_per_cu < 0 || o->waves_per_cu > 32) { set_err(c, QDTA_EARG, "waves_per_cu must be in 0..32"); return false; }
     if (o->sssp_shape < 0 || o->sssp_shape > 6) { set_err(c, QDTA_EARG, "sssp_shape must be in 0..6"); return false; }
-    if (o->sssp_kernel < 0 || o->sssp_kernel > 3) { set_err(c, QDTA_EARG, "sssp_kernel must be 0..3"); return false; }
+    if (o->sssp_kernel < 0 || o->sssp_kernel > 4) { set_err(c, QDTA_EARG, "sssp_kernel must be 0..4"); return false; }
     if (o->load_form < 0 || o->load_form > 2) { set_err(c, QDTA_EARG, "load_form must be 0, 1 or 2"); return false; }
     if (o->launch_form < 0 || o->launch_form > 2) { set_err(c, QDTA_EARG, "launch_form must be 0, 1 or 2"); return false; }
     if (o->tree_waves != 0 && o->tree_waves != 1 && o->tree_waves != 4) {
@@ -334,9 +362,17 @@ int waves_per_cu(const qdta_opts* o) {
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Block size of each block-local shape (qdta_opts.sssp_shape 1..4)
 int blk_nodes(int shape) { return shape == 3 ? 64 : shape == 4 ? 256 : 128; }
+// the chain-contracted search runs for kernel 4, and by default (kernel 0)
+// unless one wavefront per tree was asked for
+bool uses_contraction(const qdta_opts* o) {
+    return o->sssp_kernel == 4 || (o->sssp_kernel == 0 && o->tree_waves != 1);
+}
+
 // Shortest-path kernel variant (see qdta_opts.sssp_kernel / sssp_shape).
 // Variants 0-5: node queue, one wavefront per tree; 8-13: node queue, one
-// workgroup per tree; 16-19: block-local, one workgroup per tree.  The
+// workgroup per tree; 16-19: block-local, one workgroup per tree; 24-27:
+// node-per-thread queue; 32-37: the node queue over the chain-contracted
+// search (shapes as 8-13).  The
 // block-local kernel needs every instance within its block bitmap.
 int sssp_variant(const qdta_ctx* c, const qdta_opts* o) {
     int64_t nmax = 0;
@@ -351,6 +387,7 @@ int sssp_variant(const qdta_ctx* c, const qdta_opts* o) {
         return 24 + v;
     }
     const int v = (o->sssp_shape >= 1 && o->sssp_shape <= 6) ? o->sssp_shape - 1 : 2;
+    if (uses_contraction(o)) return 32 + v;
     return tree_waves(o) == 1 ? v : v + 8;
 }
 
@@ -452,6 +489,8 @@ int ensure_network(qdta_ctx* c) {
     }
     c->net_dirty = false;
     c->dem_dirty = true;
+    c->c_built = false;                // the contraction is rebuilt for the new layout
+    c->croot.clear();
     c->gen++;                          // sizes baked into a captured iteration are stale
     return QDTA_OK;
 }
@@ -471,6 +510,16 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
     v.revpos = c->revpos.p;
     v.fadj = c->fadj.p;
     v.inst = c->d_inst.p;
+    const bool ct = c->c_built;
+    v.crptr = ct ? c->crptr.p : nullptr;
+    v.cbuf = ct ? c->cbuf.p : nullptr;
+    v.cslot = ct ? c->cslot.p : nullptr;
+    v.anc = ct ? c->anc.p : nullptr;
+    v.inst_chain = ct ? c->inst_chain.p : nullptr;
+    v.ch_ptr = ct ? c->ch_ptr.p : nullptr;
+    v.ch_end = ct ? c->ch_end.p : nullptr;
+    v.ch_node = ct ? c->ch_node.p : nullptr;
+    v.ch_link = ct ? c->ch_link.p : nullptr;
     v.blk_inst = c->blk_inst.p;
     v.blk_start = c->blk_start.p;
     v.ninst = (int32_t)c->inst.size();
@@ -478,6 +527,260 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
     v.N = c->N;
     v.M = c->M;
     return v;
+}
+
+// ---------------------------------------------------------------------------
+// chain contraction of the shortest-path search (opts.sssp_kernel = 4)
+// ---------------------------------------------------------------------------
+// A node is left out of the search when it is no root (destination) of any
+// tree, has exactly two distinct neighbours (links taken both ways), one or
+// two links in and out, no parallel links and no self-loop.  A run x1..xk of
+// such nodes (k <= kChainMax; longer runs keep every (kChainMax+1)-th node)
+// between kept nodes u (next to x1) and v (next to xk) is a chain.  When every
+// link u->x1->...->xk->v exists, the search holds one record at v with source
+// u whose cost list is c(xk->v), ..., c(x1->x2), c(u->x1): the candidate label
+// of u is v's label plus each cost in turn, rounded to FP32 after each
+// addition, which is what the same relaxations link by link would give; the
+// same for v->xk->...->x1->u at u.  After a tree's search, each chain node's
+// label is the lesser of the two folds from the ends' labels (see the kernel).
+// Words of the contracted records at most: one record (2 words) per link at
+// most, and per chain of k nodes two cost blocks of ceil((k + 2) / 4) * 4
+// words at most, i.e. at most 8 words per left-out node.
+size_t contraction_words(int64_t N, int64_t M) { return 2 * (size_t)M + 4 + 8 * (size_t)N; }
+
+int build_contraction(qdta_ctx* c) {
+    const int64_t N = c->N;
+    const int ni = (int)c->inst.size();
+    std::vector<int32_t> crp(N + 1, 0), cslot(c->M, -1), ch_ptr{0}, ch_node, inst_chain(ni + 1, 0);
+    std::vector<int2> ch_end, ch_link;
+    std::vector<uint2> anc(N);
+    for (int64_t v = 0; v < N; ++v) anc[v] = make_uint2((uint32_t)v, (uint32_t)v);
+    // records per head node: plain (source, link) and shortcuts (source, chain, direction)
+    struct Rec {
+        int32_t head, src, link, chain, dir;   // link >= 0: plain; else shortcut of chain in direction dir
+    };
+    std::vector<Rec> recs;
+    std::vector<std::vector<int32_t>> sc_links;   // cost links of each shortcut, in fold order
+    for (int i = 0; i < ni; ++i) {
+        const Instance& I = c->inst[i];
+        const int n = I.n;
+        const int32_t n0 = (int32_t)c->node_off[i], l0 = (int32_t)c->link_off[i];
+        const std::vector<int32_t>& rp = I.row_ptr;
+        const std::vector<int32_t>& col = I.col;
+        inst_chain[i] = (int32_t)ch_end.size();
+        // in-links (local)
+        std::vector<int32_t> rrp(n + 1, 0), rin(I.m);
+        for (int a = 0; a < I.m; ++a) rrp[col[a] + 1]++;
+        for (int v = 0; v < n; ++v) rrp[v + 1] += rrp[v];
+        {
+            std::vector<int32_t> fill(rrp.begin(), rrp.end() - 1);
+            for (int v = 0; v < n; ++v)
+                for (int a = rp[v]; a < rp[v + 1]; ++a) rin[fill[col[a]]++] = v;
+        }
+        auto link_to = [&](int x, int y) -> int32_t {
+            for (int a = rp[x]; a < rp[x + 1]; ++a)
+                if (col[a] == y) return a;
+            return -1;
+        };
+        // candidates and their two neighbours
+        std::vector<int32_t> nb0(n, -1), nb1(n, -1);
+        std::vector<char> cand(n, 0);
+        for (int v = 0; v < n; ++v) {
+            if (c->croot[n0 + v]) continue;
+            const int od = rp[v + 1] - rp[v], id = rrp[v + 1] - rrp[v];
+            if (od < 1 || od > 2 || id < 1 || id > 2) continue;
+            int nb[4], k = 0;
+            bool ok = true;
+            for (int a = rp[v]; a < rp[v + 1]; ++a) nb[k++] = col[a];
+            if (od == 2 && nb[0] == nb[1]) ok = false;
+            for (int e = rrp[v]; e < rrp[v + 1]; ++e) nb[k++] = rin[e];
+            if (id == 2 && rin[rrp[v]] == rin[rrp[v] + 1]) ok = false;
+            int a0 = -1, a1 = -1;
+            for (int j = 0; j < k && ok; ++j) {
+                if (nb[j] == v) ok = false;
+                else if (a0 < 0 || nb[j] == a0) a0 = nb[j];
+                else if (a1 < 0 || nb[j] == a1) a1 = nb[j];
+                else ok = false;
+            }
+            if (!ok || a1 < 0) continue;
+            cand[v] = 1;
+            nb0[v] = a0;
+            nb1[v] = a1;
+        }
+        auto other = [&](int x, int from) { return nb0[x] == from ? nb1[x] : nb0[x]; };
+        std::vector<char> seen(n, 0);
+        std::vector<int32_t> run;
+        for (int s = 0; s < n; ++s) {
+            if (!cand[s] || seen[s]) continue;
+            // extend from s both ways through candidates to the kept ends
+            std::vector<int32_t> left;
+            int prev = s, cur = nb0[s];
+            bool ring = false;
+            while (cand[cur]) {
+                if (cur == s) { ring = true; break; }
+                left.push_back(cur);
+                const int nx = other(cur, prev);
+                prev = cur;
+                cur = nx;
+            }
+            if (ring) {                  // a ring of candidates with no kept node: keep them all
+                seen[s] = 1;
+                for (int x : left) seen[x] = 1;
+                cand[s] = 0;
+                for (int x : left) cand[x] = 0;
+                continue;
+            }
+            const int u = cur;
+            std::vector<int32_t> right;
+            prev = s;
+            cur = nb1[s];
+            while (cand[cur]) {
+                right.push_back(cur);
+                const int nx = other(cur, prev);
+                prev = cur;
+                cur = nx;
+            }
+            const int v = cur;
+            run.assign(left.rbegin(), left.rend());
+            run.push_back(s);
+            run.insert(run.end(), right.begin(), right.end());
+            for (int x : run) seen[x] = 1;
+            // cut into pieces of at most kChainMax nodes; the cut nodes are kept
+            int a_end = u;
+            size_t p = 0;
+            while (p < run.size()) {
+                const size_t q = std::min(run.size(), p + kChainMax);
+                const int b_end = q < run.size() ? run[q] : v;
+                if (q < run.size()) cand[run[q]] = 0;
+                // chain run[p..q) between a_end and b_end
+                const int k = (int)(q - p);
+                const int cid = (int32_t)ch_end.size();
+                std::vector<int32_t> rl(k), ll(k);
+                for (int j = 0; j < k; ++j) {
+                    const int x = run[p + j];
+                    const int nxt = j + 1 < k ? run[p + j + 1] : b_end;
+                    const int prv = j > 0 ? run[p + j - 1] : a_end;
+                    rl[j] = link_to(x, nxt);
+                    ll[j] = link_to(x, prv);
+                }
+                std::vector<char> ok_r(k), ok_l(k);
+                for (int j = k - 1; j >= 0; --j) ok_r[j] = rl[j] >= 0 && (j == k - 1 || ok_r[j + 1]);
+                for (int j = 0; j < k; ++j) ok_l[j] = ll[j] >= 0 && (j == 0 || ok_l[j - 1]);
+                ch_end.push_back(make_int2(n0 + a_end, n0 + b_end));
+                for (int j = 0; j < k; ++j) {
+                    const int x = run[p + j];
+                    ch_node.push_back(n0 + x);
+                    ch_link.push_back(make_int2(rl[j] >= 0 ? l0 + rl[j] : -1, ll[j] >= 0 ? l0 + ll[j] : -1));
+                    const int ar = ok_r[j] ? b_end : (ok_l[j] ? a_end : x);
+                    const int al = ok_l[j] ? a_end : (ok_r[j] ? b_end : x);
+                    anc[n0 + x] = make_uint2((uint32_t)(n0 + ar), (uint32_t)(n0 + al));
+                }
+                ch_ptr.push_back((int32_t)ch_node.size());
+                if (a_end != b_end) {
+                    const int32_t in_a = link_to(a_end, run[p]), in_b = link_to(b_end, run[q - 1]);
+                    if (in_a >= 0 && ok_r[0]) {              // a_end -> x1 -> ... -> b_end, held at b_end
+                        std::vector<int32_t> ls;
+                        for (int j = k - 1; j >= 0; --j) ls.push_back(l0 + rl[j]);
+                        ls.push_back(l0 + in_a);
+                        recs.push_back({n0 + b_end, n0 + a_end, -1, (int32_t)sc_links.size(), 0});
+                        sc_links.push_back(std::move(ls));
+                    }
+                    if (in_b >= 0 && ok_l[k - 1]) {          // b_end -> xk -> ... -> a_end, held at a_end
+                        std::vector<int32_t> ls;
+                        for (int j = 0; j < k; ++j) ls.push_back(l0 + ll[j]);
+                        ls.push_back(l0 + in_b);
+                        recs.push_back({n0 + a_end, n0 + b_end, -1, (int32_t)sc_links.size(), 1});
+                        sc_links.push_back(std::move(ls));
+                    }
+                }
+                (void)cid;
+                a_end = b_end;
+                p = q + (q < run.size() ? 1 : 0);
+            }
+        }
+        // plain records: links between kept nodes
+        for (int x = 0; x < n; ++x) {
+            if (cand[x]) continue;
+            for (int a = rp[x]; a < rp[x + 1]; ++a)
+                if (!cand[col[a]]) recs.push_back({n0 + col[a], n0 + x, l0 + a, -1, 0});
+        }
+    }
+    inst_chain[ni] = (int32_t)ch_end.size();
+    // contracted reverse CSR: records grouped by head, plain ones in link order first
+    std::stable_sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+        if (a.head != b.head) return a.head < b.head;
+        if ((a.link >= 0) != (b.link >= 0)) return a.link >= 0;
+        return a.link >= 0 ? a.link < b.link : a.chain < b.chain;
+    });
+    for (const Rec& r : recs) crp[r.head + 1]++;
+    for (int64_t v = 0; v < N; ++v) crp[v + 1] += crp[v];
+    const size_t rec_words = 2 * recs.size();
+    size_t words = (rec_words + 3) / 4 * 4;
+    std::vector<size_t> blk(sc_links.size());
+    for (size_t s = 0; s < sc_links.size(); ++s) {
+        blk[s] = words;
+        words += (1 + sc_links[s].size() + 3) / 4 * 4;
+    }
+    std::vector<uint32_t> cbuf(words, 0u);
+    for (size_t k = 0; k < recs.size(); ++k) {
+        const Rec& r = recs[k];
+        if (r.link >= 0) {
+            cbuf[2 * k] = (uint32_t)r.src;
+            cslot[r.link] = (int32_t)(2 * k + 1);
+        } else {
+            const size_t b = blk[r.chain];
+            cbuf[2 * k] = (uint32_t)r.src | 0x80000000u;
+            cbuf[2 * k + 1] = (uint32_t)b;
+            const std::vector<int32_t>& ls = sc_links[r.chain];
+            cbuf[b] = (uint32_t)ls.size();
+            for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]] = (int32_t)(b + 1 + j);
+        }
+    }
+    if (words >= (size_t)INT32_MAX) return set_err(c, QDTA_EARG, "contracted records beyond int32 offsets");
+    c->c_chains = (int64_t)ch_end.size();
+    c->c_left = (int64_t)ch_node.size();
+    c->cleft.assign(N, 0);
+    for (int32_t x : ch_node) c->cleft[x] = 1;
+    // inside a workspace every buffer is carved at its bound once (see
+    // contraction_words), so later rebuilds fit in place
+    const bool ws = c->ws_base != nullptr;
+    RC(upload(c, c->crptr, crp));
+    RC(upload(c, c->cbuf, cbuf, ws ? contraction_words(N, c->M) : 0));
+    RC(upload(c, c->cslot, cslot));
+    RC(upload(c, c->anc, anc));
+    RC(upload(c, c->ch_ptr, ch_ptr, ws ? (size_t)N + 1 : 0));
+    RC(upload(c, c->ch_end, ch_end, ws ? (size_t)N : 0));
+    RC(upload(c, c->ch_node, ch_node, ws ? (size_t)N : 0));
+    RC(upload(c, c->ch_link, ch_link, ws ? (size_t)N : 0));
+    RC(upload(c, c->inst_chain, inst_chain));
+    c->c_built = true;
+    c->gen++;
+    // the records' costs from the forward records, which hold the current routing costs
+    NetDev net = net_view(c);
+    HIPCHECK(c, launch_cslot_init(c->stream, net));
+    return QDTA_OK;
+}
+
+// Roots (global node ids) must stay in the search: the contraction is built
+// on first use and again when a root is a node it leaves out.
+int ensure_contraction(qdta_ctx* c, const int32_t* roots, size_t nroots) {
+    if ((int64_t)c->croot.size() != c->N) {
+        c->croot.assign(c->N, 0);
+        c->c_built = false;
+    }
+    bool again = !c->c_built;
+    for (size_t k = 0; k < nroots; ++k) {
+        c->croot[roots[k]] = 1;
+        if (c->c_built && c->cleft[roots[k]]) again = true;
+    }
+    return again ? build_contraction(c) : QDTA_OK;
+}
+
+
+// before a search of the current demand's trees
+int ensure_contract(qdta_ctx* c, const qdta_opts* o) {
+    if (!uses_contraction(o)) return QDTA_OK;
+    return ensure_contraction(c, c->h_dest_node.data(), c->h_dest_node.size());
 }
 
 // Destinations of an instance are in ascending node order; tree t's labels
@@ -1062,6 +1365,10 @@ int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int6
     add(pq, 4); add(pq, 4); add(pq, 8); add(pq + 1, 4); add(pp, 4); add(pp, 8); add(pp, 4); add(pp, 4);
     add(labels, 4); add(pq, 4); add(pp, 4); add(pp, 4);
     if (o->load_form == 2) { add(labels, 4); add(labels, 8); }   // plain-interval loading by merged paths
+    if (uses_contraction(o)) {                                    // chain contraction (at its bounds)
+        add(N + 1, 4); add(contraction_words(N, M), 4); add(M, 4); add(N, 8);
+        add(N + 1, 4); add(N, 8); add(N, 4); add(N, 8); add(ni + 1, 4);
+    }
     // shortest-path scratch (as ensure_scratch sizes it)
     {
         const int tw = tree_waves(o), wpc = waves_per_cu(o);
@@ -1321,6 +1628,7 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         dem.dest_inst = ddi.p;
         dem.dest_lab = ddl.p;
         dem.Q = nq;
+        if (uses_contraction(o) && (rc = ensure_contraction(c, dn.data(), dn.size()))) break;
         NetDev net = net_view(c);
         hipError_t e;
         // place the instance's costs in the global link order
@@ -1361,6 +1669,7 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
     RC(ensure_sweep(c, o));
+    RC(ensure_contract(c, o));
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
     NetDev net = net_view(c);
@@ -1459,6 +1768,7 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
     RC(ensure_sweep(c, o));
+    RC(ensure_contract(c, o));
     NetDev net = net_view(c, o);
     RC(init_state(c, false, 0));
     RC(clear_flags(c));
@@ -1651,6 +1961,7 @@ int qdta_fw_step(qdta_ctx* c, const qdta_opts* o, qdta_stats* hs, int32_t* live_
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (c->fw_j < 0 || c->dem_dirty) return set_err(c, QDTA_ESTATE, "qdta_fw_step needs qdta_fw_begin");
     RC(ensure_sweep(c, o));
+    RC(ensure_contract(c, o));
     int h[4] = {0, 0, 0, 0};
     if (c->fw_live) RC(fw_iteration(c, o, h));
     else {
@@ -1680,6 +1991,8 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "autotune needs the demand of every instance");
     RC(ensure_demand(c, waves_per_cu(o), 1));            // slots for either kernel form
     RC(apply_rule(c, o));
+    if (o->sssp_kernel == 0 || o->sssp_kernel == 4)       // trials of either tree form
+        RC(ensure_contraction(c, c->h_dest_node.data(), c->h_dest_node.size()));
     NetDev net = net_view(c, o);
     DemDev dem = dem_view(c);
     // trial costs: BPR of the current flows when an interval was solved, else free flow
@@ -1799,6 +2112,7 @@ int qdta_advance_interval(qdta_ctx* c, const qdta_opts* o) {
     if (!c->solved) return set_err(c, QDTA_ESTATE, "advance needs a solved interval");
     if (!o->keep_history) return set_err(c, QDTA_ESTATE, "advance needs keep_history during solve");
     RC(apply_rule(c, o));
+    RC(ensure_contract(c, o));
     int ni = (int)c->inst.size();
     NetDev net = net_view(c);
     DemDev dem = dem_view(c);
@@ -2007,6 +2321,7 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
         return set_err(c, QDTA_ESTATE, "no iteration history");
     RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
     RC(apply_rule(c, o));
+    RC(ensure_contract(c, o));
     const int64_t P = c->P, M = c->M;
     c->adj_J = -1;
     c->adj_fwd = false;

@@ -23,21 +23,24 @@ def bench():
 
 
 def test_kernel_names(bench):
-    assert bench.sssp_kernel_name(3, 4) == "k_sssp_wg<2, 4>"
-    assert bench.sssp_kernel_name(0, 0) == "k_sssp_wg<2, 4>"      # library defaults
-    assert bench.sssp_kernel_name(5, 4) == "k_sssp_wg<2, 2>"
+    assert bench.sssp_kernel_name(3, 4) == "k_sssp_wg<2, 4, false>"
+    assert bench.sssp_kernel_name(0, 0) == "k_sssp_wg<2, 4, false>"      # default shape of the node queue
+    assert bench.sssp_kernel_name(5, 4) == "k_sssp_wg<2, 2, false>"
     assert bench.sssp_kernel_name(3, 1) == "k_sssp_ds<4, 4>"
     assert bench.sssp_kernel_name(6, 1) == "k_sssp_ds<1, 1>"
+    assert bench.sssp_kernel_name(3, 4, 4) == "k_sssp_wg<2, 4, true>"   # chain-contracted search
+    assert bench.sssp_kernel_name(0, 1, 4) == "k_sssp_wg<2, 4, true>"   # one workgroup per tree whatever asked
+    assert bench.sssp_kernel_name(2, 4, 3) == "k_sssp_wn<2, 4>"
 
 
 def test_traffic_entry_matches_source_and_kernel(bench, tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
-    entry = {"kernel": "k_sssp_wg<2, 4>", "kernel_sha256": "abc", "bytes_per_launch": 123.0}
+    entry = {"kernel": "k_sssp_wg<2, 4, false>", "kernel_sha256": "abc", "bytes_per_launch": 123.0}
     (tmp_path / "profiles" / "sssp_traffic.json").write_text(json.dumps(entry))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.traffic_entry("abc", "k_sssp_wg<2, 4>") == 123.0
-    assert bench.traffic_entry("abd", "k_sssp_wg<2, 4>") is None       # kernel source changed
-    assert bench.traffic_entry("abc", "k_sssp_wg<4, 4>") is None       # another instantiation
+    assert bench.traffic_entry("abc", "k_sssp_wg<2, 4, false>") == 123.0
+    assert bench.traffic_entry("abd", "k_sssp_wg<2, 4, false>") is None       # kernel source changed
+    assert bench.traffic_entry("abc", "k_sssp_wg<4, 4, false>") is None       # another instantiation
 
 
 def test_committed_traffic_entry_is_used_only_for_its_kernel(bench):
