@@ -89,6 +89,48 @@ def sssp_kernel_name(shape, tree_waves, kernel=1):
     return "k_sssp_wg<%d, %d, false>" % WG_SHAPES[shape]
 
 
+def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands):
+    """HBM bytes per launch of `kernel` from two rocprofv3 PMC databases (one
+    pass with FETCH_SIZE, one with WRITE_SIZE, both in KiB per dispatch),
+    each scaled by what the counter reads for the calibration add kernel
+    (reads and writes calib_mib MiB once, run by --copy-calib-mib)."""
+    import sqlite3
+
+    def per_dispatch(db, counter):
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, name, counter_name, counter_value from pmc_events").fetchall()
+        con.close()
+        acc, names = {}, {}
+        for did, name, cn, cv in rows:
+            if cn == counter:
+                acc[did] = acc.get(did, 0.0) + float(cv)
+                names[did] = name
+        return acc, names
+
+    out = {"kernel": kernel, "calibration": {"kernel": f"torch.add of a {calib_mib} MiB float32 tensor (reads and "
+                                                        f"writes {calib_mib} MiB once)"}}
+    for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        acc, names = per_dispatch(db, counter)
+        ks = [acc[d] for d in acc if kernel in names[d]]
+        adds = [acc[d] for d in acc if "add" in names[d].lower() and "elementwise" in names[d].lower()]
+        if not ks or not adds:
+            raise SystemExit(f"{db}: no dispatch of {kernel} or of the calibration kernel")
+        cal = max(adds)
+        scale = (calib_mib * 1024.0) / cal
+        out[f"{key}_kib_per_launch"] = sum(ks) / len(ks)
+        out[f"{key}_launches"] = len(ks)
+        out["calibration"][f"{key}_kib"] = cal
+        out["calibration"][f"{key}_scale"] = scale
+    out["bytes_per_launch"] = 1024.0 * (out["fetch_kib_per_launch"] * out["calibration"]["fetch_scale"] +
+                                        out["write_kib_per_launch"] * out["calibration"]["write_scale"])
+    src = open(os.path.join(ROOT, "paper_2104_12911_amd", "csrc", "qdta_kernels.hip"), "rb").read()
+    out["kernel_sha256"] = hashlib.sha256(src).hexdigest()
+    out["commands"] = commands
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def traffic_entry(kernel_src_hash, kernel):
     """HBM bytes per SSSP launch from the rocprofv3 PMC runs, if they were
     taken on the current kernel source and the same instantiation."""
@@ -467,6 +509,13 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (MiB) once, for counter calibration")
     ap.add_argument("--no-autotune", action="store_true", help="skip the kernel-shape / bucket-width autotuner")
+    ap.add_argument("--reduce-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/sssp_traffic.json from two rocprofv3 --pmc databases (FETCH_SIZE, "
+                         "WRITE_SIZE) of runs made with --copy-calib-mib, and exit")
+    ap.add_argument("--traffic-kernel", default="k_sssp_wg<2, 4, true>",
+                    help="kernel instantiation the traffic reduction averages")
+    ap.add_argument("--traffic-commands", default="", help="the rocprofv3 commands, ' ;; '-separated, recorded")
+    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "sssp_traffic.json"))
     ap.add_argument("--mode", default="aon", choices=["aon", "plain", "batch", "day", "calib"],
                     help="aon: the headline AON/s line; plain: batched vs per-destination launches (config 2); "
                          "batch: 64 uneven instances together vs one after another (config 4); day: full-day QDTA; "
@@ -489,6 +538,12 @@ def main():
     ap.add_argument("--trunc", default="ceil", choices=["ceil", "floor", "progress"],
                     help="day mode: truncation rule (Eq. 2 read as CEIL or FLOOR, or link progress)")
     args = ap.parse_args()
+    if args.reduce_traffic:
+        out = reduce_traffic(args.reduce_traffic[0], args.reduce_traffic[1], args.traffic_kernel,
+                             args.copy_calib_mib or 1024, args.traffic_out,
+                             [c.strip() for c in args.traffic_commands.split(";;") if c.strip()])
+        print(json.dumps(out))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)

@@ -65,3 +65,30 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_reduce_traffic_scales_by_the_calibration_kernel(tmp_path):
+    """Per-launch HBM bytes: the kernel's mean FETCH_SIZE / WRITE_SIZE (KiB
+    per dispatch) times the factor that makes the calibration add kernel read
+    and write its known size."""
+    import sqlite3
+    import bench
+
+    def db(path, counter, rows):
+        con = sqlite3.connect(path)
+        con.execute("create table pmc_events (dispatch_id int, name text, counter_name text, counter_value real)")
+        con.executemany("insert into pmc_events values (?, ?, ?, ?)", [(d, n, counter, v) for d, n, v in rows])
+        con.commit()
+        con.close()
+
+    k = "void qdta::k_sssp_wg<2, 4, true>(qdta::NetDev)"
+    add = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctor_add<float>>()"
+    fdb, wdb = str(tmp_path / "f.db"), str(tmp_path / "w.db")
+    # FETCH_SIZE of the 1 MiB calibration reads half the true size; two launches of the kernel
+    db(fdb, "FETCH_SIZE", [(1, add, 512.0), (2, k, 1000.0), (3, k, 3000.0), (4, "other", 9.0)])
+    db(wdb, "WRITE_SIZE", [(1, add, 1024.0), (2, k, 10.0), (3, k, 30.0)])
+    out = bench.reduce_traffic(fdb, wdb, "k_sssp_wg<2, 4, true>", 1, str(tmp_path / "t.json"), ["a", "b"])
+    assert out["fetch_kib_per_launch"] == 2000.0 and out["write_kib_per_launch"] == 20.0
+    assert out["calibration"]["fetch_scale"] == 2.0 and out["calibration"]["write_scale"] == 1.0
+    assert out["bytes_per_launch"] == 1024.0 * (2000.0 * 2.0 + 20.0)
+    assert out["fetch_launches"] == 2
