@@ -89,11 +89,13 @@ def sssp_kernel_name(shape, tree_waves, kernel=1):
     return "k_sssp_wg<%d, %d, false>" % WG_SHAPES[shape]
 
 
-def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands):
+def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands, last=0):
     """HBM bytes per launch of `kernel` from two rocprofv3 PMC databases (one
     pass with FETCH_SIZE, one with WRITE_SIZE, both in KiB per dispatch),
     each scaled by what the counter reads for the calibration add kernel
-    (reads and writes calib_mib MiB once, run by --copy-calib-mib)."""
+    (reads and writes calib_mib MiB once, run by --copy-calib-mib).  last > 0:
+    only the kernel's last `last` dispatches (the timed steps of the peak
+    interval; earlier ones belong to the carried-in intervals)."""
     import sqlite3
 
     def per_dispatch(db, counter):
@@ -111,7 +113,9 @@ def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands):
                                                         f"writes {calib_mib} MiB once)"}}
     for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         acc, names = per_dispatch(db, counter)
-        ks = [acc[d] for d in acc if kernel in names[d]]
+        ks = [acc[d] for d in sorted(acc) if kernel in names[d]]
+        if last > 0:
+            ks = ks[-last:]
         adds = [acc[d] for d in acc if "add" in names[d].lower() and "elementwise" in names[d].lower()]
         if not ks or not adds:
             raise SystemExit(f"{db}: no dispatch of {kernel} or of the calibration kernel")
@@ -129,6 +133,31 @@ def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands):
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     return out
+
+
+def trace_summary(db, kernel, last):
+    """Markdown summary of a rocprofv3 --kernel-trace database: every kernel's
+    calls, total and mean duration and share of GPU time, then the mean
+    duration of `kernel`'s last `last` dispatches (the timed steps)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, dispatch_id, duration from kernels").fetchall()
+    con.close()
+    per = {}
+    for name, did, dur in rows:
+        short = name.split("(")[0].replace("void ", "")
+        per.setdefault(short, []).append((did, dur))
+    total = sum(d for _, _, d in rows)
+    lines = ["| kernel | calls | total ms | mean ms | share of GPU time |", "|---|---|---|---|---|"]
+    for short, v in sorted(per.items(), key=lambda kv: -sum(d for _, d in kv[1]))[:12]:
+        t = sum(d for _, d in v)
+        lines.append(f"| `{short}` | {len(v)} | {t / 1e6:.1f} | {t / len(v) / 1e6:.3f} | {100.0 * t / total:.1f}% |")
+    ks = sorted(v for short, vv in per.items() if kernel in short for v in vv)
+    tail = [d for _, d in ks[-last:]] if last > 0 else [d for _, d in ks]
+    lines.append("")
+    lines.append(f"`{kernel}`, last {len(tail)} dispatches (the timed steps): mean "
+                 f"{sum(tail) / max(len(tail), 1) / 1e6:.2f} ms, min {min(tail) / 1e6:.2f}, max {max(tail) / 1e6:.2f}")
+    return "\n".join(lines)
 
 
 def traffic_entry(kernel_src_hash, kernel):
@@ -516,6 +545,10 @@ def main():
                     help="kernel instantiation the traffic reduction averages")
     ap.add_argument("--traffic-commands", default="", help="the rocprofv3 commands, ' ;; '-separated, recorded")
     ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "sssp_traffic.json"))
+    ap.add_argument("--traffic-last", type=int, default=0,
+                    help="only the kernel's last N dispatches (the timed steps: 2 x --steps of the profiled run)")
+    ap.add_argument("--summarize-trace", metavar="DB",
+                    help="print a markdown summary of a rocprofv3 --kernel-trace database and exit")
     ap.add_argument("--mode", default="aon", choices=["aon", "plain", "batch", "day", "calib"],
                     help="aon: the headline AON/s line; plain: batched vs per-destination launches (config 2); "
                          "batch: 64 uneven instances together vs one after another (config 4); day: full-day QDTA; "
@@ -541,8 +574,11 @@ def main():
     if args.reduce_traffic:
         out = reduce_traffic(args.reduce_traffic[0], args.reduce_traffic[1], args.traffic_kernel,
                              args.copy_calib_mib or 1024, args.traffic_out,
-                             [c.strip() for c in args.traffic_commands.split(";;") if c.strip()])
+                             [c.strip() for c in args.traffic_commands.split(";;") if c.strip()], args.traffic_last)
         print(json.dumps(out))
+        return
+    if args.summarize_trace:
+        print(trace_summary(args.summarize_trace, args.traffic_kernel, args.traffic_last))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
