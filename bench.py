@@ -244,7 +244,7 @@ def batched_vs_plain(torch, qdta, warm_iters=3):
         ctx.fw_begin(o)
         for _ in range(warm_iters):
             ctx.fw_step(qdta.default_opts(fixed_iters=1 << 30))
-        n = 3 if form == 0 else 1
+        n = 3
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(n):
@@ -291,7 +291,7 @@ def mode_plain(args, torch, qdta):
         ctx.fw_begin(o)
         ctx.fw_step(o)
         torch.cuda.synchronize()
-        n = 3 if form == 0 else 1
+        n = 3
         t0 = time.perf_counter()
         for _ in range(n):
             ctx.fw_step(o)
@@ -317,6 +317,12 @@ def mode_batch(args, torch, qdta):
     ctx = _ctx_for(qdta, stream, [(x.net, x.demand) for x in insts])
     li = ctx.layout()
     log(f"config4: {len(insts)} instances, {li.total_links} links, {li.total_dests} destinations, {li.total_legs} legs")
+    if not args.no_autotune:
+        # kernel shape, bucket width, and walks or merged paths for the loading
+        # (every grid is a plain static assignment); both forms use the result
+        opts, best = ctx.autotune(opts, 2000.0)
+        log(f"autotune: sssp_shape={opts.sssp_shape} delta_scale={opts.delta_scale} tree_waves={opts.tree_waves} "
+            f"load_form={opts.load_form} ({best:.1f} ms)")
     _solve_timed(torch, ctx, qdta.default_opts(fixed_iters=1))
     ctx.profile(True)
     t_b, st_b = _solve_timed(torch, ctx, opts)
@@ -332,9 +338,12 @@ def mode_batch(args, torch, qdta):
         c1.close()
         log(f"sequential instance {i}: {t:.3f} s (total {t_s:.2f} s)")
     print(json.dumps({"mode": "batch", "workload": "config4", "instances": len(insts),
+                      "load_form": {0: "walk", 1: "walk", 2: "merged paths"}[opts.load_form],
                       "links": int(li.total_links), "destinations": int(li.total_dests), "legs": int(li.total_legs),
                       "iterations": iters, "batched_s": t_b, "sequential_s": t_s, "speedup": t_s / t_b,
-                      "gap_max_batched": max(s["gap"] for s in st_b)}), flush=True)
+                      "gap_max_batched": max(s["gap"] for s in st_b),
+                      "gap_median_batched": float(np.median([s["gap"] for s in st_b])),
+                      "phases_ms_batched": {k: round(v[0], 1) for k, v in prof.items()}}), flush=True)
 
 
 def mode_day(args, torch, qdta):

@@ -430,11 +430,15 @@ int qdta_model_backward(qdta_ctx *ctx, uint64_t fwd_id, const double *fbar, doub
  * costs otherwise) for a grid of kernel shapes, bucket widths and
  * wavefronts per tree, stopping once about budget_ms of GPU time is spent,
  * and writes the fastest into opts->sssp_shape, opts->delta_scale and
- * opts->tree_waves (other fields unchanged).  The configuration passed in
- * (zero fields read as the defaults) is timed first, after one untimed
- * launch, and is kept unless another is at least 5% faster.  Results never
- * depend on these fields, only the speed does.  *best_ms_out (host, may be
- * NULL) receives the time of the configuration chosen.  Synchronises. */
+ * opts->tree_waves.  The configuration passed in (zero fields read as the
+ * defaults) is timed first, after one untimed launch, and is kept unless
+ * another is at least 5% faster.  When opts->load_form is 0 and every
+ * instance is plain (no truncation), the loading by per-leg walks and by
+ * merged paths are timed on the same trees and opts->load_form becomes 2
+ * if the merged paths are at least 5% faster, else 1.  Other fields are
+ * unchanged.  Results never depend on these fields, only the speed does.
+ * *best_ms_out (host, may be NULL) receives the shortest-path time of the
+ * configuration chosen.  Synchronises. */
 int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best_ms_out);
 
 /* Per-phase timers: HIP events recorded on the context's stream around each

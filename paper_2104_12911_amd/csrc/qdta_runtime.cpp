@@ -2046,12 +2046,42 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
         best_scale = start_scale;
         best_tw = start_tw;
     }
+    // plain intervals: loading by per-leg walks or by merged paths, on the
+    // labels of the last trial (the trees do not depend on the trial)
+    int best_load = o->load_form;
+    if (rc == QDTA_OK && o->load_form == 0) {
+        qdta_opts ts = *o;
+        ts.load_form = 2;
+        if (use_sweep(c, &ts)) {
+            rc = ensure_sweep(c, &ts);
+            float ms_w = 0.0f, ms_s = 0.0f;
+            FlagsDev fl = flags_view(c);
+            for (int k = 0; k < 4 && rc == QDTA_OK; ++k) {
+                const bool sweep = k & 1;                   // walk, sweep, walk, sweep (first pair untimed)
+                hipError_t e = launch_fill_i64(c->stream, c->y.p, 0, c->M);
+                if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess)
+                    e = sweep ? launch_sweep(c->stream, net, dem, c->labels.p, c->y.p, nullptr, nullptr, nullptr, fl,
+                                             c->sw_cnt.p, c->sw_acc.p)
+                              : launch_walk(c->stream, net, dem, c->labels.p, nullptr, c->y.p, nullptr, nullptr, fl, 0,
+                                            nullptr, nullptr, nullptr, 0, -1);
+                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { rc = set_err(c, QDTA_EHIP, "autotune loading: %s", hipGetErrorString(e)); break; }
+                if (k >= 2) (sweep ? ms_s : ms_w) = ms;
+            }
+            if (rc == QDTA_OK) best_load = ms_s < 0.95f * ms_w ? 2 : 1;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc < 0) return rc;
     o->sssp_shape = best_shape;
     o->delta_scale = best_scale;
     o->tree_waves = best_tw;
+    o->load_form = best_load;
     if (best_ms_out) *best_ms_out = best;
     return QDTA_OK;
 }
