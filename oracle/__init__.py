@@ -182,10 +182,11 @@ def tree(net, cost, q):
     return D, succ, rc
 
 
-def aon(net, cost, orig, dest, d_fx, dt_s, rule=RULE_CEIL, nthreads=0, delay=None, want_delay=False):
+def aon(net, cost, orig, dest, d_fx, dt_s, rule=RULE_CEIL, nthreads=0, delay=None, want_delay=False, pq=0.0):
     """All-or-nothing loading; delay (float32[P] or None): each leg's carried
-    time to its origin (PROGRESS rule).  Returns (y, stop, rc), plus the stop
-    delays when want_delay."""
+    time to its origin (PROGRESS rule); pq > 0: stop delays rounded up to
+    multiples of pq seconds.  Returns (y, stop, rc), plus the stop delays
+    when want_delay."""
     rp, col, cost = _i32(net.row_ptr), _i32(net.col), _f32(cost)
     orig, dest, d_fx = _i32(orig), _i32(dest), _i64(d_fx)
     tau0 = None if delay is None else _f32(delay)
@@ -195,10 +196,10 @@ def aon(net, cost, orig, dest, d_fx, dt_s, rule=RULE_CEIL, nthreads=0, delay=Non
     L = lib()
     L.orc_aon_d.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
-                            C.c_void_p, C.c_void_p, C.c_int32]
+                            C.c_void_p, C.c_void_p, C.c_double, C.c_int32]
     rc = L.orc_aon_d(net.n, col.shape[0], _p(rp), _p(col), _p(cost), None, orig.shape[0], _p(orig), _p(dest),
                      _p(d_fx), _p(tau0) if tau0 is not None else None, float(dt_s), rule, _p(y), _p(stop), _p(sdl),
-                     nthreads)
+                     float(pq), nthreads)
     if rc < 0:
         raise RuntimeError(f"orc_aon failed {rc}")
     if want_delay:
@@ -302,7 +303,7 @@ def fw_solve(net, orig, dest, d_fx, *, alpha_b=0.15, beta=4, dt_s=float("inf"), 
 
 
 def residual(net, f, hist_alpha, hist_cost, orig, dest, d_fx, *, alpha_b=0.15, beta=4, dt_s=900.0,
-             rule=RULE_CEIL, delay=None, want_delay=False):
+             rule=RULE_CEIL, delay=None, want_delay=False, pq=0.0):
     rp, col = _i32(net.row_ptr), _i32(net.col)
     c0, cap = _f32(net.fftt), _f32(net.cap)
     orig, dest, d_fx = _i32(orig), _i32(dest), _i64(d_fx)
@@ -323,12 +324,12 @@ def residual(net, f, hist_alpha, hist_cost, orig, dest, d_fx, *, alpha_b=0.15, b
     L.orc_residual.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.c_int32,
                                C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p]
     rc = L.orc_residual(net.n, col.shape[0], _p(rp), _p(col), _p(c0), _p(cap), alpha_b, beta, float(dt_s),
                         rule, _p(_i64(f)), J, _p(ha), _p(hc), P, _p(orig), _p(dest), _p(d_fx),
-                        _p(tau0) if tau0 is not None else None, _p(ro), _p(rd), _p(rw), _p(rdl), C.byref(cnt),
-                        C.byref(done), _p(lam))
+                        _p(tau0) if tau0 is not None else None, float(pq), _p(ro), _p(rd), _p(rw), _p(rdl),
+                        C.byref(cnt), C.byref(done), _p(lam))
     if rc < 0:
         raise RuntimeError(f"orc_residual failed {rc}")
     k = cnt.value
@@ -367,13 +368,14 @@ def merge_legs(orig, dest, w_fx, delay=None):
 
 
 def qdta_day(net, days, *, alpha_b=0.15, beta=4, rule=RULE_CEIL, tol=1e-4, max_iter=1000,
-             stop_rule=STOP_GAP, nthreads=0, **ls_kw):
+             stop_rule=STOP_GAP, nthreads=0, pq=0.0, **ls_kw):
     """Alg. 1: for each interval, d(i) = d^o(i) + d^r(i), Frank-Wolfe, then
     Alg. 4 for d^r(i+1).  d^r(0) is empty.  Returns per-interval records and
     the residual left after the last interval (reported, not assigned).
     Under RULE_PROGRESS the residual legs carry their delays (time still
-    needed to reach their origin node), legs are merged by (destination,
-    origin, delay), and the records' "res" hold four arrays."""
+    needed to reach their origin node; rounded up to multiples of pq seconds
+    when pq > 0), legs are merged by (destination, origin, delay), and the
+    records' "res" hold four arrays."""
     prog = rule == RULE_PROGRESS
     res_o = np.zeros(0, np.int32)
     res_d = np.zeros(0, np.int32)
@@ -405,7 +407,7 @@ def qdta_day(net, days, *, alpha_b=0.15, beta=4, rule=RULE_CEIL, tol=1e-4, max_i
                       **ls_kw)
         ro, rd, rw, done, lam, rt = residual(net, fw.f, fw.hist_alpha, fw.hist_cost, o, d, w, alpha_b=alpha_b,
                                              beta=beta, dt_s=dem.dt_s, rule=rule, delay=t if prog else None,
-                                             want_delay=True)
+                                             want_delay=True, pq=pq)
         if prog:
             res_o, res_d, res_w, res_t = merge_legs(ro, rd, rw, rt)
             res = (res_o, res_d, res_w, res_t)

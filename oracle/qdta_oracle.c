@@ -336,16 +336,27 @@ int orc_tree(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, c
  *          with delay fl32(tau0 - dt).  A trip on the last link of its path
  *          has loaded every link and completes (stop node q).
  * Returns the stop node (q when the leg completes); *delay_out (may be NULL)
- * receives the remaining delay, 0 unless PROGRESS stops a trip on a link. */
+ * receives the remaining delay, 0 unless PROGRESS stops a trip on a link.
+ * pq > 0 (PROGRESS only): every delay a leg leaves with is rounded up to a
+ * whole multiple of pq seconds, fl32(pq * ceil(x / pq)) in FP64, so that
+ * legs stopped on the same link for the same destination merge into one
+ * (reading R24: with exact delays every (iterate, leg) leaves a leg of its
+ * own and the pending legs multiply from interval to interval). */
 typedef void (*load_fn)(void *ctx, int32_t link);
 
+static float progress_delay(float x, double pq) {
+    if (!(pq > 0.0)) return x;
+    return (float)(pq * ceil((double)x / pq));
+}
+
 static int32_t walk_leg(const int32_t *col, const int32_t *succ, const float *tcost, int32_t s0,
-                        int32_t q, float dt32, int rule, float tau0, load_fn fn, void *ctx, float *delay_out) {
+                        int32_t q, float dt32, int rule, float tau0, load_fn fn, void *ctx, float *delay_out,
+                        double pq) {
     int32_t u = s0;
     float tau = tau0;
     if (delay_out) *delay_out = 0.0f;
     if (rule == RULE_PROGRESS && tau >= dt32) {
-        if (delay_out) *delay_out = tau - dt32;
+        if (delay_out) *delay_out = progress_delay(tau - dt32, pq);
         return s0;
     }
     while (u != q) {
@@ -359,7 +370,7 @@ static int32_t walk_leg(const int32_t *col, const int32_t *succ, const float *tc
         u = col[e];
         if (rule == RULE_PROGRESS && tau > dt32) {
             if (u == q) return q;
-            if (delay_out) *delay_out = tau - dt32;
+            if (delay_out) *delay_out = progress_delay(tau - dt32, pq);
             return u;
         }
     }
@@ -398,7 +409,7 @@ static int effective_rule(double dt_s, int rule) { return isfinite(dt_s) ? rule 
 int orc_aon_d(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
               const float *tcost, int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
               const float *tau0, double dt_s, int32_t rule, int64_t *y, int32_t *stop, float *stop_delay,
-              int32_t nthreads) {
+              double pq, int32_t nthreads) {
     if (!tcost) tcost = cost;
     if (orc_check_csr(n, m, row_ptr, col)) return ORC_ECSR;
     for (int32_t p = 0; p < P; ++p)
@@ -443,7 +454,7 @@ int orc_aon_d(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
                 addctx ac = {y, d_fx[p]};
                 float dl = 0.0f;
                 int32_t s = walk_leg(col, succ, tcost, orig[p], q, dt32, eff, tau0 ? tau0[p] : 0.0f, add_link, &ac,
-                                     &dl);
+                                     &dl, pq);
                 if (stop) stop[p] = s;
                 if (stop_delay) stop_delay[p] = dl;
             }
@@ -460,7 +471,7 @@ int orc_aon_d(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
 int orc_aon_t(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, const float *cost,
               const float *tcost, int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx,
               double dt_s, int32_t rule, int64_t *y, int32_t *stop, int32_t nthreads) {
-    return orc_aon_d(n, m, row_ptr, col, cost, tcost, P, orig, dest, d_fx, NULL, dt_s, rule, y, stop, NULL,
+    return orc_aon_d(n, m, row_ptr, col, cost, tcost, P, orig, dest, d_fx, NULL, dt_s, rule, y, stop, NULL, 0.0,
                      nthreads);
 }
 
@@ -513,7 +524,7 @@ int orc_paths(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
             if (d_fx[p] <= 0 || orig[p] == q) continue;
             if (!isfinite(D[orig[p]])) { rc = ORC_EUNREACH; break; }
             pathctx pc = {NULL, 0};
-            walk_leg(col, succ, cost, orig[p], q, dt32, eff, 0.0f, put_link, &pc, NULL);
+            walk_leg(col, succ, cost, orig[p], q, dt32, eff, 0.0f, put_link, &pc, NULL, 0.0);
             len[p] = pc.at;
         }
     }
@@ -529,7 +540,7 @@ int orc_paths(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col, 
                 int32_t p = idx[i];
                 if (d_fx[p] <= 0 || orig[p] == q) continue;
                 pathctx pc = {links + ptr[p], 0};
-                walk_leg(col, succ, cost, orig[p], q, dt32, eff, 0.0f, put_link, &pc, NULL);
+                walk_leg(col, succ, cost, orig[p], q, dt32, eff, 0.0f, put_link, &pc, NULL, 0.0);
             }
         }
     }
@@ -788,7 +799,7 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
     rc = orc_bpr_obj(m, zero, c0, cap, o->alpha_b, o->beta, kappa, so, c);
     if (rc < 0) goto done;
     if (so) orc_bpr(m, zero, c0, cap, o->alpha_b, o->beta, kappa, tc);
-    rc = orc_aon_d(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, tau0, o->dt_s, o->rule, f, NULL, NULL,
+    rc = orc_aon_d(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, tau0, o->dt_s, o->rule, f, NULL, NULL, 0.0,
                    o->nthreads);
     if (rc < 0) goto done;
     st->absorb |= (rc == ORC_WARN_ABSORB);
@@ -798,7 +809,7 @@ int orc_fw_solve(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
         rc = orc_bpr_obj(m, f, c0, cap, o->alpha_b, o->beta, kappa, so, c);
         if (rc < 0) goto done;
         if (so) orc_bpr(m, f, c0, cap, o->alpha_b, o->beta, kappa, tc);
-        rc = orc_aon_d(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, tau0, o->dt_s, o->rule, y, NULL, NULL,
+        rc = orc_aon_d(n, m, row_ptr, col, c, tc, P, orig, dest, d_fx, tau0, o->dt_s, o->rule, y, NULL, NULL, 0.0,
                        o->nthreads);
         if (rc < 0) goto done;
         st->absorb |= (rc == ORC_WARN_ABSORB);
@@ -873,7 +884,7 @@ int orc_residual(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
                  const float *cap, double alpha_b, int32_t beta, double dt_s, int32_t rule,
                  const int64_t *f, int32_t J, const double *hist_alpha, const float *hist_cost,
                  int32_t P, const int32_t *orig, const int32_t *dest, const int64_t *d_fx, const float *tau0,
-                 int32_t *r_orig, int32_t *r_dest, int64_t *r_fx, float *r_delay, int64_t *n_out,
+                 double pq, int32_t *r_orig, int32_t *r_dest, int64_t *r_fx, float *r_delay, int64_t *n_out,
                  int64_t *done_fx, double *lambda_out) {
     double kappa = orc_kappa(dt_s);
     int eff = effective_rule(dt_s, rule);
@@ -927,7 +938,7 @@ int orc_residual(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *co
                     int64_t w = (int64_t)rint(lam[j] * (double)d_fx[p]);
                     float dl = 0.0f;
                     int32_t s = walk_leg(col, succ, cfin, orig[p], q, dt32, eff, tau0 ? tau0[p] : 0.0f, NULL, NULL,
-                                         &dl);
+                                         &dl, pq);
                     if (s == q) { done += w; continue; }
                     size_t k = (size_t)j * (size_t)P + (size_t)i;
                     t_orig[k] = s;

@@ -135,3 +135,62 @@ def test_progress_day_trip_conservation(orc):
         assert abs(r["in_fx"] - (r["done_fx"] + res)) <= slack
         in_transit += int((r["res"][3] > 0).sum())
     assert in_transit > 0
+
+
+def _quantum(x, pq):
+    """pq * ceil(x / pq) in FP64, rounded to FP32 (the delay rounding)."""
+    return np.float32(pq * np.ceil(np.float64(x) / pq))
+
+
+def test_progress_quantum_long_link_by_hand(orc):
+    """A 700 s link then a 60 s link, 300 s intervals.  Exact delays: 400 s,
+    then 100 s, completion in interval 2.  With delays rounded up to 250 s:
+    400 -> 500; interval 1 keeps the trip (500 >= 300) with 200 -> 250;
+    interval 2 reaches node 1 at 250 s and completes on the last link.  The
+    loads are the same; only the carried delays differ."""
+    net = Network(3, np.array([0, 1, 2, 2], np.int32), np.array([1, 2], np.int32),
+                  np.array([700.0, 60.0], np.float32), np.array([1e6, 1e6], np.float32))
+    for pq, delays in ((0.0, [400.0, 100.0]), (250.0, [500.0, 250.0]), (60.0, [420.0, 120.0])):
+        out, _ = orc.qdta_day(net, _days(3), alpha_b=0.0, rule=orc.RULE_PROGRESS, pq=pq)
+        assert [r["f"].tolist() for r in out] == [[FX, 0], [0, 0], [0, FX], [0, 0]], pq
+        assert [r["res"][3].tolist() for r in out[:2]] == [[delays[0]], [delays[1]]], pq
+        assert out[2]["res"][0].size == 0 and out[2]["done_fx"] == FX
+
+
+def test_progress_quantum_rounds_stop_delays_up(orc):
+    """Same trees, same walks: loads and stop nodes do not depend on the
+    rounding, and every delay equals the exact one rounded up to a multiple
+    of the quantum (at most one quantum above it)."""
+    w = synth.config1()
+    o, d, wfx = orc.demand_legs(w.demand.orig, w.demand.dest, w.demand.trips)
+    rng = np.random.default_rng(5)
+    cost = (w.net.fftt * rng.uniform(1, 3, w.net.m)).astype(np.float32)
+    tau0 = rng.uniform(0, 500, o.size).astype(np.float32)
+    for dt, pq in ((120.0, 30.0), (300.0, 60.0), (777.0, 7.5)):
+        y0, s0, d0, _ = orc.aon(w.net, cost, o, d, wfx, dt, orc.RULE_PROGRESS, delay=tau0, want_delay=True)
+        y1, s1, d1, _ = orc.aon(w.net, cost, o, d, wfx, dt, orc.RULE_PROGRESS, delay=tau0, want_delay=True, pq=pq)
+        assert np.array_equal(y0, y1) and np.array_equal(s0, s1)
+        exp = np.array([_quantum(x, pq) if x > 0 else np.float32(0) for x in d0], np.float32)
+        assert np.array_equal(d1, exp), (dt, pq)
+        assert (d1 >= d0).all() and (d1 - d0 < pq).all() and (d1 % np.float32(pq) == 0).all()
+
+
+def test_progress_quantum_day_merges_pending_legs(orc):
+    """Over a chain of short intervals, rounding the delays lets legs that
+    stopped on the same link for the same destination merge: no more pending
+    legs than with exact delays, every delay a multiple of the quantum, and
+    trips conserved as with exact delays."""
+    w = synth.config1()
+    rng = np.random.default_rng(9)
+    days = []
+    for i in range(4):
+        sel = rng.random(w.demand.P) < 0.3
+        days.append(Demand(w.demand.orig[sel], w.demand.dest[sel], w.demand.trips[sel] / 4, 90.0))
+    ex, _ = orc.qdta_day(w.net, days, tol=1e-3, max_iter=30, rule=orc.RULE_PROGRESS)
+    qu, _ = orc.qdta_day(w.net, days, tol=1e-3, max_iter=30, rule=orc.RULE_PROGRESS, pq=30.0)
+    for a, b in zip(ex, qu):
+        assert b["res"][0].size <= a["res"][0].size
+        assert (b["res"][3] % np.float32(30.0) == 0).all()
+        slack = (b["iters"] + 1) * b["legs"]
+        assert abs(b["in_fx"] - (b["done_fx"] + int(b["res"][2].sum()))) <= slack
+    assert sum(r["res"][0].size for r in qu) < sum(r["res"][0].size for r in ex)
