@@ -327,6 +327,15 @@ def mode_batch(args, torch, qdta):
     ctx.profile(True)
     t_b, st_b = _solve_timed(torch, ctx, opts)
     prof = ctx.profile_read()
+    # per-phase times of an iteration: three more with direct launches, timed per phase
+    od = qdta.default_opts(fixed_iters=3, launch_form=1, sssp_shape=opts.sssp_shape, delta_scale=opts.delta_scale,
+                           tree_waves=opts.tree_waves, load_form=opts.load_form)
+    ctx.profile(True)
+    _solve_timed(torch, ctx, od)
+    pd = ctx.profile_read()
+    ctx.profile(False)
+    phase_iter = {k: round(v[0] / v[1], 2) for k, v in pd.items() if k != "sssp_work" and v[1]}
+    log(f"phases per launch (ms), direct launches: {json.dumps(phase_iter)}")
     ctx.close()
     log(f"batched: {t_b:.2f} s for {iters} iterations; phases {json.dumps({k: round(v[0], 1) for k, v in prof.items()})}")
     t_s = 0.0
@@ -343,7 +352,7 @@ def mode_batch(args, torch, qdta):
                       "iterations": iters, "batched_s": t_b, "sequential_s": t_s, "speedup": t_s / t_b,
                       "gap_max_batched": max(s["gap"] for s in st_b),
                       "gap_median_batched": float(np.median([s["gap"] for s in st_b])),
-                      "phases_ms_batched": {k: round(v[0], 1) for k, v in prof.items()}}), flush=True)
+                      "phase_ms_per_launch": phase_iter}), flush=True)
 
 
 def mode_day(args, torch, qdta):
@@ -361,6 +370,7 @@ def mode_day(args, torch, qdta):
     ls_mode = {"ksection": qdta.LS_KSECTION, "qn": qdta.LS_QN, "msa": qdta.LS_MSA}[args.ls]
     trunc = {"ceil": qdta.RULE_CEIL, "floor": qdta.RULE_FLOOR, "progress": qdta.RULE_PROGRESS}[args.trunc]
     opts = qdta.default_opts(stop_rule=stop, tol=args.tol, max_iter=args.steps, keep_history=1, trunc_rule=trunc,
+                             progress_quantum_s=args.progress_quantum,
                              launch_form=1 if args.profile_day else 0, tree_waves=args.tree_waves,
                              waves_per_cu=args.waves_per_cu, delta_scale=args.delta_scale, ls_mode=ls_mode,
                              objective=qdta.OBJ_SO if args.objective == "so" else qdta.OBJ_UE)
@@ -408,6 +418,7 @@ def mode_day(args, torch, qdta):
                       "intervals": len(days), "trips": tot_trips, "wall_s": wall, "fw_iterations": sum(iters),
                       "stop_rule": args.stop, "tol": args.tol, "line_search": args.ls, "objective": args.objective,
                       "truncation": args.trunc,
+                      "progress_quantum_s": args.progress_quantum if args.trunc == "progress" else None,
                       "intervals_stopped_by": {k: stops.count(v) for k, v in
                                                (("gap", 1), ("objective_change", 2), ("stall", 3), ("cap", 0))},
                       "max_abs_gap": max((abs(g) for g in gaps), default=0.0),
@@ -579,6 +590,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4, help="day and plain modes: stop tolerance")
     ap.add_argument("--trunc", default="ceil", choices=["ceil", "floor", "progress"],
                     help="day mode: truncation rule (Eq. 2 read as CEIL or FLOOR, or link progress)")
+    ap.add_argument("--progress-quantum", type=float, default=60.0,
+                    help="day mode, link progress: delays rounded up to multiples of this many seconds (0 exact)")
     args = ap.parse_args()
     if args.reduce_traffic:
         out = reduce_traffic(args.reduce_traffic[0], args.reduce_traffic[1], args.traffic_kernel,

@@ -153,6 +153,12 @@ typedef struct {
                               1 walk every leg to its destination, 2 merge the legs' paths children before
                               parents (two passes over the legs, each link loaded once per tree with the sum
                               of the demand through it; same int64 flows); truncated intervals always walk */
+    int32_t pad1;
+    double progress_quantum_s; /* link-progress rule only: every delay a leg leaves an interval with is rounded
+                              up to a whole multiple of this many seconds, fl32(q * ceil(x / q)) in FP64, so
+                              that legs stopped on the same link for the same destination merge (default
+                              60; 0 keeps exact delays, with which every (iterate, leg) leaves a pending leg
+                              of its own and a long day's pending legs multiply) */
 } qdta_opts;
 
 /* Per-instance results of qdta_solve. */

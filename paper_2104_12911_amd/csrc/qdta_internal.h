@@ -35,6 +35,7 @@ struct InstDev {
     int32_t rule;            // effective truncation rule (NONE when dt = inf)
     float dt32;              // interval length rounded to FP32
     double kappa;            // 3600/dt, or 1 for dt = inf
+    double pq;               // link-progress rule: delays rounded up to multiples of this (0: exact)
 };
 
 // Per-instance Frank-Wolfe / line-search state, resident on the device.

@@ -2360,63 +2360,78 @@ __device__ __forceinline__ void finish_leg(const WalkOut& o, int l, int s, int q
 // as CEIL; a trip still on a link at dt stops at its head with delay
 // nt - dt (a trip on its last link completes), and a leg that starts with
 // its delay at or above dt is still on its way to its origin.
+// A delay a leg leaves the interval with, rounded up to a whole multiple of
+// pq seconds in FP64 when pq > 0 (legs stopped on the same link for the
+// same destination then merge).
+__device__ __forceinline__ float progress_delay(float x, double pq) {
+    return pq > 0.0 ? (float)(pq * ceil((double)x / pq)) : x;
+}
+
 __device__ __forceinline__ bool stop_at_node(int rule, float tau, float dt) {
     return (rule == RULE_CEIL || rule == RULE_PROGRESS) && tau >= dt;
 }
 
 // time_cost: the costs that clock the truncation (Eq. 2); NULL = the trees'
 // own costs (the forward records), as in the AON of an iteration.
+// Legs per thread of the walk: the threads of a wavefront walk legs of
+// different lengths, so each takes several (strided, so that a wavefront
+// still walks 64 consecutive legs of one tree at a time) and the sums of
+// their lengths vary less than single lengths do.
+constexpr int kWalkLegsPerThread = 4;
+
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                               const float* __restrict__ time_cost, const InstState* st,
                                               FlagsDev fl, WalkOut o, int l_begin, int l_end) {
-    const int l = l_begin + blockIdx.x * kWG + threadIdx.x;
-    if (l >= l_end) return;
-    const int qi = dem.leg_q[l];
-    const int inst = dem.dest_inst[qi];
-    if (!inst_live(st, inst)) return;
-    const InstDev I = net.inst[inst];
-    const int node0 = I.node0;
-    const int q = dem.dest_node[qi];
-    const label_t* lab = tree_labels(labels, dem, qi);
-    const int64_t d = dem.leg_dfx[l];
-    int u = dem.leg_orig[l];
-    float du = lab_val(lab, u - node0);
-    fl.int_node[l] = -1;
-    if (!(du <= 3.4028234663852886e38f)) {       // origin cannot reach q
-        atomicOr(fl.err_unreach, 1);
-        if (o.stop) o.stop[l] = -1;
-        return;
-    }
-    float tau = dem.leg_delay ? dem.leg_delay[l] : 0.0f;
-    float delay = 0.0f;
-    if (I.rule == RULE_PROGRESS && tau >= I.dt32) {
-        delay = tau - I.dt32;                     // still on its way to its origin
-    } else {
-        for (int hops = 0; u != q; ++hops) {
-            if (stop_at_node(I.rule, tau, I.dt32)) break;
-            int head = 0;
-            float ce = 0.0f;
-            const int e = succ_rec(net, lab, node0, u, du, head, ce);
-            if (e < 0 || hops > I.n) {            // absorption: finish in the fallback
-                fl.int_node[l] = u;
-                fl.int_tau[l] = tau;
-                fl.absorb_q[qi] = 1;
-                atomicAdd(fl.absorb_count, 1);
-                return;
-            }
-            const float nt = tau + (time_cost ? time_cost[e] : ce);
-            if (I.rule == RULE_FLOOR && nt > I.dt32) break;
-            if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
-            tau = nt;
-            u = head;
-            du = lab_val(lab, u - node0);
-            if (I.rule == RULE_PROGRESS && tau > I.dt32) {
-                if (u != q) delay = tau - I.dt32;
-                break;
+    for (int l = l_begin + blockIdx.x * kWG + threadIdx.x; l < l_end; l += gridDim.x * kWG) {
+        const int qi = dem.leg_q[l];
+        const int inst = dem.dest_inst[qi];
+        if (!inst_live(st, inst)) continue;
+        const InstDev I = net.inst[inst];
+        const int node0 = I.node0;
+        const int q = dem.dest_node[qi];
+        const label_t* lab = tree_labels(labels, dem, qi);
+        const int64_t d = dem.leg_dfx[l];
+        int u = dem.leg_orig[l];
+        float du = lab_val(lab, u - node0);
+        fl.int_node[l] = -1;
+        if (!(du <= 3.4028234663852886e38f)) {       // origin cannot reach q
+            atomicOr(fl.err_unreach, 1);
+            if (o.stop) o.stop[l] = -1;
+            continue;
+        }
+        float tau = dem.leg_delay ? dem.leg_delay[l] : 0.0f;
+        float delay = 0.0f;
+        bool absorbed = false;
+        if (I.rule == RULE_PROGRESS && tau >= I.dt32) {
+            delay = progress_delay(tau - I.dt32, I.pq);   // still on its way to its origin
+        } else {
+            for (int hops = 0; u != q; ++hops) {
+                if (stop_at_node(I.rule, tau, I.dt32)) break;
+                int head = 0;
+                float ce = 0.0f;
+                const int e = succ_rec(net, lab, node0, u, du, head, ce);
+                if (e < 0 || hops > I.n) {            // absorption: finish in the fallback
+                    fl.int_node[l] = u;
+                    fl.int_tau[l] = tau;
+                    fl.absorb_q[qi] = 1;
+                    atomicAdd(fl.absorb_count, 1);
+                    absorbed = true;
+                    break;
+                }
+                const float nt = tau + (time_cost ? time_cost[e] : ce);
+                if (I.rule == RULE_FLOOR && nt > I.dt32) break;
+                if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
+                tau = nt;
+                u = head;
+                du = lab_val(lab, u - node0);
+                if (I.rule == RULE_PROGRESS && tau > I.dt32) {
+                    if (u != q) delay = progress_delay(tau - I.dt32, I.pq);
+                    break;
+                }
             }
         }
+        if (!absorbed) finish_leg(o, l, u, q, qi, dem.dest_lab[qi], inst, node0, d, delay);
     }
-    finish_leg(o, l, u, q, qi, dem.dest_lab[qi], inst, node0, d, delay);
 }
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
@@ -2428,7 +2443,8 @@ hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, cons
     if (l_end <= l_begin) return hipSuccess;
     WalkOut o{y, stop, stop_delay, residual_mode, lambda, r_dense, done_fx,
               tr ? *tr : TransitOut{nullptr, nullptr, nullptr, nullptr, nullptr, 0u}, fl.err_overflow};
-    hipLaunchKernelGGL(k_walk, dim3((l_end - l_begin + kWG - 1) / kWG), dim3(kWG), 0, s, net, dem, labels,
+    const int64_t per = (int64_t)kWG * kWalkLegsPerThread;
+    hipLaunchKernelGGL(k_walk, dim3((unsigned)((l_end - l_begin + per - 1) / per)), dim3(kWG), 0, s, net, dem, labels,
                        time_cost, st, fl, o, l_begin, l_end);
     return hipGetLastError();
 }
@@ -2641,7 +2657,7 @@ __global__ __launch_bounds__(kWG) void k_fallback(NetDev net, DemDev dem, const 
                     u = net.col[e];
                     du = lab_val(lab, u - node0);
                     if (I.rule == RULE_PROGRESS && tau > I.dt32) {
-                        if (u != q) delay = tau - I.dt32;
+                        if (u != q) delay = progress_delay(tau - I.dt32, I.pq);
                         break;
                     }
                 }

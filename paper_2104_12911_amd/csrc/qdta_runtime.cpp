@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -11,6 +12,7 @@
 #include <map>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "qdta.h"
@@ -337,6 +339,10 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
     if (o->launch_form < 0 || o->launch_form > 2) { set_err(c, QDTA_EARG, "launch_form must be 0, 1 or 2"); return false; }
     if (o->tree_waves != 0 && o->tree_waves != 1 && o->tree_waves != 4) {
         set_err(c, QDTA_EARG, "tree_waves must be 0, 1 or 4");
+        return false;
+    }
+    if (!(o->progress_quantum_s >= 0.0) || !std::isfinite(o->progress_quantum_s)) {
+        set_err(c, QDTA_EARG, "progress_quantum_s must be finite and >= 0");
         return false;
     }
     if (!(o->delta_scale >= 0.0) || !std::isfinite(o->delta_scale)) {
@@ -896,8 +902,9 @@ int apply_rule(qdta_ctx* c, const qdta_opts* o) {
     bool changed = false;
     for (size_t i = 0; i < c->inst.size(); ++i) {
         int32_t r = std::isfinite(c->inst[i].dt_s) ? o->trunc_rule : QDTA_RULE_NONE;
-        if (c->h_inst[i].rule != r) {
+        if (c->h_inst[i].rule != r || c->h_inst[i].pq != o->progress_quantum_s) {
             c->h_inst[i].rule = r;
+            c->h_inst[i].pq = o->progress_quantum_s;
             changed = true;
         }
     }
@@ -1214,26 +1221,62 @@ int64_t trips_fx(double t) { return (int64_t)std::nearbyint(t * 1048576.0); }
 
 // Sort legs by (dest, orig, delay) and sum equal ones; drop zero and
 // orig == dest.  Delays are non-negative floats, which order like their bits.
+// Legs of different destinations never merge: they are bucketed by
+// destination (counting sort), and the buckets are sorted by (orig, delay)
+// packed in 64 bits on several host threads (the link-progress rule leaves
+// tens of millions of pending legs at a peak interval).
 void merge_legs(std::vector<int32_t>& o, std::vector<int32_t>& d, std::vector<int64_t>& w, std::vector<float>& t) {
-    t.resize(o.size(), 0.0f);
-    auto key = [&](size_t i) { return std::make_tuple(d[i], o[i], __builtin_bit_cast(uint32_t, t[i])); };
-    std::vector<size_t> idx(o.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return key(a) < key(b); });
+    const size_t n = o.size();
+    t.resize(n, 0.0f);
+    int32_t dmax = -1;
+    for (size_t i = 0; i < n; ++i) dmax = std::max(dmax, d[i]);
+    std::vector<size_t> start((size_t)dmax + 2, 0), idx(n);
+    for (size_t i = 0; i < n; ++i) start[(size_t)d[i] + 1]++;
+    for (size_t v = 0; v + 1 < start.size(); ++v) start[v + 1] += start[v];
+    {
+        std::vector<size_t> fill(start.begin(), start.end() - 1);
+        for (size_t i = 0; i < n; ++i) idx[fill[(size_t)d[i]]++] = i;
+    }
+    // per destination: (orig << 32 | delay bits, weight), sorted and summed
+    std::vector<std::vector<std::pair<uint64_t, int64_t>>> out((size_t)dmax + 1);
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        std::vector<std::pair<uint64_t, int64_t>> v;
+        for (int64_t b; (b = next.fetch_add(1)) <= dmax;) {
+            const size_t b0 = start[(size_t)b], b1 = start[(size_t)b + 1];
+            if (b0 == b1) continue;
+            v.clear();
+            for (size_t k = b0; k < b1; ++k) {
+                const size_t i = idx[k];
+                v.emplace_back(((uint64_t)(uint32_t)o[i] << 32) | __builtin_bit_cast(uint32_t, t[i]), w[i]);
+            }
+            std::sort(v.begin(), v.end(), [](const auto& a, const auto& c) { return a.first < c.first; });
+            auto& r = out[(size_t)b];
+            for (size_t k = 0; k < v.size(); ++k) {
+                if (!r.empty() && r.back().first == v[k].first) r.back().second += v[k].second;
+                else r.push_back(v[k]);
+            }
+        }
+    };
+    const unsigned nt = n < (1u << 16) ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned k = 1; k < nt; ++k) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
     std::vector<int32_t> no, nd;
     std::vector<int64_t> nw;
-    std::vector<float> nt;
-    for (size_t k = 0; k < idx.size(); ++k) {
-        size_t i = idx[k];
-        if (k > 0 && key(idx[k - 1]) == key(i)) nw.back() += w[i];
-        else { no.push_back(o[i]); nd.push_back(d[i]); nw.push_back(w[i]); nt.push_back(t[i]); }
+    std::vector<float> ntl;
+    for (int32_t b = 0; b <= dmax; ++b) {
+        for (const auto& e : out[(size_t)b]) {
+            const int32_t oo = (int32_t)(e.first >> 32);
+            if (e.second <= 0 || oo == b) continue;
+            no.push_back(oo);
+            nd.push_back(b);
+            nw.push_back(e.second);
+            ntl.push_back(__builtin_bit_cast(float, (uint32_t)(e.first & 0xffffffffu)));
+        }
     }
-    size_t j = 0;
-    for (size_t k = 0; k < no.size(); ++k) {
-        if (nw[k] > 0 && no[k] != nd[k]) { no[j] = no[k]; nd[j] = nd[k]; nw[j] = nw[k]; nt[j] = nt[k]; ++j; }
-    }
-    no.resize(j); nd.resize(j); nw.resize(j); nt.resize(j);
-    o.swap(no); d.swap(nd); w.swap(nw); t.swap(nt);
+    o.swap(no); d.swap(nd); w.swap(nw); t.swap(ntl);
 }
 
 }  // namespace
@@ -1263,6 +1306,7 @@ void qdta_default_opts(qdta_opts* o) {
     o->keep_history = 0;
     o->waves_per_cu = 0;
     o->delta_scale = 0.0;
+    o->progress_quantum_s = 60.0;
 }
 
 const char* qdta_strerror(int code) {

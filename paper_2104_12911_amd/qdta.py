@@ -42,7 +42,8 @@ class Opts(C.Structure):
                 ("max_iter", C.c_int32), ("fixed_iters", C.c_int32), ("keep_history", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("delta_scale", C.c_double), ("sssp_shape", C.c_int32),
                 ("launch_form", C.c_int32), ("tree_waves", C.c_int32), ("history_mib", C.c_int32),
-                ("objective", C.c_int32), ("sssp_kernel", C.c_int32), ("load_form", C.c_int32)]
+                ("objective", C.c_int32), ("sssp_kernel", C.c_int32), ("load_form", C.c_int32),
+                ("pad1", C.c_int32), ("progress_quantum_s", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -45,7 +45,7 @@ def test_default_opts_are_the_papers():
     assert (o.alpha, o.beta, o.K, o.passes) == (0.15, 4, 32, 3)
     assert (o.T1, o.T2, o.dx, o.tol) == (1e-4, 1e-4, 1e-4, 1e-4)
     assert o.trunc_rule == q.RULE_CEIL and o.ls_mode == q.LS_KSECTION
-    assert ctypes.sizeof(q.Opts) == 128 and ctypes.sizeof(q.Stats) == 48
+    assert ctypes.sizeof(q.Opts) == 136 and ctypes.sizeof(q.Stats) == 48
 
 
 def test_strerror_covers_codes():

@@ -1,7 +1,9 @@
 """GPU parity of the link-progress truncation (QDTA_RULE_PROGRESS) against the
 oracle: loading, stop nodes and stop delays bit for bit; Frank-Wolfe and the
 interval chain with residual legs carrying their delays, bit for bit; the
-long-link example of the oracle's pins; checkpoint and resume with delays."""
+long-link example of the oracle's pins; checkpoint and resume with delays.
+With exact delays (progress_quantum_s = 0) and with delays rounded up to a
+quantum (the library's default of 60 s, and others)."""
 from __future__ import annotations
 
 import numpy as np
@@ -36,7 +38,8 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def test_progress_aon_with_carried_delays(q, orc):
+@pytest.mark.parametrize("pq", [0.0, 60.0, 7.5])
+def test_progress_aon_with_carried_delays(q, orc, pq):
     """Legs carrying delays (set as residual, merged by set_demand) on tiny
     graphs and on the metro network: loading, stop nodes and delays equal the
     oracle's."""
@@ -67,8 +70,9 @@ def test_progress_aon_with_carried_delays(q, orc):
             y = torch.empty(net.m, dtype=torch.int64, device="cuda")
             stop = torch.empty(o.size, dtype=torch.int32, device="cuda")
             sd = torch.empty(o.size, dtype=torch.float32, device="cuda")
-            ctx.aon(q.default_opts(trunc_rule=q.RULE_PROGRESS, delta_scale=0.5), _dev(cost), y, stop, sd)
-            yo, so, sdo, _ = orc.aon(net, cost, o, d, w, dt, orc.RULE_PROGRESS, delay=t, want_delay=True)
+            ctx.aon(q.default_opts(trunc_rule=q.RULE_PROGRESS, delta_scale=0.5, progress_quantum_s=pq), _dev(cost),
+                    y, stop, sd)
+            yo, so, sdo, _ = orc.aon(net, cost, o, d, w, dt, orc.RULE_PROGRESS, delay=t, want_delay=True, pq=pq)
             assert np.array_equal(_host(y), yo)
             assert np.array_equal(_host(stop), so)
             assert np.array_equal(_host(sd).view(np.uint32), sdo.view(np.uint32))
@@ -93,20 +97,22 @@ def _day(q, torch, net, days, opts):
     return out
 
 
-def test_progress_long_link_by_hand(q, orc):
+@pytest.mark.parametrize("pq", [0.0, 60.0])
+def test_progress_long_link_by_hand(q, orc, pq):
     """The oracle pin's 12-minute link under 5-minute intervals: the trip is
-    carried 420 s, then 120 s short of node 1, and completes in interval 2."""
+    carried 420 s, then 120 s short of node 1, and completes in interval 2
+    (both delays are whole minutes, so rounding to 60 s keeps them)."""
     import torch
     net = Network(3, np.array([0, 1, 2, 2], np.int32), np.array([1, 2], np.int32),
                   np.array([720.0, 60.0], np.float32), np.array([1e6, 1e6], np.float32))
     one = Demand(np.array([0], np.int32), np.array([2], np.int32), np.array([1.0]), 300.0)
     empty = Demand(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 300.0)
-    opts = q.default_opts(alpha=0.0, trunc_rule=q.RULE_PROGRESS, keep_history=1)
+    opts = q.default_opts(alpha=0.0, trunc_rule=q.RULE_PROGRESS, keep_history=1, progress_quantum_s=pq)
     g = _day(q, torch, net, [one, empty, empty, empty], opts)
     assert g[0]["f"].tolist() == [FX, 0] and g[0]["res"][3].tolist() == [420.0]
     assert g[1]["f"].tolist() == [0, 0] and g[1]["res"][3].tolist() == [120.0]
     assert g[2]["f"].tolist() == [0, FX] and g[2]["res"][0].size == 0
-    ref, _ = orc.qdta_day(net, [one, empty, empty, empty], alpha_b=0.0, rule=orc.RULE_PROGRESS)
+    ref, _ = orc.qdta_day(net, [one, empty, empty, empty], alpha_b=0.0, rule=orc.RULE_PROGRESS, pq=pq)
     for a, b in zip(g, ref):
         if a is None:
             continue
@@ -115,8 +121,8 @@ def test_progress_long_link_by_hand(q, orc):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("scale", ["grid", "metro"])
-def test_progress_day_chain(q, orc, scale):
+@pytest.mark.parametrize("scale,pq", [("grid", 0.0), ("grid", 30.0), ("metro", 0.0), ("metro", 60.0)])
+def test_progress_day_chain(q, orc, scale, pq):
     """A chain of short intervals (90 s on the grid; 120 s on the 1/20-scale
     metro network's morning): flows, iterations and the residual legs with
     their delays equal the oracle's, interval by interval."""
@@ -133,9 +139,9 @@ def test_progress_day_chain(q, orc, scale):
         w = synth.config3_day(0.05)
         net = w.net
         days = [Demand(x.orig, x.dest, x.trips, 120.0) for x in w.demand[30:33]]
-    opts = q.default_opts(keep_history=1, tol=1e-3, max_iter=30, trunc_rule=q.RULE_PROGRESS)
+    opts = q.default_opts(keep_history=1, tol=1e-3, max_iter=30, trunc_rule=q.RULE_PROGRESS, progress_quantum_s=pq)
     g = _day(q, torch, net, days, opts)
-    ref, _ = orc.qdta_day(net, days, tol=1e-3, max_iter=30, rule=orc.RULE_PROGRESS)
+    ref, _ = orc.qdta_day(net, days, tol=1e-3, max_iter=30, rule=orc.RULE_PROGRESS, pq=pq)
     carried = 0
     for a, b in zip(g, ref):
         assert a["iters"] == b["iters"]
