@@ -389,6 +389,8 @@ def mode_day(args, torch, qdta):
         if legs == 0:
             iters.append(0)
             seg_s.append(0.0)
+            gaps.append(0.0)
+            stops.append(-1)
             continue
         st, rc = ctx.solve(opts)
         torch.cuda.synchronize()
@@ -425,7 +427,9 @@ def mode_day(args, torch, qdta):
                       "tree_waves": opts.tree_waves or 4,
                       "delta_scale": opts.delta_scale or 10.0, "left_after_last_trips": carried / FX,
                       "split_s": {k: round(v, 3) for k, v in split.items()},
-                      "iters_per_interval": iters, "seconds_per_interval": [round(x, 3) for x in seg_s]}), flush=True)
+                      "iters_per_interval": iters, "seconds_per_interval": [round(x, 3) for x in seg_s],
+                      "gap_per_interval": [float("%.3g" % g) for g in gaps],
+                      "stopped_by_per_interval": stops}), flush=True)
 
 
 def mode_calib(args, torch, qdta):
