@@ -432,8 +432,10 @@ int qdta_model_forward(qdta_ctx *ctx, const qdta_opts *opts, const double *d, co
 int qdta_model_backward(qdta_ctx *ctx, uint64_t fwd_id, const double *fbar, double *dbar, double *capbar);
 
 /* Autotuner: times the shortest-path launch of the current demand (every
- * instance, under the costs BPR(f) of the last solved iterate, free-flow
- * costs otherwise) for a grid of kernel shapes, bucket widths and
+ * instance, under the costs BPR(f) of the running solve's iterate or of the
+ * last solved one, free-flow costs otherwise; the running solve's next
+ * qdta_fw_step recomputes whatever the trials overwrote) for a grid of
+ * kernel shapes, bucket widths and
  * wavefronts per tree, stopping once about budget_ms of GPU time is spent,
  * and writes the fastest into opts->sssp_shape, opts->delta_scale and
  * opts->tree_waves.  The configuration passed in (zero fields read as the

@@ -2039,8 +2039,9 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
         RC(ensure_contraction(c, c->h_dest_node.data(), c->h_dest_node.size()));
     NetDev net = net_view(c, o);
     DemDev dem = dem_view(c);
-    // trial costs: BPR of the current flows when an interval was solved, else free flow
-    if (!c->solved) HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
+    // trial costs: BPR of the current flows while a solve runs or after one,
+    // else free flow
+    if (!c->solved && c->fw_j < 0) HIPCHECK(c, launch_fill_i64(c->stream, c->f.p, 0, c->M));
     RC(clear_flags(c));
     HIPCHECK(c, launch_bpr(c->stream, net, c->f.p, o->alpha, o->beta, c->cost.p, c->radj.p, nullptr, 0, c->flags.p));
     hipEvent_t e0, e1;
