@@ -83,7 +83,8 @@ def sssp_kernel_name(shape, tree_waves, kernel=1):
         return "k_sssp_wn<%d, %d>" % WN_SHAPES.get(shape, (2, 4))
     shape = shape if shape in WG_SHAPES else 3
     if kernel == 4:
-        return "k_sssp_wg<%d, %d, true>" % WG_SHAPES[shape]
+        # the <2, 4> form is instantiated with registers for 7 wavefronts per SIMD
+        return "k_sssp_wg<%d, %d, true%s>" % (WG_SHAPES[shape] + (", 7" if shape == 3 else "",))
     if (tree_waves or 4) == 1:
         return "k_sssp_ds<%d, %d>" % DS_SHAPES[shape]
     return "k_sssp_wg<%d, %d, false>" % WG_SHAPES[shape]
@@ -566,7 +567,7 @@ def main():
     ap.add_argument("--reduce-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write profiles/sssp_traffic.json from two rocprofv3 --pmc databases (FETCH_SIZE, "
                          "WRITE_SIZE) of runs made with --copy-calib-mib, and exit")
-    ap.add_argument("--traffic-kernel", default="k_sssp_wg<2, 4, true>",
+    ap.add_argument("--traffic-kernel", default="k_sssp_wg<2, 4, true, 7>",
                     help="kernel instantiation the traffic reduction averages")
     ap.add_argument("--traffic-commands", default="", help="the rocprofv3 commands, ' ;; '-separated, recorded")
     ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "sssp_traffic.json"))
@@ -733,7 +734,7 @@ def main():
                                f"intervals: {net.n} nodes, {net.m} links, {Q} destinations, {P} legs "
                                f"({dem.P} original + {ro.size} residual), dt {dem.dt_s:g} s",
                    "sssp_kernel": kname, "delta_scale": opts.delta_scale or 10.0,
-                   "waves_per_cu": opts.waves_per_cu or 24,
+                   "waves_per_cu": opts.waves_per_cu or (32 if opts.tree_waves == 1 else 28),
                    "line_search": "K-section K=32 x3", "launch": "HIP graph per FW iteration"},
         "gteps": Q * net.m / sssp_avg_s / 1e9,
         "gteps_counted": work_links / n_launch / sssp_avg_s / 1e9,

@@ -116,8 +116,9 @@ typedef struct {
     int32_t fixed_iters;   /* > 0: exactly this many updates, stop rule ignored */
     int32_t keep_history;  /* record (alpha_j, c_j) per iteration; needed by qdta_advance_interval */
     int32_t waves_per_cu;  /* shortest-path wavefronts in flight per compute unit (a tree takes
-                              tree_waves of them): 0 auto (24 with four wavefronts per tree,
-                              32 with one), else 1..32 */
+                              tree_waves of them): 0 auto (28 for the chain-contracted search, 24
+                              for the other kernels with four wavefronts per tree, 32 with one),
+                              else 1..32 */
     double delta_scale;    /* delta-stepping bucket width as a multiple of the instance's geometric-mean
                               link cost: 0 auto (10.0); any value > 0 gives the same trees, only the speed
                               changes */

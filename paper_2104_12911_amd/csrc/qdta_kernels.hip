@@ -1059,8 +1059,12 @@ __device__ __forceinline__ void chain_fill(const NetDev& net, label_t* D, int no
 // (a chain's record adds its link costs one at a time); a leg whose origin
 // is left out waits for the kept nodes its label depends on; after the
 // search the chain nodes' labels are filled from their chains' ends.
-template <int U, int V, bool CT>
-__global__ __launch_bounds__(kWG) void k_sssp_wg(NetDev net, DemDev dem, const uint2* __restrict__ radj,
+//
+// W: wavefronts per SIMD the register allocation leaves room for (1: the
+// compiler's choice).  The contracted <2, 4> form fits 7 in 72 VGPRs with no
+// spill, one more than the 6 the compiler's own choice of 74 allows.
+template <int U, int V, bool CT, int W = 1>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k_sssp_wg(NetDev net, DemDev dem, const uint2* __restrict__ radj,
                                                  label_t* labels, Scratch scr, const InstState* st,
                                                  const float* __restrict__ delta_inst, int early, int t_begin,
                                                  int t_end) {
@@ -2186,7 +2190,10 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
         switch (variant - 32) {
             case 0: QDTA_SSSP_CT(1, 2); break;
             case 1: QDTA_SSSP_CT(1, 4); break;
-            case 2: QDTA_SSSP_CT(2, 4); break;
+            case 2:
+                hipLaunchKernelGGL((k_sssp_wg<2, 4, true, 7>), g, b, 0, s, net, dem, radj, labels, scr, st, delta_inst,
+                                   early, t_begin, t_end);
+                break;
             case 3: QDTA_SSSP_CT(4, 4); break;
             case 4: QDTA_SSSP_CT(2, 2); break;
             default: QDTA_SSSP_CT(4, 2); break;

@@ -361,9 +361,12 @@ bool opts_ok(qdta_ctx* c, const qdta_opts* o) {
 int tree_waves(const qdta_opts* o) { return (o->sssp_kernel < 2 && o->tree_waves == 1) ? 1 : 4; }
 // FW updates a solve may apply (iterates 1..this, plus the initial AON)
 int hist_iters(const qdta_opts* o) { return o->fixed_iters > 0 ? o->fixed_iters : std::max(o->max_iter, 0); }
+bool uses_contraction(const qdta_opts* o);
+// wavefronts in flight per CU by default: what the kernels' registers allow
+// (one tree per wavefront: 32; the contracted <2, 4> form: 28; else 24)
 int waves_per_cu(const qdta_opts* o) {
     if (o->waves_per_cu) return o->waves_per_cu;
-    return tree_waves(o) == 1 ? 32 : 24;
+    return tree_waves(o) == 1 ? 32 : uses_contraction(o) ? 28 : 24;
 }
 double delta_scale(const qdta_opts* o) { return o->delta_scale > 0.0 ? o->delta_scale : 10.0; }
 // Block size of each block-local shape (qdta_opts.sssp_shape 1..4)

@@ -28,8 +28,9 @@ def test_kernel_names(bench):
     assert bench.sssp_kernel_name(5, 4) == "k_sssp_wg<2, 2, false>"
     assert bench.sssp_kernel_name(3, 1) == "k_sssp_ds<4, 4>"
     assert bench.sssp_kernel_name(6, 1) == "k_sssp_ds<1, 1>"
-    assert bench.sssp_kernel_name(3, 4, 4) == "k_sssp_wg<2, 4, true>"   # chain-contracted search
-    assert bench.sssp_kernel_name(0, 1, 4) == "k_sssp_wg<2, 4, true>"   # one workgroup per tree whatever asked
+    assert bench.sssp_kernel_name(3, 4, 4) == "k_sssp_wg<2, 4, true, 7>"   # chain-contracted search
+    assert bench.sssp_kernel_name(0, 1, 4) == "k_sssp_wg<2, 4, true, 7>"   # one workgroup per tree whatever asked
+    assert bench.sssp_kernel_name(2, 4, 4) == "k_sssp_wg<1, 4, true>"
     assert bench.sssp_kernel_name(2, 4, 3) == "k_sssp_wn<2, 4>"
 
 
