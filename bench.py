@@ -270,6 +270,16 @@ def mode_plain(args, torch, qdta):
     ctx = _ctx_for(qdta, stream, [(w.net, w.demand)])
     out = {"mode": "plain", "workload": "config2"}
     opts_b = qdta.default_opts(tol=args.tol, max_iter=args.steps)
+    if not args.no_autotune:
+        # tuned under congested costs: a few iterations first (untimed)
+        ctx.fw_begin(opts_b)
+        for _ in range(3):
+            ctx.fw_step(opts_b)
+        opts_b, best = ctx.autotune(opts_b, 2000.0)
+        log(f"autotune: sssp_shape={opts_b.sssp_shape} delta_scale={opts_b.delta_scale} "
+            f"tree_waves={opts_b.tree_waves} ({best:.1f} ms)")
+        out["autotuned"] = {"sssp_shape": opts_b.sssp_shape, "delta_scale": opts_b.delta_scale,
+                            "tree_waves": opts_b.tree_waves}
     # the batched solve, step by step so that long runs report progress
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -288,7 +298,8 @@ def mode_plain(args, torch, qdta):
         f"stopped_by {st[0]['stopped_by']}")
     per = {}
     for form in (0, 2):
-        o = qdta.default_opts(fixed_iters=1 << 30, launch_form=form)
+        o = qdta.default_opts(fixed_iters=1 << 30, launch_form=form, sssp_shape=opts_b.sssp_shape,
+                              delta_scale=opts_b.delta_scale, tree_waves=opts_b.tree_waves)
         ctx.fw_begin(o)
         ctx.fw_step(o)
         torch.cuda.synchronize()

@@ -2051,22 +2051,33 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
     HIPCHECK(c, hipEventCreate(&e0));
     HIPCHECK(c, hipEventCreate(&e1));
     static const int shapes[] = {3, 4, 2, 5};
-    static const double scales[] = {10.0, 5.0, 20.0};
+    static const double scales[] = {10.0, 5.0, 20.0, 2.5, 1.25};
     static const int tws[] = {4, 1};
+    // trial order: the bucket widths at the starting shape first (on heavily
+    // congested networks the width matters most and trials are slow), then
+    // every shape at every width, then one wavefront per tree
+    struct Trial { int shape; double scale; int tw; };
+    std::vector<Trial> trials;
     // the starting configuration (the caller's, else the defaults) is trial
     // -1, after an untimed launch that takes the first-touch costs; another
     // replaces it only when at least 5% faster (single trials vary by about
     // 2%), so near-ties do not flip the choice from run to run
     const int start_shape = o->sssp_shape ? o->sssp_shape : 3, start_tw = o->tree_waves ? o->tree_waves : 4;
     const double start_scale = delta_scale(o);
+    for (double sc : scales)
+        if (sc != start_scale) trials.push_back({start_shape, sc, start_tw});
+    for (int tw : tws)
+        for (double sc : scales)
+            for (int sh : shapes)
+                if (!(tw == start_tw && sh == start_shape)) trials.push_back({sh, sc, tw});
     int best_shape = start_shape, best_tw = start_tw;
     double best_scale = start_scale, best = 1e300, start_ms = 1e300, spent = 0.0;
     int rc = QDTA_OK;
-    for (int k = -2; k < 24 && rc == QDTA_OK && (k < 0 || spent < budget_ms); ++k) {
+    for (int k = -2; k < (int)trials.size() && rc == QDTA_OK && (k < 0 || spent < budget_ms); ++k) {
         qdta_opts t = *o;
-        t.sssp_shape = k < 0 ? start_shape : shapes[k % 4];
-        t.delta_scale = k < 0 ? start_scale : scales[(k % 12) / 4];
-        t.tree_waves = k < 0 ? start_tw : tws[k / 12];
+        t.sssp_shape = k < 0 ? start_shape : trials[k].shape;
+        t.delta_scale = k < 0 ? start_scale : trials[k].scale;
+        t.tree_waves = k < 0 ? start_tw : trials[k].tw;
         const int sh = t.sssp_shape, tw = t.tree_waves;
         const double sc = t.delta_scale;
         // the trial's own occupancy (the scratch, sized for one wavefront per
