@@ -799,6 +799,37 @@ def test_autotune_picks_valid_options_and_results_do_not_move(torch_dev, q, orc)
     assert np.array_equal(host(f), ref.f)
 
 
+def test_autotune_inside_a_running_solve_and_load_form(torch_dev, q, orc):
+    """Tuned after two iterations of a running solve (its trials overwrite
+    the costs, trees and direction, which the next step recomputes), the
+    solve goes on to the same flows as an untuned one and as the oracle.  On
+    a plain interval the tuner also picks the loading form (walks or merged
+    paths), which changes no bit either."""
+    w = synth.config1()
+    o, d, wfx = orc.demand_legs(w.demand.orig, w.demand.dest, w.demand.trips)
+    ref = orc.fw_solve(w.net, o, d, wfx, fixed_iters=6, keep_history=False)
+    with q.Context() as ctx:
+        ctx.add(w.net)
+        ctx.set_demand(0, w.demand.orig, w.demand.dest, w.demand.trips, w.demand.dt_s)
+        opts = q.default_opts(fixed_iters=6)
+        ctx.fw_begin(opts)
+        for _ in range(2):
+            ctx.fw_step(opts)
+        tuned, best = ctx.autotune(opts, 200.0)
+        assert tuned.load_form in (1, 2) and best > 0
+        live = True
+        while live:
+            st, live = ctx.fw_step(tuned)
+        f = torch_dev.empty(w.net.m, dtype=torch_dev.int64, device="cuda")
+        ctx.get_flows(f)
+        assert np.array_equal(host(f), ref.f)
+        assert st[0]["iters"] == 6 and st[0]["gap"] == ref.gap
+        for form in (1, 2):
+            st2, _ = ctx.solve(q.default_opts(fixed_iters=6, load_form=form))
+            ctx.get_flows(f)
+            assert np.array_equal(host(f), ref.f), form
+
+
 @pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6])
 def test_sssp_shapes_identical(torch_dev, q, orc, shape, waves):
