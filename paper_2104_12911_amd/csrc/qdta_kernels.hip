@@ -2381,15 +2381,42 @@ __device__ __forceinline__ bool stop_at_node(int rule, float tau, float dt) {
 // time_cost: the costs that clock the truncation (Eq. 2); NULL = the trees'
 // own costs (the forward records), as in the AON of an iteration.
 // Legs per thread of the walk: the threads of a wavefront walk legs of
-// different lengths, so each takes several (strided, so that a wavefront
-// still walks 64 consecutive legs of one tree at a time) and the sums of
-// their lengths vary less than single lengths do.
+// different lengths, so each takes several (a workgroup walks a contiguous
+// run of kWG * kWalkLegsPerThread legs, a wavefront 64 consecutive legs at a
+// time) and the sums of their lengths vary less than single lengths do.
 constexpr int kWalkLegsPerThread = 4;
+// Loads of a workgroup's legs are summed per link in an LDS table first
+// (legs of one destination share links); the table is added to y when the
+// workgroup is done, and a load whose probes find no slot goes to y directly.
+// Integer sums: the order does not change them.
+constexpr int kWalkSlots = 2048;
 
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                               const float* __restrict__ time_cost, const InstState* st,
                                               FlagsDev fl, WalkOut o, int l_begin, int l_end) {
-    for (int l = l_begin + blockIdx.x * kWG + threadIdx.x; l < l_end; l += gridDim.x * kWG) {
+    __shared__ int s_key[kWalkSlots];
+    __shared__ unsigned long long s_sum[kWalkSlots];
+    for (int x = threadIdx.x; x < kWalkSlots; x += kWG) {
+        s_key[x] = -1;
+        s_sum[x] = 0ull;
+    }
+    __syncthreads();
+    auto load = [&](int e, int64_t d) {
+        int h = (int)(((unsigned)e * 2654435761u) >> 21) & (kWalkSlots - 1);
+        for (int probe = 0; probe < 4; ++probe) {
+            int k = s_key[h];
+            if (k == -1) k = atomicCAS(&s_key[h], -1, e);
+            if (k == -1 || k == e) {
+                atomicAdd(&s_sum[h], (unsigned long long)d);
+                return;
+            }
+            h = (h + 1) & (kWalkSlots - 1);
+        }
+        atomicAdd(reinterpret_cast<unsigned long long*>(&o.y[e]), (unsigned long long)d);
+    };
+    const int base = l_begin + blockIdx.x * kWG * kWalkLegsPerThread;
+    const int lim = min(l_end, base + kWG * kWalkLegsPerThread);
+    for (int l = base + threadIdx.x; l < lim; l += kWG) {
         const int qi = dem.leg_q[l];
         const int inst = dem.dest_inst[qi];
         if (!inst_live(st, inst)) continue;
@@ -2427,7 +2454,7 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
                 }
                 const float nt = tau + (time_cost ? time_cost[e] : ce);
                 if (I.rule == RULE_FLOOR && nt > I.dt32) break;
-                if (!o.residual_mode) atomicAdd((unsigned long long*)&o.y[e], (unsigned long long)d);
+                if (!o.residual_mode) load(e, d);
                 tau = nt;
                 u = head;
                 du = lab_val(lab, u - node0);
@@ -2439,6 +2466,9 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
         }
         if (!absorbed) finish_leg(o, l, u, q, qi, dem.dest_lab[qi], inst, node0, d, delay);
     }
+    __syncthreads();
+    for (int x = threadIdx.x; x < kWalkSlots; x += kWG)
+        if (s_key[x] >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(&o.y[s_key[x]]), s_sum[x]);
 }
 
 hipError_t launch_walk(hipStream_t s, const NetDev& net, const DemDev& dem, const label_t* labels,
