@@ -149,7 +149,8 @@ typedef struct {
                               between two kept nodes is relaxed as one link applying its link costs one
                               by one, and their labels are filled from the run's ends after the search
                               (built on the host when first needed and again when a destination is a
-                              left-out node).  The trees are the same whichever runs */
+                              left-out node; networks of fewer than 2^30 nodes in all, QDTA_EARG
+                              otherwise).  The trees are the same whichever runs */
     int32_t load_form;     /* loading of plain intervals (dt = +inf, every instance plain): 0 auto (walk),
                               1 walk every leg to its destination, 2 merge the legs' paths children before
                               parents (two passes over the legs, each link loaded once per tree with the sum

@@ -73,10 +73,11 @@ struct NetDev {
     uint2* fadj;             // [M]   forward records (head, cost bits): the costs the trees are grown with
     const InstDev* inst;     // [ninst]
     // chain contraction (NULL until built): the search's reverse CSR over the
-    // kept nodes, whose records are 2 words (source, cost bits) or, for a
-    // chain, (source | 1 << 31, word offset of its cost block: count, then
-    // the costs in the order they are added); cslot[a] is the word that
-    // holds link a's cost there (-1 none)
+    // kept nodes, whose records are 4 words: source | form << 30, then the
+    // cost bits in the order they are added, one for a plain link (form 0),
+    // two or three for a chain of one or two nodes (forms 1, 2); form 3, a
+    // longer chain, holds the word offset of its cost block (count, then the
+    // costs) instead; cslot[a] is the word that holds link a's cost (-1 none)
     const int32_t* crptr;    // [N+1]
     uint32_t* cbuf;
     const int32_t* cslot;    // [M]

@@ -1093,7 +1093,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
         const InstDev I = net.inst[inst];
         const int n = I.n, node0 = I.node0;
         const int* __restrict__ rptr = (CT ? net.crptr : net.rptr) + node0;
-        const uint2* __restrict__ recs = CT ? reinterpret_cast<const uint2*>(net.cbuf) : radj;
+        const uint2* __restrict__ recs = radj;
+        const uint4* __restrict__ crec = reinterpret_cast<const uint4*>(net.cbuf);
         label_t* D = labels + dem.dest_lab[t];
         const int root = dem.dest_node[t] - node0;
         const float delta = delta_inst[inst];
@@ -1259,11 +1260,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                                 if (s_pre[mid] <= g) lo = mid; else hi = mid;
                             }
                             const int e = s_e0[lo] + (g - s_pre[lo]);
-                            const uint2 r = recs[e];
-                            if (CT && (r.x & kNotQueued)) {
-                                vv[x] = (int)(r.x & kValueBits) - node0;
-                                cd[x] = chain_fold(net.cbuf + r.y, s_dw[lo]);
+                            if (CT) {
+                                // form 0: a link; 1, 2: a chain's two or three
+                                // costs inline; 3: a longer chain's cost block
+                                const uint4 r = crec[e];
+                                const uint32_t form = r.x >> 30;
+                                vv[x] = (int)(r.x & 0x3fffffffu) - node0;
+                                if (form == 3u) {
+                                    cd[x] = chain_fold(net.cbuf + r.y, s_dw[lo]);
+                                } else {
+                                    float d = s_dw[lo] + __uint_as_float(r.y);
+                                    if (form >= 1u) d = d + __uint_as_float(r.z);
+                                    if (form >= 2u) d = d + __uint_as_float(r.w);
+                                    cd[x] = d;
+                                }
                             } else {
+                                const uint2 r = recs[e];
                                 vv[x] = (int)r.x - node0;
                                 cd[x] = s_dw[lo] + __uint_as_float(r.y);
                             }

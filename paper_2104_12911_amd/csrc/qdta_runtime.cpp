@@ -552,13 +552,20 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
 // addition, which is what the same relaxations link by link would give; the
 // same for v->xk->...->x1->u at u.  After a tree's search, each chain node's
 // label is the lesser of the two folds from the ends' labels (see the kernel).
-// Words of the contracted records at most: one record (2 words) per link at
-// most, and per chain of k nodes two cost blocks of ceil((k + 2) / 4) * 4
-// words at most, i.e. at most 8 words per left-out node.
-size_t contraction_words(int64_t N, int64_t M) { return 2 * (size_t)M + 4 + 8 * (size_t)N; }
+// Records are 4 words: (source | form << 30, then up to three costs in the
+// order they are added).  Form 0 is a plain link (one cost), forms 1 and 2 a
+// chain of one or two nodes (two or three costs inline), form 3 a longer
+// chain, whose second word is the offset of its cost block (count, then the
+// costs).  Inline costs spare the search a dependent read per relaxation.
+// Words at most: one record per link at most (a chain's record stands for
+// two links or more), and per chain of k > 2 nodes two cost blocks of
+// ceil((k + 2) / 4) * 4 words, under 6 words per left-out node.
+constexpr int kInlineCosts = 3;
+size_t contraction_words(int64_t N, int64_t M) { return 4 * (size_t)M + 4 + 8 * (size_t)N; }
 
 int build_contraction(qdta_ctx* c) {
     const int64_t N = c->N;
+    if (N >= (int64_t)1 << 30) return set_err(c, QDTA_EARG, "the contracted search takes fewer than 2^30 nodes");
     const int ni = (int)c->inst.size();
     std::vector<int32_t> crp(N + 1, 0), cslot(c->M, -1), ch_ptr{0}, ch_node, inst_chain(ni + 1, 0);
     std::vector<int2> ch_end, ch_link;
@@ -723,10 +730,10 @@ int build_contraction(qdta_ctx* c) {
     });
     for (const Rec& r : recs) crp[r.head + 1]++;
     for (int64_t v = 0; v < N; ++v) crp[v + 1] += crp[v];
-    const size_t rec_words = 2 * recs.size();
-    size_t words = (rec_words + 3) / 4 * 4;
-    std::vector<size_t> blk(sc_links.size());
+    size_t words = 4 * recs.size();
+    std::vector<size_t> blk(sc_links.size(), 0);
     for (size_t s = 0; s < sc_links.size(); ++s) {
+        if (sc_links[s].size() <= (size_t)kInlineCosts) continue;
         blk[s] = words;
         words += (1 + sc_links[s].size() + 3) / 4 * 4;
     }
@@ -734,13 +741,18 @@ int build_contraction(qdta_ctx* c) {
     for (size_t k = 0; k < recs.size(); ++k) {
         const Rec& r = recs[k];
         if (r.link >= 0) {
-            cbuf[2 * k] = (uint32_t)r.src;
-            cslot[r.link] = (int32_t)(2 * k + 1);
+            cbuf[4 * k] = (uint32_t)r.src;
+            cslot[r.link] = (int32_t)(4 * k + 1);
+            continue;
+        }
+        const std::vector<int32_t>& ls = sc_links[r.chain];
+        if (ls.size() <= (size_t)kInlineCosts) {
+            cbuf[4 * k] = (uint32_t)r.src | (uint32_t)(ls.size() - 1) << 30;
+            for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]] = (int32_t)(4 * k + 1 + j);
         } else {
             const size_t b = blk[r.chain];
-            cbuf[2 * k] = (uint32_t)r.src | 0x80000000u;
-            cbuf[2 * k + 1] = (uint32_t)b;
-            const std::vector<int32_t>& ls = sc_links[r.chain];
+            cbuf[4 * k] = (uint32_t)r.src | 3u << 30;
+            cbuf[4 * k + 1] = (uint32_t)b;
             cbuf[b] = (uint32_t)ls.size();
             for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]] = (int32_t)(b + 1 + j);
         }
