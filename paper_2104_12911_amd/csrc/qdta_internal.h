@@ -16,6 +16,18 @@ constexpr int kBlkMaxBits = 8192;
 // chain-contracted search: most nodes one chain holds (longer runs of
 // two-neighbour nodes are cut by keeping a node)
 constexpr int kChainMax = 8;
+// A kept node's row of contracted records packed in one word, (first record
+// << 6) | count, carried by the records that name the node as their source
+// and by its queue entries so that a pop need not read the row pointers;
+// kNoRow when the row does not fit (64 records or more, or a first record at
+// 2^26 or beyond) or the record has no room for it.
+constexpr uint32_t kNoRow = 0xffffffffu;
+constexpr int kRowCountBits = 6;
+__host__ __device__ inline uint32_t pack_row(int64_t e0, int64_t count) {
+    return (count < (1 << kRowCountBits) && e0 < ((int64_t)1 << (32 - kRowCountBits)))
+               ? (uint32_t)(e0 << kRowCountBits) | (uint32_t)count
+               : kNoRow;
+}
 // allocation-free line search: 16 words of flags, then the exact accumulators
 // (three 64-bit chunks per sum, two sums per step size) of up to 64 instances
 // at K = 64
@@ -110,8 +122,12 @@ struct DemDev {
 // Per-wavefront scratch of the shortest-path kernel (also the workgroup
 // scratch of the tie fallback, slot = workgroup there).
 struct Scratch {
-    int32_t* nearq;          // [slots][nmax] near queue (ring of n + 1)
-    int32_t* farq;           // [slots][nmax] far queue of (node, label) pairs (2 ints each)
+    // near queue (ring of n + 1) and far queue of each slot: nmax entries of
+    // the node (1 word; contracted search: the node and its packed row, 2
+    // words) and of (node, label) (2 words; contracted search: node, label,
+    // packed row and a pad word, 4 words)
+    int32_t* nearq;
+    int32_t* farq;
     int64_t nmax;            // >= largest n + 65
     int32_t* work;           // tree work counter
     int32_t nslots;          // slots allocated (a launch is clamped to them)

@@ -25,6 +25,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "qdta_internal.h"
 
@@ -1078,9 +1079,26 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
     __shared__ int s_wsum[NW];
     __shared__ int s_t, s_nn, s_fn;
     __shared__ uint32_t s_fm;
+    __shared__ uint32_t s_row[CT ? NT * V : 1];   // each relaxation's source row, kept out of registers
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    int32_t* nearq = scr.nearq + (int64_t)blockIdx.x * scr.nmax;
-    uint2* farq = reinterpret_cast<uint2*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
+    // queue entries: the node (near) and (node, label) (far); the contracted
+    // search's also carry the node's packed row (kNoRow: read the row pointers)
+    using NearE = typename std::conditional<CT, uint2, int32_t>::type;
+    using FarE = typename std::conditional<CT, uint4, uint2>::type;
+    NearE* nearq = reinterpret_cast<NearE*>(scr.nearq) + (int64_t)blockIdx.x * scr.nmax;
+    FarE* farq = reinterpret_cast<FarE*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
+    auto near_entry = [](int v, uint32_t row) -> NearE {
+        if constexpr (CT) return make_uint2((uint32_t)v, row);
+        else return v;
+    };
+    auto far_entry = [](uint32_t v, uint32_t lab, uint32_t row) -> FarE {
+        if constexpr (CT) return make_uint4(v, lab, row, 0u);
+        else return make_uint2(v, lab);
+    };
+    auto far_row = [](const FarE& e) -> uint32_t {
+        if constexpr (CT) return e.z;
+        else return kNoRow;
+    };
     unsigned long long n_taken = 0, n_relaxed = 0;    // counted by every thread alike (uniform values)
     for (;;) {
         if (tid == 0) s_t = t_begin + atomicAdd(scr.work, 1);
@@ -1123,18 +1141,18 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
         __syncthreads();
         if (tid == 0) {
             D[root] = 0u;                         // value 0, queued
-            nearq[(root >> rsh) * (rs + 1)] = root;
+            nearq[(root >> rsh) * (rs + 1)] = near_entry(root, pack_row(rptr[root], rptr[root + 1] - rptr[root]));
         }
         __threadfence_block();
         __syncthreads();
-        auto ring_at = [&](int r, int pos) -> int32_t* {
+        auto ring_at = [&](int r, int pos) -> NearE* {
             const int cap = min(rs, n - r * rs) + 1;
             if (pos >= cap) pos -= cap;
             return nearq + (int64_t)r * (rs + 1) + pos;
         };
-        auto push_near = [&](int v) {
+        auto push_near = [&](int v, uint32_t row) {
             const int r = v >> rsh;
-            *ring_at(r, s_tail[r] + atomicAdd(&s_push[r], 1)) = v;
+            *ring_at(r, s_tail[r] + atomicAdd(&s_push[r], 1)) = near_entry(v, row);
             atomicAdd(&s_nn, 1);
         };
         // wavefront 0: tails of the rings for the pushes to come
@@ -1208,10 +1226,23 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                             const int mid = (lo + hi) >> 1;
                             if (s_tpre[mid] <= j) lo = mid; else hi = mid;
                         }
-                        const int w = *ring_at(lo, s_rhp[lo] + (j - s_tpre[lo]));
+                        const NearE qe = *ring_at(lo, s_rhp[lo] + (j - s_tpre[lo]));
+                        int w, e0;
+                        if constexpr (CT) {
+                            w = (int)qe.x;
+                            if (qe.y != kNoRow) {
+                                e0 = (int)(qe.y >> kRowCountBits);
+                                deg[u] = (int)(qe.y & ((1u << kRowCountBits) - 1u));
+                            } else {
+                                e0 = rptr[w];
+                                deg[u] = rptr[w + 1] - e0;
+                            }
+                        } else {
+                            w = qe;
+                            e0 = rptr[w];
+                            deg[u] = rptr[w + 1] - e0;
+                        }
                         const uint32_t lw = atomicOr(&D[w], kNotQueued);   // dequeue, read the label
-                        const int e0 = rptr[w];
-                        deg[u] = rptr[w + 1] - e0;
                         s_e0[j] = e0;
                         s_dw[j] = __uint_as_float(lw & kValueBits);
                     }
@@ -1266,6 +1297,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                                 const uint4 r = crec[e];
                                 const uint32_t form = r.x >> 30;
                                 vv[x] = (int)(r.x & 0x3fffffffu) - node0;
+                                s_row[x * NT + tid] = form != 2u ? r.w : kNoRow;   // the source's packed row
                                 if (form == 3u) {
                                     cd[x] = chain_fold(net.cbuf + r.y, s_dw[lo]);
                                 } else {
@@ -1288,10 +1320,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                     for (int x = 0; x < V; ++x) {
                         const uint32_t cb = __float_as_uint(cd[x]);
                         if (ok[x] && cb < cur[x] && (atomicMin(&D[vv[x]], cb) & kNotQueued)) {
+                            const uint32_t row = CT ? s_row[x * NT + tid] : kNoRow;
                             if (cd[x] < thr) {
-                                push_near(vv[x]);
+                                push_near(vv[x], row);
                             } else {
-                                farq[fcnt + atomicAdd(&s_fn, 1)] = make_uint2((uint32_t)vv[x], cb);
+                                farq[fcnt + atomicAdd(&s_fn, 1)] = far_entry((uint32_t)vv[x], cb, row);
                                 atomicMin(&s_fm, cb);
                             }
                         }
@@ -1326,12 +1359,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                     for (int i0 = 0; i0 < fcnt; i0 += NT) {
                         const int i = i0 + tid;
                         const bool h = i < fcnt;
-                        uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                        FarE ent = h ? farq[i] : far_entry(0u, kInfBits, kNoRow);
                         if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;   // the label now
                         const bool late = h && __uint_as_float(ent.y) < thr;
                         __syncthreads();                  // the chunk is read before it is overwritten
                         if (late) {
-                            push_near((int)ent.x);
+                            push_near((int)ent.x, far_row(ent));
                         } else if (h) {
                             farq[keep + atomicAdd(&s_fn, 1)] = ent;
                             atomicMin(&s_fm, ent.y);
@@ -1372,7 +1405,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
             for (int i0 = 0; i0 < fcnt; i0 += NT) {
                 const int i = i0 + tid;
                 const bool h = i < fcnt;
-                uint2 ent = h ? farq[i] : make_uint2(0u, kInfBits);
+                FarE ent = h ? farq[i] : far_entry(0u, kInfBits, kNoRow);
                 // key by the label now: a far node improved since its push keeps
                 // its queued flag and is not pushed again, and waiting for the
                 // threshold to pass its old label would make every node it
@@ -1380,7 +1413,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                 if (h) ent.y = ld_coherent(&D[ent.x]) & kValueBits;
                 __syncthreads();
                 if (h && __uint_as_float(ent.y) < thr) {
-                    push_near((int)ent.x);
+                    push_near((int)ent.x, far_row(ent));
                 } else if (h) {
                     farq[keep + atomicAdd(&s_fn, 1)] = ent;
                     atomicMin(&s_fm, ent.y);

@@ -81,6 +81,7 @@ struct qdta_ctx {
     int64_t Q = 0, P = 0, nmax = 0;
     int slots = 0, scr_slots = 0;
     int64_t scr_nmax = 0;
+    bool scr_wide = false;             // queues sized for the contracted search's entries
     size_t label_count = 0;
     DBuf<int32_t> dest_node, dest_inst, qptr, leg_orig, leg_q;
     DBuf<int64_t> dest_lab, leg_dfx;
@@ -557,6 +558,8 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
 // chain of one or two nodes (two or three costs inline), form 3 a longer
 // chain, whose second word is the offset of its cost block (count, then the
 // costs).  Inline costs spare the search a dependent read per relaxation.
+// The last word of forms 0, 1 and 3 holds the source's packed row
+// (pack_row), which the search queues with the node.
 // Words at most: one record per link at most (a chain's record stands for
 // two links or more), and per chain of k > 2 nodes two cost blocks of
 // ceil((k + 2) / 4) * 4 words, under 6 words per left-out node.
@@ -740,6 +743,9 @@ int build_contraction(qdta_ctx* c) {
     std::vector<uint32_t> cbuf(words, 0u);
     for (size_t k = 0; k < recs.size(); ++k) {
         const Rec& r = recs[k];
+        // the last word carries the source's packed row where no cost takes it
+        const uint32_t row = pack_row(crp[r.src], crp[r.src + 1] - crp[r.src]);
+        cbuf[4 * k + 3] = row;
         if (r.link >= 0) {
             cbuf[4 * k] = (uint32_t)r.src;
             cslot[r.link] = (int32_t)(4 * k + 1);
@@ -801,6 +807,12 @@ int ensure_contraction(qdta_ctx* c, const int32_t* roots, size_t nroots) {
 // before a search of the current demand's trees
 int ensure_contract(qdta_ctx* c, const qdta_opts* o) {
     if (!uses_contraction(o)) return QDTA_OK;
+    // queues sized for the other search's narrower entries: widen them in place
+    if (!c->scr_wide && c->scr_slots > 0) {
+        RC(dalloc(c, c->nearq, (size_t)c->scr_slots * (size_t)c->scr_nmax * 2));
+        RC(dalloc(c, c->farq, (size_t)c->scr_slots * (size_t)c->scr_nmax * 4));
+        c->scr_wide = true;
+    }
     return ensure_contraction(c, c->h_dest_node.data(), c->h_dest_node.size());
 }
 
@@ -811,19 +823,22 @@ int64_t tree_words(int64_t n) { return (n + 31) / 32 * 32; }
 // c->slots: wavefronts of a shortest-path launch (whole workgroups of four).
 // Scratch: one slot per tree in flight, i.e. per wavefront (tree_waves 1) or
 // per workgroup (tree_waves 4); launches never use more slots than exist.
-int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
+int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw, bool wide) {
     // every tree takes tw wavefronts; never more than wpc per CU
     int slots = (int)std::min<int64_t>(std::max<int64_t>(trees, 1) * (tw == 1 ? 1 : 4), (int64_t)c->cus * wpc);
     slots = (slots + 3) / 4 * 4;
     c->slots = slots;
     const int need = tw == 1 ? slots : slots / 4;
     nmax = std::max<int64_t>(nmax, 1) + 65;      // near rings: n queued nodes in n + (up to 64) slots
-    if (need > c->scr_slots || nmax > c->scr_nmax) {
+    // the contracted search's queue entries are twice as wide (see Scratch)
+    if (need > c->scr_slots || nmax > c->scr_nmax || (wide && !c->scr_wide)) {
         int64_t ns = std::max<int64_t>(need, c->scr_slots), nm = std::max<int64_t>(nmax, c->scr_nmax);
-        RC(dalloc(c, c->nearq, (size_t)ns * nm));
-        RC(dalloc(c, c->farq, (size_t)ns * nm * 2));
+        const bool w = wide || c->scr_wide;
+        RC(dalloc(c, c->nearq, (size_t)ns * nm * (w ? 2 : 1)));
+        RC(dalloc(c, c->farq, (size_t)ns * nm * (w ? 4 : 2)));
         c->scr_slots = (int)ns;
         c->scr_nmax = nm;
+        c->scr_wide = w;
     }
     RC(dalloc(c, c->work, 1));
     if (!c->sssp_stats.p) {
@@ -836,10 +851,10 @@ int ensure_scratch(qdta_ctx* c, int64_t trees, int64_t nmax, int wpc, int tw) {
 }
 
 // wpc = 0: the demand tables only (no shortest-path scratch).
-int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
+int ensure_demand(qdta_ctx* c, int wpc, int tw = 1, bool wide = false) {
     RC(ensure_network(c));
-    if (!c->dem_dirty) return wpc > 0 ? ensure_scratch(c, (int64_t)plan_dests(c, (size_t)c->Q), c->nmax, wpc, tw)
-                                      : QDTA_OK;
+    if (!c->dem_dirty)
+        return wpc > 0 ? ensure_scratch(c, (int64_t)plan_dests(c, (size_t)c->Q), c->nmax, wpc, tw, wide) : QDTA_OK;
     int64_t total_legs = 0;
     for (const Instance& I : c->inst) total_legs += (int64_t)I.orig.size();
     if (total_legs >= INT32_MAX) return set_err(c, QDTA_EARG, "total legs beyond int32 ids");
@@ -903,7 +918,7 @@ int ensure_demand(qdta_ctx* c, int wpc, int tw = 1) {
     RC(dalloc(c, c->absorb_q, pq));
     RC(dalloc(c, c->int_node, pp));
     RC(dalloc(c, c->int_tau, pp));
-    if (wpc > 0) RC(ensure_scratch(c, (int64_t)pq, nmax, wpc, tw));
+    if (wpc > 0) RC(ensure_scratch(c, (int64_t)pq, nmax, wpc, tw, wide));
     c->dem_dirty = false;
     c->solved = false;
     c->lab_hist_ok.clear();
@@ -1436,7 +1451,8 @@ int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int6
         slots = (slots + 3) / 4 * 4;
         const int64_t need = tw == 1 ? slots : slots / 4;
         const int64_t nm = std::max<int64_t>(nmax, 1) + 65;
-        add((size_t)(need * nm), 4); add((size_t)(need * nm * 2), 4);
+        const size_t qw = uses_contraction(o) || o->sssp_kernel == 0 ? 2 : 1;   // wider entries (Scratch)
+        add((size_t)(need * nm) * qw, 4); add((size_t)(need * nm * 2) * qw, 4);
         add(1, 4); add(2, 8); add(ni, 4); add(ni, 8);
     }
     if (o->keep_history) {
@@ -1678,7 +1694,9 @@ int qdta_trees(qdta_ctx* c, const qdta_opts* o, int32_t inst, const float* cost,
         if ((rc = dalloc(c, lab, (size_t)nq * tree_words(I.n)))) break;
         if ((rc = dalloc(c, aq, nq))) break;
         int saved_slots = c->slots;
-        if ((rc = ensure_scratch(c, nq, std::max<int64_t>(c->nmax, I.n), waves_per_cu(o), tree_waves(o)))) break;
+        if ((rc = ensure_scratch(c, nq, std::max<int64_t>(c->nmax, I.n), waves_per_cu(o), tree_waves(o),
+                                 uses_contraction(o))))
+            break;
         int slots = c->slots;
         c->slots = saved_slots;
         DemDev dem;
@@ -1725,7 +1743,7 @@ int qdta_aon(qdta_ctx* c, const qdta_opts* o, const float* cost, int64_t* y, int
     c->err.clear();
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!cost || !y) return set_err(c, QDTA_EARG, "null array");
-    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
+    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o), uses_contraction(o)));
     RC(apply_rule(c, o));
     RC(ensure_sweep(c, o));
     RC(ensure_contract(c, o));
@@ -1751,7 +1769,7 @@ int qdta_ls_eval(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const int64_
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (K < 1 || K > kMaxK || !f || !y || !alphas || !sums) return set_err(c, QDTA_EARG, "bad arguments");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o), tree_waves(o), uses_contraction(o)));
     int ni = (int)c->inst.size();
     RC(clear_flags(c));
     HIPCHECK(c, launch_fill_i64(c->stream, reinterpret_cast<int64_t*>(c->ls_acc.p), 0, (int64_t)ni * K * 6));
@@ -1796,7 +1814,7 @@ int qdta_line_search(qdta_ctx* c, const qdta_opts* o, const int64_t* f, const in
     if (!opts_ok(c, o)) return QDTA_EARG;
     if (!f || !y || !alpha_out || j < 1) return set_err(c, QDTA_EARG, "bad arguments");
     RC(ensure_network(c));
-    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
+    if (c->dem_dirty) RC(ensure_demand(c, waves_per_cu(o), tree_waves(o), uses_contraction(o)));
     int ni = (int)c->inst.size();
     RC(init_state(c, true, j));
     RC(clear_flags(c));
@@ -1824,7 +1842,7 @@ int qdta_fw_begin(qdta_ctx* c, const qdta_opts* o) {
     if (!opts_ok(c, o)) return QDTA_EARG;
     for (const Instance& I : c->inst)
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "every instance needs qdta_set_demand before solving");
-    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
+    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o), uses_contraction(o)));
     RC(apply_rule(c, o));
     RC(ensure_sweep(c, o));
     RC(ensure_contract(c, o));
@@ -2048,7 +2066,8 @@ int qdta_autotune(qdta_ctx* c, qdta_opts* o, double budget_ms, double* best_ms_o
     if (!(budget_ms > 0.0)) return set_err(c, QDTA_EARG, "budget_ms must be > 0");
     for (const Instance& I : c->inst)
         if (!I.has_demand) return set_err(c, QDTA_ESTATE, "autotune needs the demand of every instance");
-    RC(ensure_demand(c, waves_per_cu(o), 1));            // slots for either kernel form
+    RC(ensure_demand(c, waves_per_cu(o), 1,               // slots for either kernel form
+                     o->sssp_kernel == 0 || o->sssp_kernel == 4));
     RC(apply_rule(c, o));
     if (o->sssp_kernel == 0 || o->sssp_kernel == 4)       // trials of either tree form
         RC(ensure_contraction(c, c->h_dest_node.data(), c->h_dest_node.size()));
@@ -2420,7 +2439,7 @@ int qdta_adjoint_record(qdta_ctx* c, const qdta_opts* o) {
     const int J = I.solved_iters;
     if (J < 0 || (int)I.hist_alpha.size() < J + 1 || c->hist_iters_cap < (size_t)J + 1)
         return set_err(c, QDTA_ESTATE, "no iteration history");
-    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o)));
+    RC(ensure_demand(c, waves_per_cu(o), tree_waves(o), uses_contraction(o)));
     RC(apply_rule(c, o));
     RC(ensure_contract(c, o));
     const int64_t P = c->P, M = c->M;
