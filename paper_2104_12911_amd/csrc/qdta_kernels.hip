@@ -1080,11 +1080,17 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
     __shared__ int s_t, s_nn, s_fn;
     __shared__ uint32_t s_fm;
     __shared__ uint32_t s_row[CT ? NT * V : 1];   // each relaxation's source row, kept out of registers
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // queue entries: the node (near) and (node, label) (far); the contracted
     // search's also carry the node's packed row (kNoRow: read the row pointers)
     using NearE = typename std::conditional<CT, uint2, int32_t>::type;
     using FarE = typename std::conditional<CT, uint4, uint2>::type;
+    // The near entries one pushing phase makes go to an LDS buffer first (the
+    // next step pops them all, before the rings), and to the rings in HBM
+    // once it is full: s_bp counts the pushes since the last pop.
+    constexpr int NB = NP;
+    __shared__ NearE s_buf[NB];
+    __shared__ int s_bp;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     NearE* nearq = reinterpret_cast<NearE*>(scr.nearq) + (int64_t)blockIdx.x * scr.nmax;
     FarE* farq = reinterpret_cast<FarE*>(scr.farq) + (int64_t)blockIdx.x * scr.nmax;
     auto near_entry = [](int v, uint32_t row) -> NearE {
@@ -1136,6 +1142,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
             s_nn = 0;
             s_fn = 0;
             s_fm = kInfBits;
+            s_bp = 0;
         }
         __threadfence_block();
         __syncthreads();
@@ -1151,8 +1158,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
             return nearq + (int64_t)r * (rs + 1) + pos;
         };
         auto push_near = [&](int v, uint32_t row) {
-            const int r = v >> rsh;
-            *ring_at(r, s_tail[r] + atomicAdd(&s_push[r], 1)) = near_entry(v, row);
+            const int b = atomicAdd(&s_bp, 1);
+            if (b < NB) {
+                s_buf[b] = near_entry(v, row);
+            } else {
+                const int r = v >> rsh;
+                *ring_at(r, s_tail[r] + atomicAdd(&s_push[r], 1)) = near_entry(v, row);
+            }
             atomicAdd(&s_nn, 1);
         };
         // wavefront 0: tails of the rings for the pushes to come
@@ -1193,6 +1205,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
         for (;;) {
             while (ncnt > 0) {
                 const int k = ncnt < NP ? ncnt : NP;
+                // the buffer's entries first (all of them: kb <= k), then the
+                // lowest ranges' rings
+                const int kb = min(s_bp, NB);
                 if (wv == 0) {
                     const int rc = s_rc[lane], rh = s_rh[lane];
                     int incl = rc;
@@ -1201,9 +1216,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                         if (lane >= o) incl += x;
                     }
                     const int excl = incl - rc;
-                    const int take = max(0, min(rc, NP - excl));
+                    const int take = max(0, min(rc, NP - kb - excl));
                     const int cap = lane < nranges ? min(rs, n - lane * rs) + 1 : 1;
-                    s_tpre[lane] = min(excl, NP);
+                    s_tpre[lane] = min(excl, NP - kb);
                     s_rhp[lane] = rh;
                     int nh = rh + take;
                     if (nh >= cap) nh -= cap;
@@ -1215,18 +1230,25 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
                     s_push[lane] = 0;
                 }
                 __syncthreads();
+                if (tid == 0) s_bp = 0;               // every thread has read it; pushes come after barriers
                 int deg[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = u * NT + tid;
                     deg[u] = 0;
                     if (j < k) {
-                        int lo = 0, hi = 64;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (s_tpre[mid] <= j) lo = mid; else hi = mid;
+                        NearE qe;
+                        if (j < kb) {
+                            qe = s_buf[j];
+                        } else {
+                            const int jr = j - kb;
+                            int lo = 0, hi = 64;
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (s_tpre[mid] <= jr) lo = mid; else hi = mid;
+                            }
+                            qe = *ring_at(lo, s_rhp[lo] + (jr - s_tpre[lo]));
                         }
-                        const NearE qe = *ring_at(lo, s_rhp[lo] + (j - s_tpre[lo]));
                         int w, e0;
                         if constexpr (CT) {
                             w = (int)qe.x;
