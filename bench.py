@@ -83,8 +83,9 @@ def sssp_kernel_name(shape, tree_waves, kernel=1):
         return "k_sssp_wn<%d, %d>" % WN_SHAPES.get(shape, (2, 4))
     shape = shape if shape in WG_SHAPES else 3
     if kernel == 4:
-        # the <2, 4> form is instantiated with registers for 7 wavefronts per SIMD
-        return "k_sssp_wg<%d, %d, true%s>" % (WG_SHAPES[shape] + (", 7" if shape == 3 else "",))
+        # the <2, 4> form is instantiated with registers for 7 wavefronts per
+        # SIMD; the trees are complete after the chain fill that follows
+        return "k_sssp_wg<%d, %d, true%s> + k_chain_fill" % (WG_SHAPES[shape] + (", 7" if shape == 3 else "",))
     if (tree_waves or 4) == 1:
         return "k_sssp_ds<%d, %d>" % DS_SHAPES[shape]
     return "k_sssp_wg<%d, %d, false>" % WG_SHAPES[shape]
@@ -96,7 +97,8 @@ def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands, la
     each scaled by what the counter reads for the calibration add kernel
     (reads and writes calib_mib MiB once, run by --copy-calib-mib).  last > 0:
     only the kernel's last `last` dispatches (the timed steps of the peak
-    interval; earlier ones belong to the carried-in intervals)."""
+    interval; earlier ones belong to the carried-in intervals).  A kernel
+    named "A + B" is the sum of one launch of each."""
     import sqlite3
 
     def per_dispatch(db, counter):
@@ -112,18 +114,25 @@ def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands, la
 
     out = {"kernel": kernel, "calibration": {"kernel": f"torch.add of a {calib_mib} MiB float32 tensor (reads and "
                                                         f"writes {calib_mib} MiB once)"}}
+    parts = [k.strip() for k in kernel.split(" + ")]
     for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         acc, names = per_dispatch(db, counter)
-        ks = [acc[d] for d in sorted(acc) if kernel in names[d]]
-        if last > 0:
-            ks = ks[-last:]
         adds = [acc[d] for d in acc if "add" in names[d].lower() and "elementwise" in names[d].lower()]
-        if not ks or not adds:
-            raise SystemExit(f"{db}: no dispatch of {kernel} or of the calibration kernel")
+        per_launch, launches = 0.0, []
+        for part in parts:
+            ks = [acc[d] for d in sorted(acc) if part in names[d]]
+            if last > 0:
+                ks = ks[-last:]
+            if not ks:
+                raise SystemExit(f"{db}: no dispatch of {part}")
+            per_launch += sum(ks) / len(ks)
+            launches.append(len(ks))
+        if not adds:
+            raise SystemExit(f"{db}: no dispatch of the calibration kernel")
         cal = max(adds)
         scale = (calib_mib * 1024.0) / cal
-        out[f"{key}_kib_per_launch"] = sum(ks) / len(ks)
-        out[f"{key}_launches"] = len(ks)
+        out[f"{key}_kib_per_launch"] = per_launch
+        out[f"{key}_launches"] = launches[0] if len(launches) == 1 else launches
         out["calibration"][f"{key}_kib"] = cal
         out["calibration"][f"{key}_scale"] = scale
     out["bytes_per_launch"] = 1024.0 * (out["fetch_kib_per_launch"] * out["calibration"]["fetch_scale"] +
@@ -139,7 +148,8 @@ def reduce_traffic(fetch_db, write_db, kernel, calib_mib, out_path, commands, la
 def trace_summary(db, kernel, last):
     """Markdown summary of a rocprofv3 --kernel-trace database: every kernel's
     calls, total and mean duration and share of GPU time, then the mean
-    duration of `kernel`'s last `last` dispatches (the timed steps)."""
+    duration of `kernel`'s last `last` dispatches (the timed steps); for a
+    kernel named "A + B", of each part and their sum."""
     import sqlite3
     con = sqlite3.connect(db)
     rows = con.execute("select name, dispatch_id, duration from kernels").fetchall()
@@ -153,11 +163,18 @@ def trace_summary(db, kernel, last):
     for short, v in sorted(per.items(), key=lambda kv: -sum(d for _, d in kv[1]))[:12]:
         t = sum(d for _, d in v)
         lines.append(f"| `{short}` | {len(v)} | {t / 1e6:.1f} | {t / len(v) / 1e6:.3f} | {100.0 * t / total:.1f}% |")
-    ks = sorted(v for short, vv in per.items() if kernel in short for v in vv)
-    tail = [d for _, d in ks[-last:]] if last > 0 else [d for _, d in ks]
     lines.append("")
-    lines.append(f"`{kernel}`, last {len(tail)} dispatches (the timed steps): mean "
-                 f"{sum(tail) / max(len(tail), 1) / 1e6:.2f} ms, min {min(tail) / 1e6:.2f}, max {max(tail) / 1e6:.2f}")
+    mean_sum = 0.0
+    parts = [k.strip() for k in kernel.split(" + ")]
+    for part in parts:
+        ks = sorted(v for short, vv in per.items() if part in short for v in vv)
+        tail = [d for _, d in ks[-last:]] if last > 0 else [d for _, d in ks]
+        mean_sum += sum(tail) / max(len(tail), 1)
+        lines.append(f"`{part}`, last {len(tail)} dispatches (the timed steps): mean "
+                     f"{sum(tail) / max(len(tail), 1) / 1e6:.2f} ms, min {min(tail) / 1e6:.2f}, "
+                     f"max {max(tail) / 1e6:.2f}")
+    if len(parts) > 1:
+        lines.append(f"`{kernel}`: mean {mean_sum / 1e6:.2f} ms per launch of both")
     return "\n".join(lines)
 
 
@@ -578,7 +595,7 @@ def main():
     ap.add_argument("--reduce-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write profiles/sssp_traffic.json from two rocprofv3 --pmc databases (FETCH_SIZE, "
                          "WRITE_SIZE) of runs made with --copy-calib-mib, and exit")
-    ap.add_argument("--traffic-kernel", default="k_sssp_wg<2, 4, true, 7>",
+    ap.add_argument("--traffic-kernel", default="k_sssp_wg<2, 4, true, 7> + k_chain_fill",
                     help="kernel instantiation the traffic reduction averages")
     ap.add_argument("--traffic-commands", default="", help="the rocprofv3 commands, ' ;; '-separated, recorded")
     ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "sssp_traffic.json"))
@@ -715,8 +732,13 @@ def main():
         ctx.profile(False)
         prof["sssp"] = prof_d["sssp"]
         prof["walk"] = prof_d["walk"]
+        prof["fill"] = prof_d["fill"]
     sssp_ms, sssp_n = prof["sssp"]
     sssp_avg_s = sssp_ms / max(sssp_n, 1) / 1e3
+    # the contracted search's trees are complete after the chain fill
+    fill_ms, fill_n = prof["fill"]
+    if fill_n > 0:
+        sssp_avg_s += fill_ms / fill_n / 1e3
     bytes_launch = Q * sssp_bytes_per_tree(net.n, net.m) + 8.0 * net.m + 4.0 * net.n
     achieved = bytes_launch / sssp_avg_s / 1e9
     # the work the kernel counted over the timed steps: per launch, 8 bytes

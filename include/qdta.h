@@ -456,7 +456,8 @@ int qdta_autotune(qdta_ctx *ctx, qdta_opts *opts, double budget_ms, double *best
  * synchronisation.  Phases: 0 BPR costs, 1 shortest-path trees, 2 loading
  * walk (with the tie fallback), 3 gap sums and stop test, 4 line search,
  * 5 flow update, 6 a whole iteration replayed as a HIP graph (the phases
- * inside a graph are not timed separately).  qdta_profile_enable(ctx, 1) resets and starts the timers,
+ * inside a graph are not timed separately), 7 the labels of the nodes the
+ * chain-contracted search leaves out (filled after phase 1's search).  qdta_profile_enable(ctx, 1) resets and starts the timers,
  * 0 stops them; qdta_profile_read copies the totals (host output; synchronises).  The work
  * counters (sssp_nodes, sssp_links) add up over every shortest-path launch, graph replays
  * included, from the last qdta_profile_enable on. */

@@ -16,6 +16,7 @@ constexpr int kBlkMaxBits = 8192;
 // chain-contracted search: most nodes one chain holds (longer runs of
 // two-neighbour nodes are cut by keeping a node)
 constexpr int kChainMax = 8;
+constexpr int kFillChunk = 1024;         // chains per work item of the fill after the contracted search
 // A kept node's row of contracted records packed in one word, (first record
 // << 6) | count, carried by the records that name the node as their source
 // and by its queue entries so that a pop need not read the row pointers;
@@ -91,14 +92,16 @@ struct NetDev {
     // longer chain, holds the word offset of its cost block (count, then the
     // costs) instead; cslot[a] is the word that holds link a's cost (-1 none)
     const int32_t* crptr;    // [N+1]
-    uint32_t* cbuf;
-    const int32_t* cslot;    // [M]
+    uint32_t* cbuf;          // records, cost blocks, then the chains' fill blocks
+    const int2* cslot;       // [M] (record word, fill word) holding link a's cost, -1 none
     const uint2* anc;        // [N] nodes whose labels must be final before the node's own is (itself if kept)
     const int32_t* inst_chain;// [ninst+1] chains of each instance
-    const int32_t* ch_ptr;   // [C+1] first node of each chain in ch_node
-    const int2* ch_end;      // [C] kept ends (u, v): u next to the chain's first node, v next to its last
-    const int32_t* ch_node;  // chain nodes, u to v
-    const int2* ch_link;     // per chain node: (link to the next node toward v, link to the previous toward u), -1 none
+    // [C] chain headers (u, v, k, word offset in cbuf of the fill block), u
+    // next to the chain's first node and v next to its last; the block holds
+    // per chain node its id, the cost of its link toward v and of its link
+    // toward u (+inf bits where the link is missing)
+    const int4* ch_hdr;
+    int32_t fill_chunks;     // most chunks of kFillChunk chains in one instance
     const int32_t* blk_inst; // [nblk] instance of each link chunk
     const int32_t* blk_start;// [nblk] first global link of each chunk
     int32_t ninst, nblk;
@@ -194,12 +197,16 @@ hipError_t launch_cslot_init(hipStream_t s, const NetDev& net);
 
 hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, double delta_scale, float* delta_inst,
                         double* logsum);
+// The contracted search's trees (variant >= 32) are complete only after
+// launch_chain_fill of the same trees; fill = true launches it right after.
 hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, const uint2* radj, label_t* labels,
                         const Scratch& scr, int slots, const InstState* st, const float* delta_inst, int variant,
-                        int early, int t_begin, int t_end);
+                        int early, int t_begin, int t_end, bool fill = true);
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst, double* logsum, int variant, int early);
+                       float* delta_inst, double* logsum, int variant, int early, bool fill = true);
+hipError_t launch_chain_fill(hipStream_t s, const NetDev& net, const DemDev& dem, label_t* labels,
+                             const InstState* st, int t_begin, int t_end);
 
 // time_cost NULL: the trees' own costs (held in the forward records)
 // Legs the link-progress rule leaves on a link (residual mode): appended as

@@ -197,8 +197,9 @@ __global__ __launch_bounds__(kWG) void k_bpr(NetDev net, const int64_t* __restri
             radj[net.revpos[a]].y = __float_as_uint(c32);
             net.fadj[a].y = __float_as_uint(c32);
             if (net.cbuf) {
-                const int w = net.cslot[a];
-                if (w >= 0) net.cbuf[w] = __float_as_uint(c32);
+                const int2 w = net.cslot[a];
+                if (w.x >= 0) net.cbuf[w.x] = __float_as_uint(c32);
+                if (w.y >= 0) net.cbuf[w.y] = __float_as_uint(c32);
             }
         }
     }
@@ -607,8 +608,9 @@ __global__ __launch_bounds__(kWG) void k_scatter_rcost(NetDev net, const float* 
         radj[net.revpos[a]].y = __float_as_uint(cost[a]);
         net.fadj[a].y = __float_as_uint(cost[a]);
         if (net.cbuf) {
-            const int w = net.cslot[a];
-            if (w >= 0) net.cbuf[w] = __float_as_uint(cost[a]);
+            const int2 w = net.cslot[a];
+            if (w.x >= 0) net.cbuf[w.x] = __float_as_uint(cost[a]);
+            if (w.y >= 0) net.cbuf[w.y] = __float_as_uint(cost[a]);
         }
     }
 }
@@ -621,8 +623,9 @@ hipError_t launch_scatter_rcost(hipStream_t s, const NetDev& net, const float* c
 
 __global__ __launch_bounds__(kWG) void k_cslot_init(NetDev net) {
     for (int64_t a = blockIdx.x * (int64_t)kWG + threadIdx.x; a < net.M; a += (int64_t)gridDim.x * kWG) {
-        const int w = net.cslot[a];
-        if (w >= 0) net.cbuf[w] = net.fadj[a].y;
+        const int2 w = net.cslot[a];
+        if (w.x >= 0) net.cbuf[w.x] = net.fadj[a].y;
+        if (w.y >= 0) net.cbuf[w.y] = net.fadj[a].y;
     }
 }
 
@@ -1011,41 +1014,6 @@ __device__ __forceinline__ float chain_fold(const uint32_t* __restrict__ blk, fl
     return d;
 }
 
-// Labels of the chain nodes of one tree from its chain ends' labels (after
-// the search): for chain node x_j, the fold from v through x_k..x_j and the
-// fold from u through x_1..x_j, each only over links that exist, and the
-// lesser of the two.  Bouncing inside a chain never beats this, since each
-// addition of a non-negative cost keeps or raises a value.
-__device__ __forceinline__ void chain_fill(const NetDev& net, label_t* D, int node0, int inst, int tid, int nt) {
-    const int c1 = net.inst_chain[inst + 1];
-    for (int ch = net.inst_chain[inst] + tid; ch < c1; ch += nt) {
-        const int2 uv = net.ch_end[ch];
-        const float du = __uint_as_float(ld_coherent(&D[uv.x - node0]) & kValueBits);
-        const float dv = __uint_as_float(ld_coherent(&D[uv.y - node0]) & kValueBits);
-        if (!(du < __uint_as_float(kInfBits)) && !(dv < __uint_as_float(kInfBits))) continue;
-        const int j0 = net.ch_ptr[ch], k = net.ch_ptr[ch + 1] - j0;
-        float lv[kChainMax];
-        float l = du;
-#pragma unroll
-        for (int j = 0; j < kChainMax; ++j) {
-            if (j < k) {
-                const int e = net.ch_link[j0 + j].y;
-                l = e >= 0 ? l + __uint_as_float(net.fadj[e].y) : __uint_as_float(kInfBits);
-                lv[j] = l;
-            }
-        }
-        float r = dv;
-#pragma unroll
-        for (int j = kChainMax - 1; j >= 0; --j) {
-            if (j < k) {
-                const int e = net.ch_link[j0 + j].x;
-                r = e >= 0 ? r + __uint_as_float(net.fadj[e].y) : __uint_as_float(kInfBits);
-                D[net.ch_node[j0 + j] - node0] = kNotQueued | __float_as_uint(fminf(lv[j], r));
-            }
-        }
-    }
-}
-
 // Workgroup-per-tree form of the same delta-stepping: the four wavefronts of
 // a workgroup grow one tree together, popping up to 256 U nodes per step
 // from the lowest node-id ranges, so a quarter as many trees are in flight
@@ -1058,8 +1026,8 @@ __device__ __forceinline__ void chain_fill(const NetDev& net, label_t* D, int no
 // CT: the chain-contracted search.  Nodes left out by the contraction are
 // never queued; the kept nodes' in-links come from the contracted records
 // (a chain's record adds its link costs one at a time); a leg whose origin
-// is left out waits for the kept nodes its label depends on; after the
-// search the chain nodes' labels are filled from their chains' ends.
+// is left out waits for the kept nodes its label depends on; the chain
+// nodes' labels are filled from their chains' ends afterwards (k_chain_fill).
 //
 // W: wavefronts per SIMD the register allocation leaves room for (1: the
 // compiler's choice).  The contracted <2, 4> form fits 7 in 72 VGPRs with no
@@ -1461,10 +1429,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(W))) void k
             __syncthreads();
             fcnt = keep;
             fmin = km;
-        }
-        if (CT) {
-            __syncthreads();
-            chain_fill(net, D, node0, inst, tid, NT);
         }
         __syncthreads();
     }
@@ -2238,9 +2202,85 @@ hipError_t launch_delta(hipStream_t s, const NetDev& net, const float* cost, dou
     return hipGetLastError();
 }
 
+// Labels of the chain nodes left out of the contracted search, from their
+// chains' ends: for chain node x_j, the FP32 fold from v through x_k..x_j
+// and the fold from u through x_1..x_j (each over links that exist: a
+// missing link's +inf cost stops the fold), and the lesser of the two.
+// Turning back inside a chain never beats this, since each addition of a
+// non-negative cost keeps or raises a value.  Work item (r, t): chunk r of
+// kFillChunk chains of tree t's instance, kFillPer per thread with their
+// header and end-label loads in flight together; items run chunk by chunk,
+// so the trees in flight share the chunk's headers and blocks in the cache.
+constexpr int kFillPer = kFillChunk / kWG;
+__global__ __launch_bounds__(kWG) void k_chain_fill(NetDev net, DemDev dem, label_t* labels, const InstState* st,
+                                                    int t_begin, int t_end) {
+    const int64_t nq = t_end - t_begin;
+    const int64_t items = (int64_t)net.fill_chunks * nq;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int r = (int)(it / nq);
+        const int t = t_begin + (int)(it - (int64_t)r * nq);
+        const int inst = dem.dest_inst[t];
+        if (!inst_live(st, inst)) continue;
+        const int cb = net.inst_chain[inst] + r * kFillChunk;
+        const int ce = min(net.inst_chain[inst + 1], cb + kFillChunk);
+        if (cb >= ce) continue;
+        label_t* D = labels + dem.dest_lab[t];
+        const int node0 = net.inst[inst].node0;
+        // loads with in-range indices whether or not the slot has a chain, so
+        // that none of them waits on a branch
+        int4 h[kFillPer];
+        bool ok[kFillPer];
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            const int ch = cb + q * kWG + (int)threadIdx.x;
+            ok[q] = ch < ce;
+            h[q] = net.ch_hdr[min(ch, ce - 1)];
+        }
+        uint32_t wu[kFillPer], wv[kFillPer];
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            wu[q] = D[h[q].x - node0];
+            wv[q] = D[h[q].y - node0];
+        }
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            const float du = __uint_as_float(wu[q] & kValueBits), dv = __uint_as_float(wv[q] & kValueBits);
+            if (!ok[q] || (!(du < __uint_as_float(kInfBits)) && !(dv < __uint_as_float(kInfBits)))) continue;
+            const uint32_t* blk = net.cbuf + h[q].w;
+            const int k = h[q].z;
+            float lv[kChainMax];
+            float l = du;
+#pragma unroll
+            for (int j = 0; j < kChainMax; ++j) {
+                if (j < k) {
+                    l = l + __uint_as_float(blk[3 * j + 2]);
+                    lv[j] = l;
+                }
+            }
+            float rv = dv;
+#pragma unroll
+            for (int j = kChainMax - 1; j >= 0; --j) {
+                if (j < k) {
+                    rv = rv + __uint_as_float(blk[3 * j + 1]);
+                    D[(int)blk[3 * j] - node0] = kNotQueued | __float_as_uint(fminf(lv[j], rv));
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_chain_fill(hipStream_t s, const NetDev& net, const DemDev& dem, label_t* labels,
+                             const InstState* st, int t_begin, int t_end) {
+    const int64_t items = (int64_t)net.fill_chunks * (t_end - t_begin);
+    if (items <= 0 || !net.cbuf) return hipSuccess;
+    hipLaunchKernelGGL(k_chain_fill, dim3((unsigned)std::min<int64_t>(items, 4096)), dim3(kWG), 0, s, net, dem, labels,
+                       st, t_begin, t_end);
+    return hipGetLastError();
+}
+
 hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, const uint2* radj, label_t* labels,
                         const Scratch& scr, int slots, const InstState* st, const float* delta_inst, int variant,
-                        int early, int t_begin, int t_end) {
+                        int early, int t_begin, int t_end, bool fill) {
     if (t_end <= t_begin) return hipSuccess;
     hipError_t e = launch_fill_u32(s, reinterpret_cast<uint32_t*>(scr.work), 0u, 1);
     if (e != hipSuccess) return e;
@@ -2266,7 +2306,9 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
             default: QDTA_SSSP_CT(4, 2); break;
         }
 #undef QDTA_SSSP_CT
-        return hipGetLastError();
+        e = hipGetLastError();
+        if (e != hipSuccess || !fill) return e;
+        return launch_chain_fill(s, net, dem, labels, st, t_begin, t_end);   // the left-out chain nodes
     }
     if (variant >= 24) {
         // one workgroup per tree, every thread relaxing its own nodes' in-links
@@ -2342,11 +2384,11 @@ hipError_t launch_trees(hipStream_t s, const NetDev& net, const DemDev& dem, con
 
 hipError_t launch_sssp(hipStream_t s, const NetDev& net, const DemDev& dem, const float* cost, const uint2* radj,
                        label_t* labels, const Scratch& scr, int slots, const InstState* st, double delta_scale,
-                       float* delta_inst, double* logsum, int variant, int early) {
+                       float* delta_inst, double* logsum, int variant, int early, bool fill) {
     if (dem.Q == 0) return hipSuccess;
     hipError_t e = launch_delta(s, net, cost, delta_scale, delta_inst, logsum);
     if (e != hipSuccess) return e;
-    return launch_trees(s, net, dem, radj, labels, scr, slots, st, delta_inst, variant, early, 0, dem.Q);
+    return launch_trees(s, net, dem, radj, labels, scr, slots, st, delta_inst, variant, early, 0, dem.Q, fill);
 }
 
 // ---------------------------------------------------------------------------

@@ -107,10 +107,12 @@ struct qdta_ctx {
     std::vector<uint8_t> croot, cleft;   // nodes kept as roots; nodes the search leaves out
     bool c_built = false;
     int64_t c_chains = 0, c_left = 0;
-    DBuf<int32_t> crptr, cslot, ch_ptr, ch_node, inst_chain;
+    DBuf<int32_t> crptr, inst_chain;
+    DBuf<int4> ch_hdr;
     DBuf<uint32_t> cbuf;
     DBuf<uint2> anc;
-    DBuf<int2> ch_end, ch_link;
+    DBuf<int2> cslot;
+    int32_t c_fill_chunks = 0;         // most chain chunks of one instance (k_chain_fill items)
 
     // Frank-Wolfe state
     DBuf<int64_t> f, y;
@@ -526,10 +528,8 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
     v.cslot = ct ? c->cslot.p : nullptr;
     v.anc = ct ? c->anc.p : nullptr;
     v.inst_chain = ct ? c->inst_chain.p : nullptr;
-    v.ch_ptr = ct ? c->ch_ptr.p : nullptr;
-    v.ch_end = ct ? c->ch_end.p : nullptr;
-    v.ch_node = ct ? c->ch_node.p : nullptr;
-    v.ch_link = ct ? c->ch_link.p : nullptr;
+    v.ch_hdr = ct ? c->ch_hdr.p : nullptr;
+    v.fill_chunks = ct ? c->c_fill_chunks : 0;
     v.blk_inst = c->blk_inst.p;
     v.blk_start = c->blk_start.p;
     v.ninst = (int32_t)c->inst.size();
@@ -560,17 +560,23 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
 // costs).  Inline costs spare the search a dependent read per relaxation.
 // The last word of forms 0, 1 and 3 holds the source's packed row
 // (pack_row), which the search queues with the node.
+// After the records and cost blocks, one fill block per chain: per chain
+// node x1..xk its id, the cost of its link toward v and of its link toward u
+// (+inf bits where the link is missing); the chain's header (u, v, k, word
+// offset of the block) is in ch_hdr.  k_chain_fill labels the chain nodes.
 // Words at most: one record per link at most (a chain's record stands for
-// two links or more), and per chain of k > 2 nodes two cost blocks of
-// ceil((k + 2) / 4) * 4 words, under 6 words per left-out node.
+// two links or more), per chain of k > 2 nodes two cost blocks of
+// ceil((k + 2) / 4) * 4 words (under 6 words per left-out node), and per
+// chain a fill block of 3k words.
 constexpr int kInlineCosts = 3;
-size_t contraction_words(int64_t N, int64_t M) { return 4 * (size_t)M + 4 + 8 * (size_t)N; }
+size_t contraction_words(int64_t N, int64_t M) { return 4 * (size_t)M + 4 + 9 * (size_t)N; }
 
 int build_contraction(qdta_ctx* c) {
     const int64_t N = c->N;
     if (N >= (int64_t)1 << 30) return set_err(c, QDTA_EARG, "the contracted search takes fewer than 2^30 nodes");
     const int ni = (int)c->inst.size();
-    std::vector<int32_t> crp(N + 1, 0), cslot(c->M, -1), ch_ptr{0}, ch_node, inst_chain(ni + 1, 0);
+    std::vector<int32_t> crp(N + 1, 0), ch_ptr{0}, ch_node, inst_chain(ni + 1, 0);
+    std::vector<int2> cslot(c->M, make_int2(-1, -1));   // (record word, fill word) holding each link's cost
     std::vector<int2> ch_end, ch_link;
     std::vector<uint2> anc(N);
     for (int64_t v = 0; v < N; ++v) anc[v] = make_uint2((uint32_t)v, (uint32_t)v);
@@ -748,22 +754,49 @@ int build_contraction(qdta_ctx* c) {
         cbuf[4 * k + 3] = row;
         if (r.link >= 0) {
             cbuf[4 * k] = (uint32_t)r.src;
-            cslot[r.link] = (int32_t)(4 * k + 1);
+            cslot[r.link].x = (int32_t)(4 * k + 1);
             continue;
         }
         const std::vector<int32_t>& ls = sc_links[r.chain];
         if (ls.size() <= (size_t)kInlineCosts) {
             cbuf[4 * k] = (uint32_t)r.src | (uint32_t)(ls.size() - 1) << 30;
-            for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]] = (int32_t)(4 * k + 1 + j);
+            for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]].x = (int32_t)(4 * k + 1 + j);
         } else {
             const size_t b = blk[r.chain];
             cbuf[4 * k] = (uint32_t)r.src | 3u << 30;
             cbuf[4 * k + 1] = (uint32_t)b;
             cbuf[b] = (uint32_t)ls.size();
-            for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]] = (int32_t)(b + 1 + j);
+            for (size_t j = 0; j < ls.size(); ++j) cslot[ls[j]].x = (int32_t)(b + 1 + j);
         }
     }
+    // fill blocks and chain headers
+    const size_t nch = ch_end.size();
+    std::vector<int4> ch_hdr(nch);
+    for (size_t ch = 0; ch < nch; ++ch) {
+        const int k = ch_ptr[ch + 1] - ch_ptr[ch];
+        ch_hdr[ch] = make_int4(ch_end[ch].x, ch_end[ch].y, k, (int32_t)std::min(words, (size_t)INT32_MAX));
+        words += 3 * (size_t)k;
+    }
     if (words >= (size_t)INT32_MAX) return set_err(c, QDTA_EARG, "contracted records beyond int32 offsets");
+    cbuf.resize(words, 0u);
+    for (size_t ch = 0; ch < nch; ++ch) {
+        const size_t b = (size_t)ch_hdr[ch].w;
+        const int j0 = ch_ptr[ch], k = ch_ptr[ch + 1] - j0;
+        for (int j = 0; j < k; ++j) {
+            const size_t q = b + 3 * (size_t)j;
+            cbuf[q] = (uint32_t)ch_node[j0 + j];
+            const int2 lk = ch_link[j0 + j];
+            cbuf[q + 1] = kInfBits;               // a missing link stops the fold
+            cbuf[q + 2] = kInfBits;
+            if (lk.x >= 0) cslot[lk.x].y = (int32_t)(q + 1);
+            if (lk.y >= 0) cslot[lk.y].y = (int32_t)(q + 2);
+        }
+    }
+    c->c_fill_chunks = 0;
+    for (int i = 0; i < ni; ++i) {
+        const int32_t chunks = (inst_chain[i + 1] - inst_chain[i] + kFillChunk - 1) / kFillChunk;
+        c->c_fill_chunks = std::max(c->c_fill_chunks, chunks);
+    }
     c->c_chains = (int64_t)ch_end.size();
     c->c_left = (int64_t)ch_node.size();
     c->cleft.assign(N, 0);
@@ -775,10 +808,7 @@ int build_contraction(qdta_ctx* c) {
     RC(upload(c, c->cbuf, cbuf, ws ? contraction_words(N, c->M) : 0));
     RC(upload(c, c->cslot, cslot));
     RC(upload(c, c->anc, anc));
-    RC(upload(c, c->ch_ptr, ch_ptr, ws ? (size_t)N + 1 : 0));
-    RC(upload(c, c->ch_end, ch_end, ws ? (size_t)N : 0));
-    RC(upload(c, c->ch_node, ch_node, ws ? (size_t)N : 0));
-    RC(upload(c, c->ch_link, ch_link, ws ? (size_t)N : 0));
+    RC(upload(c, c->ch_hdr, ch_hdr, ws ? (size_t)N : 0));
     RC(upload(c, c->inst_chain, inst_chain));
     c->c_built = true;
     c->gen++;
@@ -990,8 +1020,8 @@ int read_flags(qdta_ctx* c, int* h) {
     return QDTA_OK;
 }
 
-constexpr int kPhases = 7;
-enum { PH_BPR = 0, PH_SSSP = 1, PH_WALK = 2, PH_GAP = 3, PH_LS = 4, PH_UPDATE = 5, PH_GRAPH = 6 };
+constexpr int kPhases = 8;
+enum { PH_BPR = 0, PH_SSSP = 1, PH_WALK = 2, PH_GAP = 3, PH_LS = 4, PH_UPDATE = 5, PH_GRAPH = 6, PH_FILL = 7 };
 
 // Record the start (edge 0) or end (edge 1) of a phase on the stream.
 int prof_mark(qdta_ctx* c, int ph, int edge) {
@@ -1053,12 +1083,17 @@ int aon_core(qdta_ctx* c, const qdta_opts* o, const float* cost, const float* ti
         HIPCHECK(c, launch_delta(c->stream, net, cost, delta_scale(o), c->delta_inst.p, c->logsum.p));
         for (int64_t t = 0; t < c->Q; ++t)
             HIPCHECK(c, launch_trees(c->stream, net, dem, c->radj.p, c->labels.p, scr_view(c), 4, st, c->delta_inst.p,
-                                     sssp_variant(c, o), 1, (int)t, (int)t + 1));
+                                     sssp_variant(c, o), 1, (int)t, (int)t + 1, false));
     } else {
         HIPCHECK(c, launch_sssp(c->stream, net, dem, cost, c->radj.p, c->labels.p, scr_view(c), c->slots, st,
-                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(c, o), 1));
+                                delta_scale(o), c->delta_inst.p, c->logsum.p, sssp_variant(c, o), 1, false));
     }
     if (marks) RC(prof_mark(c, PH_SSSP, 1));
+    if (sssp_variant(c, o) >= 32) {   // the contracted search's left-out chain nodes, timed apart
+        if (marks) RC(prof_mark(c, PH_FILL, 0));
+        HIPCHECK(c, launch_chain_fill(c->stream, net, dem, c->labels.p, st, 0, (int)c->Q));
+        if (marks) RC(prof_mark(c, PH_FILL, 1));
+    }
     if (marks) RC(prof_mark(c, PH_WALK, 0));
     HIPCHECK(c, launch_fill_i64(c->stream, y, 0, c->M));
     HIPCHECK(c, launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(c->absorb_q.p), 0u, c->Q));
@@ -1440,8 +1475,8 @@ int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int6
     add(labels, 4); add(pq, 4); add(pp, 4); add(pp, 4);
     if (o->load_form == 2) { add(labels, 4); add(labels, 8); }   // plain-interval loading by merged paths
     if (uses_contraction(o)) {                                    // chain contraction (at its bounds)
-        add(N + 1, 4); add(contraction_words(N, M), 4); add(M, 4); add(N, 8);
-        add(N + 1, 4); add(N, 8); add(N, 4); add(N, 8); add(ni + 1, 4);
+        add(N + 1, 4); add(contraction_words(N, M), 4); add(M, 8); add(N, 8);
+        add(N, 16); add(ni + 1, 4);
     }
     // shortest-path scratch (as ensure_scratch sizes it)
     {

@@ -32,7 +32,7 @@ EXPORTS = [
     "qdta_profile_enable", "qdta_profile_read", "qdta_autotune", "qdta_workspace_query", "qdta_bind_workspace",
     "qdta_alloc_count", "qdta_ls_eval_noalloc",
 ]
-PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration"]
+PHASES = ["bpr", "sssp", "walk", "gap", "line_search", "update", "graph_iteration", "fill"]
 
 
 class Opts(C.Structure):
