@@ -2497,8 +2497,10 @@ constexpr int kWalkLegsPerThread = 4;
 // Loads of a workgroup's legs are summed per link in an LDS table first
 // (legs of one destination share links); the table is added to y when the
 // workgroup is done, and a load whose probes find no slot goes to y directly.
-// Integer sums: the order does not change them.
-constexpr int kWalkSlots = 2048;
+// Integer sums: the order does not change them.  4,096 slots (48 KB, three
+// workgroups per CU): a workgroup's 1,024 legs load more distinct links than
+// 2,048 slots hold, and 8,192 leave one workgroup per CU.
+constexpr int kWalkSlots = 4096;
 
 __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const label_t* __restrict__ labels,
                                               const float* __restrict__ time_cost, const InstState* st,
@@ -2511,7 +2513,7 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
     }
     __syncthreads();
     auto load = [&](int e, int64_t d) {
-        int h = (int)(((unsigned)e * 2654435761u) >> 21) & (kWalkSlots - 1);
+        int h = (int)(((unsigned)e * 2654435761u) >> 20) & (kWalkSlots - 1);
         for (int probe = 0; probe < 4; ++probe) {
             int k = s_key[h];
             if (k == -1) k = atomicCAS(&s_key[h], -1, e);
