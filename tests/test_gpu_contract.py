@@ -5,9 +5,11 @@ everything the oracle computes over the whole network -- FP32 distances and
 successor links of every node, loads, stop nodes, flows -- must come out bit
 for bit: on hand-made chains (two-way, one-way, broken in either direction,
 loops back to one node, runs longer than one chain, rings with no kept
-node), random sparse graphs with ties and FP32 absorption, the grid, the
-metro networks and the 1.0M-link peak interval; with legs starting on
-left-out nodes; and after the destinations change."""
+node), a hub whose record row is too long to pack into its queue entries
+and whose pop queues more near entries than the LDS buffer holds, random
+sparse graphs with ties and FP32 absorption, the grid, the metro networks
+and the 1.0M-link peak interval; with legs starting on left-out nodes; and
+after the destinations change."""
 from __future__ import annotations
 
 import numpy as np
@@ -122,6 +124,38 @@ def test_contract_trees_sparse_random(q, orc, costs):
         dests = sorted(set(rng.integers(0, n, 3).tolist()))
         D, S, _ = _trees(q, net, net.fftt, dests, ds=0.7)
         _check(orc, net, net.fftt, dests, D, S)
+
+
+def _hub_net(rng, k, costs):
+    """Hub 0 linked both ways to spokes 1..k, the spokes in a two-way ring
+    (three neighbours each, so all are kept), and every seventh spoke with a
+    two-way run of three two-neighbour nodes to the next spoke: the hub's
+    row holds k records (too many to pack, so its pops read the row
+    pointers), and popping it queues k spokes in one step (more than the
+    LDS buffer of near entries holds when the bucket takes them all)."""
+    edges = []
+    for i in range(1, k + 1):
+        edges += [(0, i), (i, 0)]
+        j = i % k + 1
+        edges += [(i, j), (j, i)]
+    n = k + 1
+    for i in range(1, k + 1, 7):
+        a, b, c = n, n + 1, n + 2
+        n += 3
+        j = i % k + 1
+        edges += [(i, a), (a, i), (a, b), (b, a), (b, c), (c, b), (c, j), (j, c)]
+    return _net(n, edges, rng, costs)
+
+
+@pytest.mark.parametrize("costs", ["float", "int"])
+@pytest.mark.parametrize("ds", [0.3, 1e30])
+def test_contract_trees_hub_unpacked_row_and_buffer_overflow(q, orc, costs, ds):
+    rng = np.random.default_rng(4242)
+    k = 700
+    net = _hub_net(rng, k, costs)
+    dests = [5, 0, 350, k + 2]          # spokes, the hub, a run node (kept as a root)
+    D, S, _ = _trees(q, net, net.fftt, dests, ds=ds)
+    _check(orc, net, net.fftt, dests, D, S)
 
 
 @pytest.mark.parametrize("ds", [0.05, 1.0, 40.0])
