@@ -84,6 +84,7 @@ struct NetDev {
     const int32_t* rlink;    // [M]   global link id of each in-link
     const int32_t* revpos;   // [M]   position of link a in the reverse arrays
     uint2* fadj;             // [M]   forward records (head, cost bits): the costs the trees are grown with
+    const uint32_t* frow;    // [M]   the head's forward row packed as pack_row does (first link, count)
     const InstDev* inst;     // [ninst]
     // chain contraction (NULL until built): the search's reverse CSR over the
     // kept nodes, whose records are 4 words: source | form << 30, then the

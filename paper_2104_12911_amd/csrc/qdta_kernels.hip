@@ -2426,6 +2426,50 @@ __device__ __forceinline__ int succ_rec(const NetDev& net, const label_t* lab, i
     return -1;
 }
 
+// The same successor as succ_rec, for a walk that carries u's forward row
+// packed (kNoRow: read the row pointers): the row's records with their
+// heads' packed rows, then the heads' labels, are loaded four at a time
+// together (indices past the row's end repeat its last link), and the
+// lowest tight strict link wins as before.  Also returns the head's packed
+// row and label for the next hop.
+__device__ __forceinline__ int succ_row(const NetDev& net, const label_t* lab, int node0, int u, uint32_t row,
+                                        float du, int& head, float& cost, uint32_t& head_row, float& head_lab) {
+    int e0, deg;
+    if (row != kNoRow) {
+        e0 = (int)(row >> kRowCountBits);
+        deg = (int)(row & ((1u << kRowCountBits) - 1u));
+    } else {
+        e0 = net.row_ptr[u];
+        deg = net.row_ptr[u + 1] - e0;
+    }
+    const int last = e0 + deg - 1;
+    for (int b = 0; b < deg; b += 4) {
+        uint2 r[4];
+        uint32_t fr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = min(e0 + b + j, last);
+            r[j] = net.fadj[e];
+            fr[j] = net.frow[e];
+        }
+        float dw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dw[j] = lab_val(lab, (int)r[j].x - node0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float c = __uint_as_float(r[j].y);
+            if (b + j < deg && dw[j] < du && dw[j] + c == du) {
+                head = (int)r[j].x;
+                cost = c;
+                head_row = fr[j];
+                head_lab = dw[j];
+                return e0 + b + j;
+            }
+        }
+    }
+    return -1;
+}
+
 struct WalkOut {
     int64_t* y;
     int32_t* stop;
@@ -2550,11 +2594,13 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
         if (I.rule == RULE_PROGRESS && tau >= I.dt32) {
             delay = progress_delay(tau - I.dt32, I.pq);   // still on its way to its origin
         } else {
+            uint32_t urow = kNoRow;                   // u's forward row, carried from the link into u
             for (int hops = 0; u != q; ++hops) {
                 if (stop_at_node(I.rule, tau, I.dt32)) break;
                 int head = 0;
-                float ce = 0.0f;
-                const int e = succ_rec(net, lab, node0, u, du, head, ce);
+                float ce = 0.0f, hlab = 0.0f;
+                uint32_t hrow = kNoRow;
+                const int e = succ_row(net, lab, node0, u, urow, du, head, ce, hrow, hlab);
                 if (e < 0 || hops > I.n) {            // absorption: finish in the fallback
                     fl.int_node[l] = u;
                     fl.int_tau[l] = tau;
@@ -2568,7 +2614,8 @@ __global__ __launch_bounds__(kWG) void k_walk(NetDev net, DemDev dem, const labe
                 if (!o.residual_mode) load(e, d);
                 tau = nt;
                 u = head;
-                du = lab_val(lab, u - node0);
+                urow = hrow;
+                du = hlab;
                 if (I.rule == RULE_PROGRESS && tau > I.dt32) {
                     if (u != q) delay = progress_delay(tau - I.dt32, I.pq);
                     break;

@@ -119,6 +119,7 @@ struct qdta_ctx {
     DBuf<float> cost, cfin, tcost;    // routing costs, final times, travel times (system optimum)
     DBuf<uint2> radj;             // reverse adjacency records (source node, cost)
     DBuf<uint2> fadj;             // forward link records (head node, cost)
+    DBuf<uint32_t> frow;          // per link its head's forward row, packed (pack_row)
     DBuf<InstState> st;
     DBuf<long long> acc, ls_acc;
     DBuf<double> alphas, alpha_arr;
@@ -478,12 +479,15 @@ int ensure_network(qdta_ctx* c) {
     RC(dalloc(c, c->cost, c->M));
     {
         std::vector<uint2> ra(c->M), fa(c->M);
+        std::vector<uint32_t> fr(c->M);
         for (int64_t k = 0; k < c->M; ++k) {
             ra[k] = make_uint2((uint32_t)rsrc[k], 0u);
             fa[k] = make_uint2((uint32_t)col[k], 0u);
+            fr[k] = pack_row(rp[col[k]], rp[col[k] + 1] - rp[col[k]]);
         }
         RC(upload(c, c->radj, ra));
         RC(upload(c, c->fadj, fa));
+        RC(upload(c, c->frow, fr));
     }
     RC(dalloc(c, c->cfin, c->M));
     RC(dalloc(c, c->tcost, c->M));
@@ -521,6 +525,7 @@ NetDev net_view(qdta_ctx* c, const qdta_opts* o = nullptr) {
     v.rlink = c->rlink.p;
     v.revpos = c->revpos.p;
     v.fadj = c->fadj.p;
+    v.frow = c->frow.p;
     v.inst = c->d_inst.p;
     const bool ct = c->c_built;
     v.crptr = ct ? c->crptr.p : nullptr;
@@ -1467,7 +1472,7 @@ int qdta_workspace_query(qdta_ctx* c, const qdta_opts* o, int64_t max_legs, int6
     // network and Frank-Wolfe state
     add(N + 1, 4); add(M, 4); add(M, 4); add(M, 4); add(N + 1, 4); add(M, 4); add(M, 4); add(M, 4);
     add(nblk, 4); add(nblk, 4); add(ni, sizeof(InstDev));
-    add(M, 8); add(M, 8); add(M, 4); add(M, 8); add(M, 8); add(M, 4); add(M, 4);
+    add(M, 8); add(M, 8); add(M, 4); add(M, 8); add(M, 8); add(M, 4); add(M, 4); add(M, 4);
     add(ni, sizeof(InstState)); add((size_t)ni * 6, 8); add((size_t)ni * kMaxK * 6, 8); add((size_t)ni * kMaxK, 8);
     add(ni, 8); add(4, 4); add(ni, 8);
     // demand tables and shortest-path labels
